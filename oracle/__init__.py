@@ -1,0 +1,185 @@
+"""CPU oracle for the residual sums (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never imports it and shares no code with it.
+
+The arithmetic lives in ``dmk_oracle.c`` (long-double brute force, one
+OpenMP thread per target batch); this module only marshals numpy arrays.
+
+Functions follow the paper's notation:
+
+* :func:`residual` -- mode R, eq. (u_local) of Sec. 2.3 over the image set of
+  eq. (periodic-images), Sec. 1, with the residual kernels of eq.
+  (Hhatsplit_wfunc) and App. B (eqs. (res_stokeslet), (res_stresslet),
+  (res_rotlet)) for the Gaussian window.
+* :func:`residual_vjp` -- its exact vector-Jacobian product.
+* :func:`direct_free` -- D = 0 direct sum of the original kernels (App. B).
+* :func:`full_split_3p` -- mode F for D = 3 (eq. (ewald_far_3P) plus the
+  self-interaction correction of Sec. 2.4).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dmk_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+KERNELS = {"laplace": 0, "stokeslet": 1, "stresslet": 2, "rotlet": 3}
+M_IN = {0: 1, 1: 3, 2: 9, 3: 3}
+M_OUT = {0: 1, 1: 3, 2: 3, 3: 3}
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        D = ctypes.c_double
+        C = ctypes.c_int
+        lib.oracle_residual.argtypes = [C, C, P, D, D, I64, P, P, I64, P, P]
+        lib.oracle_residual_vjp.argtypes = [C, C, P, D, D, I64, P, P, P, I64, P, P, P]
+        lib.oracle_direct_free.argtypes = [C, I64, P, P, D, I64, P, P]
+        lib.oracle_full_split_3p.argtypes = [C, P, D, I64, P, P, D, D, I64, P, P]
+        lib.oracle_kernel_tensor.argtypes = [C, P, D, P, P]
+        lib.oracle_kernel_free_tensor.argtypes = [C, P, P]
+        for f in (lib.oracle_residual, lib.oracle_residual_vjp, lib.oracle_direct_free,
+                  lib.oracle_full_split_3p, lib.oracle_kernel_tensor, lib.oracle_kernel_free_tensor):
+            f.restype = C
+        _lib = lib
+    return _lib
+
+
+def _kid(kernel) -> int:
+    return KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _targets(targets, n):
+    if targets is None:
+        return None, n
+    t = np.ascontiguousarray(np.asarray(targets, dtype=np.int64).ravel())
+    if t.size and (t.min() < 0 or t.max() >= n):
+        raise IndexError("target index out of range")
+    return t, t.size
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def residual(kernel, D, L, sigma, rc, x, rho, targets=None):
+    """Mode R residual sum; returns u[ntgt, m_out] (float64)."""
+    k = _kid(kernel)
+    x = _f64(x, (-1, 3))
+    n = x.shape[0]
+    rho = _f64(rho, (n, M_IN[k]))
+    Lv = _f64(L, (3,))
+    t, nt = _targets(targets, n)
+    u = np.zeros((nt, M_OUT[k]), dtype=np.float64)
+    rc_ = _load().oracle_residual(k, int(D), _ptr(Lv), float(sigma), float(rc), n, _ptr(x), _ptr(rho),
+                                  nt, _ptr(t), _ptr(u))
+    if rc_ != 0:
+        raise ValueError("oracle_residual: bad arguments")
+    return u
+
+
+def residual_vjp(kernel, D, L, sigma, rc, x, rho, G, targets=None):
+    """Gradients of F = sum_b G_b . u_b; returns (grad_rho[ntgt, m_in], grad_x[ntgt, 3])."""
+    k = _kid(kernel)
+    x = _f64(x, (-1, 3))
+    n = x.shape[0]
+    rho = _f64(rho, (n, M_IN[k]))
+    G = _f64(G, (n, M_OUT[k]))
+    Lv = _f64(L, (3,))
+    t, nt = _targets(targets, n)
+    gr = np.zeros((nt, M_IN[k]), dtype=np.float64)
+    gx = np.zeros((nt, 3), dtype=np.float64)
+    rc_ = _load().oracle_residual_vjp(k, int(D), _ptr(Lv), float(sigma), float(rc), n, _ptr(x), _ptr(rho),
+                                      _ptr(G), nt, _ptr(t), _ptr(gr), _ptr(gx))
+    if rc_ != 0:
+        raise ValueError("oracle_residual_vjp: bad arguments")
+    return gr, gx
+
+
+def direct_free(kernel, x, rho, rc=np.inf, targets=None):
+    """D = 0 direct sum of the original kernels over pairs with 0 < r < rc."""
+    k = _kid(kernel)
+    x = _f64(x, (-1, 3))
+    n = x.shape[0]
+    rho = _f64(rho, (n, M_IN[k]))
+    t, nt = _targets(targets, n)
+    u = np.zeros((nt, M_OUT[k]), dtype=np.float64)
+    rc_ = _load().oracle_direct_free(k, n, _ptr(x), _ptr(rho), float(rc), nt, _ptr(t), _ptr(u))
+    if rc_ != 0:
+        raise ValueError("oracle_direct_free: bad arguments")
+    return u
+
+
+def full_split_3p(kernel, L, sigma, x, rho, rcut_real=None, kmax=None, targets=None):
+    """Mode F (D = 3): residual over all images + Fourier part (k != 0) + self term.
+
+    Defaults: real-space cutoff 7 sigma and |k| sigma <= 14, so both neglected
+    tails are below 1e-17 relative to the leading terms for the Gaussian window.
+    """
+    k = _kid(kernel)
+    x = _f64(x, (-1, 3))
+    n = x.shape[0]
+    rho = _f64(rho, (n, M_IN[k]))
+    Lv = _f64(L, (3,))
+    if rcut_real is None:
+        rcut_real = 7.0 * sigma
+    if kmax is None:
+        kmax = 14.0 / sigma
+    t, nt = _targets(targets, n)
+    u = np.zeros((nt, M_OUT[k]), dtype=np.float64)
+    rc_ = _load().oracle_full_split_3p(k, _ptr(Lv), float(sigma), n, _ptr(x), _ptr(rho), float(rcut_real),
+                                       float(kmax), nt, _ptr(t), _ptr(u))
+    if rc_ != 0:
+        raise ValueError("oracle_full_split_3p: bad arguments")
+    return u
+
+
+def kernel_tensor(kernel, d, sigma):
+    """Residual kernel K[j, L] and derivative dK[k, j, L] at one displacement."""
+    k = _kid(kernel)
+    d = _f64(d, (3,))
+    K = np.zeros((3, 9))
+    dK = np.zeros((3, 3, 9))
+    _load().oracle_kernel_tensor(k, _ptr(d), float(sigma), _ptr(K), _ptr(dK))
+    return K[:M_OUT[k], :M_IN[k]], dK[:, :M_OUT[k], :M_IN[k]]
+
+
+def kernel_free_tensor(kernel, d):
+    """Original (unsplit) kernel K[j, L] at one displacement."""
+    k = _kid(kernel)
+    d = _f64(d, (3,))
+    K = np.zeros((3, 9))
+    _load().oracle_kernel_free_tensor(k, _ptr(d), _ptr(K))
+    return K[:M_OUT[k], :M_IN[k]]
