@@ -1,0 +1,165 @@
+/*
+ * dmk.h -- C ABI of libdmkloc: the leaf-level residual (short-range) kernel
+ * interaction of the periodized DMK method on one AMD MI355X (gfx950).
+ *
+ * Operation (Sec. 2.3, eq. (u_local); image set P_D of eq. (periodic-images),
+ * Sec. 1): for every point x_b of the cell [0,L1)x[0,L2)x[0,L3), whose first
+ * D axes are periodic,
+ *
+ *     u_b = sum_a sum_{p in P_D} [0 < |d| < rc] K_R(d; sigma) rho_a,
+ *     d   = x_b - x_a + p,
+ *
+ * where sources and targets are the same N points.  The term |d| = 0 is the
+ * excluded self/coincident term of eq. (periodic_sum).  K_R is the residual
+ * kernel of the Gaussian split (window phi(t) = exp(-t^2)/sqrt(pi),
+ * Phi = erfc, functions evaluated at t = r/sigma):
+ *
+ *     DMK_LAPLACE    erfc(t)/(4 pi r) q                     eq. (Hhatsplit_wfunc)
+ *     DMK_STOKESLET  residual Stokeslet S_R f               App. B eq. (res_stokeslet)
+ *     DMK_STRESSLET  residual stresslet T_R : rho (rho 3x3) App. B eq. (res_stresslet)
+ *     DMK_ROTLET     residual rotlet Omega_R rho            App. B eq. (res_rotlet)
+ *
+ * The cell is tiled by n1 x n2 x n3 leaf boxes of side h_i = L_i/n_i (the
+ * exact cube tiling of Sec. 4.1.1 at the leaf level).  With rc <= min_i h_i
+ * every interaction of a target lies in its own leaf box and its 26
+ * neighbours (colleagues, Sec. 3.1.1 and 3.1.5); neighbours across a
+ * periodic face are the image-shifted boxes (Sec. 4.1.2-4.1.3).
+ *
+ * Conventions
+ *  - All pointers named "dev" are device pointers on the current HIP device.
+ *    The caller owns every byte: the library allocates nothing and keeps no
+ *    global state, so calls on different streams with different arenas are
+ *    independent.
+ *  - User-facing arrays are row-major in the ORIGINAL point order and FP64:
+ *      x[N][3], rho[N][m_in], u[N][m_out], grad_rho[N][m_in], grad_x[N][3]
+ *    with (m_in, m_out) = (1,1) Laplace, (3,3) Stokeslet, (9,3) stresslet
+ *    (rho_lm row-major, u_j = T_jlm rho_lm), (3,3) rotlet.
+ *  - prec selects only the internal pair arithmetic: DMK_FP64, or DMK_FP32C
+ *    (FP32 pair arithmetic on hi/lo FP32 coordinates formed in FP64, Kahan
+ *    compensated FP32 accumulation, FP64 final combine).
+ *  - Return value: a dmk_status.  Argument errors are detected on the host
+ *    before any launch.  dmk_residual_eval / _backward return right after
+ *    their launches (asynchronous on `stream`).  dmk_tree_bin synchronises
+ *    `stream` once to read back its data checks.
+ */
+#ifndef DMK_H
+#define DMK_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DMK_OK = 0,
+    DMK_EINVAL = 1,       /* bad argument (null pointer, size, enum)                 */
+    DMK_EDOMAIN = 2,      /* non-finite coordinate, or free-axis coordinate outside [0,L) */
+    DMK_ECUTOFF = 3,      /* rc not in (0, min h_i], or sigma <= 0                   */
+    DMK_EUNSUPPORTED = 4, /* combination not provided by this build                 */
+    DMK_EHIP = 5,         /* a HIP runtime call failed                               */
+    DMK_ESIZE = 6         /* arena / workspace too small, or N / box count too large */
+} dmk_status;
+
+typedef enum { DMK_LAPLACE = 0, DMK_STOKESLET = 1, DMK_STRESSLET = 2, DMK_ROTLET = 3 } dmk_kernel;
+typedef enum { DMK_FP64 = 0, DMK_FP32C = 1 } dmk_prec;
+
+/* Cell and leaf tiling: cell [0,L[0])x[0,L[1])x[0,L[2]); axes 0..D-1 are
+ * periodic (eq. (periodic-images)), the others free; n[i] >= 1 leaf boxes
+ * along axis i. */
+typedef struct {
+    double L[3];
+    int32_t D;
+    int32_t n[3];
+} dmk_grid;
+
+/*
+ * Binned point set.  All pointers are device pointers carved by
+ * dmk_bins_carve from ONE caller-owned device arena; the scalar fields are
+ * host values.  Box id of leaf (b0,b1,b2) is (b0*n1 + b1)*n2 + b2.
+ * "Sorted order" is the stable counting-sort order by box id (points of a box
+ * keep their original relative order).
+ */
+typedef struct {
+    int64_t N;           /* number of points                                   */
+    int64_t nbox;        /* n0*n1*n2                                           */
+    int64_t ntiles;      /* target tiles built by dmk_tree_bin (host value)    */
+    int64_t max_tiles;   /* capacity of `tiles`                                */
+    int32_t *key;        /* [N]      box id of each point, original order       */
+    int32_t *perm;       /* [N]      sorted position -> original index          */
+    int32_t *skey;       /* [N]      box id in sorted order                     */
+    int32_t *box_start;  /* [nbox+1] first sorted position of each box          */
+    double *ys;          /* [3][N]   wrapped coordinates, sorted order (SoA)    */
+    int32_t *axis_nbr;   /* [n0+n1+n2][3] neighbour box index along each axis    */
+                         /*          for offsets -1,0,+1, or -1 if none (free)  */
+    int8_t *axis_img;    /* [n0+n1+n2][3] image index s in {-1,0,1}: the        */
+                         /*          neighbour's points sit at x + s*L_i         */
+    int32_t *tiles;      /* [max_tiles][4] target tiles (see DESIGN notes)      */
+    int32_t *status;     /* [4] device error word, tile count                   */
+    int32_t *tmp;        /* sort / tile scratch                                  */
+    int64_t tmp_ints;    /* size of tmp in int32                                 */
+} dmk_bins;
+
+/* Bytes of device arena dmk_bins_carve needs for N points on `grid`
+ * (0 on invalid arguments). */
+size_t dmk_bins_bytes(const dmk_grid *grid, int64_t N);
+
+/* Carve the arena (device pointer, >= dmk_bins_bytes bytes, 256-byte
+ * aligned) into `bins`.  No device work.  DMK_EINVAL / DMK_ESIZE on bad
+ * input. */
+int dmk_bins_carve(const dmk_grid *grid, int64_t N, void *dev_arena, size_t arena_bytes, dmk_bins *bins);
+
+/*
+ * Bin the points x[N][3] (dev, FP64, original order) into the leaf tiling:
+ *  - periodic axis: y = x - L floor(x/L); free axis: 0 <= x < L required;
+ *  - box index b_i = min(n_i - 1, floor(y_i * (n_i / L_i))), IEEE FP64 ops
+ *    without contraction, so the result is bit-exact;
+ *  - stable counting sort by box id (perm, skey, box_start), the sorted
+ *    wrapped coordinates ys, the per-axis neighbour/image tables and the
+ *    target tiles used by the residual kernels.
+ * Runs on `stream`, then synchronises it once to read the error word:
+ * DMK_EDOMAIN if any coordinate is non-finite or a free-axis coordinate is
+ * outside [0, L).  Sets bins->ntiles.
+ */
+int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bins, hipStream_t stream);
+
+/* Workspace bytes for dmk_residual_eval (backward = 0) or
+ * dmk_residual_backward (backward = 1). */
+size_t dmk_residual_ws_bytes(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, int backward);
+
+/*
+ * u[N][m_out] (dev, FP64, original order) = residual sum above with strengths
+ * rho[N][m_in] (dev, FP64, original order).  Requires 0 < sigma and
+ * 0 < rc <= min_i h_i (DMK_ECUTOFF otherwise).  `ws` is a device workspace of
+ * >= dmk_residual_ws_bytes(.., 0) bytes.  Asynchronous on `stream`; u is
+ * fully overwritten.  Summation order is fixed, so results are bit-identical
+ * between runs.
+ */
+int dmk_residual_eval(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma, double rc,
+                      const double *rho, double *u, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Vector-Jacobian product of dmk_residual_eval: with cotangent
+ * gu[N][m_out] (dev) and F = sum_b gu_b . u_b,
+ *     grad_rho[N][m_in] = dF/drho,   grad_x[N][3] = dF/dx
+ * (both dev, FP64, original order, fully overwritten).  The cutoff mask is
+ * treated as locally constant.  Same argument rules as dmk_residual_eval;
+ * workspace of >= dmk_residual_ws_bytes(.., 1) bytes.  Asynchronous.
+ */
+int dmk_residual_backward(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma,
+                          double rc, const double *rho, const double *gu, double *grad_rho, double *grad_x,
+                          void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Static description of a status code. */
+const char *dmk_strerror(int status);
+
+/* Library version string. */
+const char *dmk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMK_H */

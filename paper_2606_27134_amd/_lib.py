@@ -1,0 +1,134 @@
+"""ctypes binding of libdmkloc (include/dmk.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  PyTorch supplies device memory (tensors) and the
+current HIP stream.  There is no fallback: if the library cannot be loaded
+the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmkloc.so")
+
+DMK_OK, DMK_EINVAL, DMK_EDOMAIN, DMK_ECUTOFF, DMK_EUNSUPPORTED, DMK_EHIP, DMK_ESIZE = range(7)
+KERNELS = {"laplace": 0, "stokeslet": 1, "stresslet": 2, "rotlet": 3}
+PRECS = {"fp64": 0, "fp32c": 1}
+M_IN = {0: 1, 1: 3, 2: 9, 3: 3}
+M_OUT = {0: 1, 1: 3, 2: 3, 3: 3}
+
+
+class dmk_grid(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double * 3), ("D", ctypes.c_int32), ("n", ctypes.c_int32 * 3)]
+
+
+class dmk_bins(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("nbox", ctypes.c_int64), ("ntiles", ctypes.c_int64), ("max_tiles", ctypes.c_int64),
+        ("key", ctypes.c_void_p), ("perm", ctypes.c_void_p), ("skey", ctypes.c_void_p),
+        ("box_start", ctypes.c_void_p), ("ys", ctypes.c_void_p), ("axis_nbr", ctypes.c_void_p),
+        ("axis_img", ctypes.c_void_p), ("tiles", ctypes.c_void_p), ("status", ctypes.c_void_p),
+        ("tmp", ctypes.c_void_p), ("tmp_ints", ctypes.c_int64),
+    ]
+
+
+class DmkError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__("%s failed: %s (status %d)" % (where, strerror(code), code))
+
+
+_lib = None
+
+
+def load():
+    """Load libdmkloc.so; build it first only when no built library exists."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build as _build
+        _build.build()
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    G = ctypes.POINTER(dmk_grid)
+    B = ctypes.POINTER(dmk_bins)
+    lib.dmk_bins_bytes.argtypes = [G, ctypes.c_int64]
+    lib.dmk_bins_bytes.restype = ctypes.c_size_t
+    lib.dmk_bins_carve.argtypes = [G, ctypes.c_int64, P, ctypes.c_size_t, B]
+    lib.dmk_bins_carve.restype = ctypes.c_int
+    lib.dmk_tree_bin.argtypes = [G, P, B, P]
+    lib.dmk_tree_bin.restype = ctypes.c_int
+    lib.dmk_residual_ws_bytes.argtypes = [G, B, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.dmk_residual_ws_bytes.restype = ctypes.c_size_t
+    lib.dmk_residual_eval.argtypes = [G, B, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, P, P,
+                                      ctypes.c_size_t, P]
+    lib.dmk_residual_eval.restype = ctypes.c_int
+    lib.dmk_residual_backward.argtypes = [G, B, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, P,
+                                          P, P, P, ctypes.c_size_t, P]
+    lib.dmk_residual_backward.restype = ctypes.c_int
+    lib.dmk_strerror.argtypes = [ctypes.c_int]
+    lib.dmk_strerror.restype = ctypes.c_char_p
+    lib.dmk_version.argtypes = []
+    lib.dmk_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().dmk_strerror(int(code)).decode()
+
+
+def make_grid(L, D, n) -> dmk_grid:
+    g = dmk_grid()
+    for i in range(3):
+        g.L[i] = float(L[i])
+        g.n[i] = int(n[i])
+    g.D = int(D)
+    return g
+
+
+def _check(code, where):
+    if code != DMK_OK:
+        raise DmkError(code, where)
+
+
+# ---- thin wrappers with the C names -------------------------------------
+def dmk_bins_bytes(grid: dmk_grid, N: int) -> int:
+    return int(load().dmk_bins_bytes(ctypes.byref(grid), int(N)))
+
+
+def dmk_bins_carve(grid: dmk_grid, N: int, arena_ptr: int, nbytes: int, bins: dmk_bins) -> int:
+    return int(load().dmk_bins_carve(ctypes.byref(grid), int(N), ctypes.c_void_p(arena_ptr), int(nbytes),
+                                     ctypes.byref(bins)))
+
+
+def dmk_tree_bin(grid: dmk_grid, x_ptr: int, bins: dmk_bins, stream: int) -> int:
+    return int(load().dmk_tree_bin(ctypes.byref(grid), ctypes.c_void_p(x_ptr), ctypes.byref(bins),
+                                   ctypes.c_void_p(stream)))
+
+
+def dmk_residual_ws_bytes(grid: dmk_grid, bins: dmk_bins, kernel: int, prec: int, backward: int) -> int:
+    return int(load().dmk_residual_ws_bytes(ctypes.byref(grid), ctypes.byref(bins), int(kernel), int(prec),
+                                            int(backward)))
+
+
+def dmk_residual_eval(grid, bins, kernel, prec, sigma, rc, rho_ptr, u_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return int(load().dmk_residual_eval(ctypes.byref(grid), ctypes.byref(bins), int(kernel), int(prec),
+                                        float(sigma), float(rc), ctypes.c_void_p(rho_ptr), ctypes.c_void_p(u_ptr),
+                                        ctypes.c_void_p(ws_ptr), int(ws_bytes), ctypes.c_void_p(stream)))
+
+
+def dmk_residual_backward(grid, bins, kernel, prec, sigma, rc, rho_ptr, gu_ptr, grho_ptr, gx_ptr, ws_ptr, ws_bytes,
+                          stream) -> int:
+    return int(load().dmk_residual_backward(ctypes.byref(grid), ctypes.byref(bins), int(kernel), int(prec),
+                                            float(sigma), float(rc), ctypes.c_void_p(rho_ptr),
+                                            ctypes.c_void_p(gu_ptr), ctypes.c_void_p(grho_ptr),
+                                            ctypes.c_void_p(gx_ptr), ctypes.c_void_p(ws_ptr), int(ws_bytes),
+                                            ctypes.c_void_p(stream)))
+
+
+def dmk_version() -> str:
+    return load().dmk_version().decode()

@@ -1,0 +1,522 @@
+// dmk_bin.hip -- leaf binning for libdmkloc on gfx950.
+//
+// The leaf level of the method is an exact tiling of the cell by n0 x n1 x n2
+// boxes (Sec. 4.1.1 at the leaf level); the residual interaction of a target
+// involves its own box and the 26 colleagues (Sec. 3.1.1, 3.1.5), with
+// periodic neighbours across the faces of the first D axes (Sec. 4.1.2,
+// 4.1.3).  This file builds, all with integer or contraction-free IEEE FP64
+// arithmetic so that the output is bit-exact:
+//   1. the wrapped coordinate y and the box id of every point;
+//   2. a stable LSD radix sort (8-bit digits) of the box ids -> perm, skey;
+//   3. box_start by binary search in the sorted ids;
+//   4. the sorted wrapped coordinates ys (SoA);
+//   5. the per-axis neighbour / image tables;
+//   6. the target tiles walked by the residual kernels.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include "dmk_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace dmk {
+
+struct BinGeom {
+    double L[3];
+    double inv[3];  // n_i / L_i, formed on the host
+    int n[3];
+    int D;
+};
+
+// ---------------------------------------------------------------------------
+// 1. wrap + box id
+__device__ inline bool wrap_coord(double xc, int ax, const BinGeom &g, double &y)
+{
+    if (!isfinite(xc)) return false;
+    if (ax < g.D) {
+        y = xc - g.L[ax] * floor(xc / g.L[ax]);
+        return true;
+    }
+    if (!(xc >= 0.0 && xc < g.L[ax])) return false;
+    y = xc;
+    return true;
+}
+
+__device__ inline int box_coord(double y, int ax, const BinGeom &g)
+{
+    double f = floor(y * g.inv[ax]);
+    int b = (f < 0.0) ? 0 : (f >= (double)g.n[ax] ? g.n[ax] - 1 : (int)f);
+    return b;
+}
+
+__global__ void k_bin_keys(const double *__restrict__ x, int64_t N, BinGeom g, int32_t *__restrict__ key,
+                           int32_t *__restrict__ err)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int b[3];
+    bool ok = true;
+    for (int ax = 0; ax < 3; ++ax) {
+        double y = 0.0;
+        ok = wrap_coord(x[3 * i + ax], ax, g, y) && ok;
+        b[ax] = ok ? box_coord(y, ax, g) : 0;
+    }
+    if (!ok) atomicOr(err, 1);
+    key[i] = ok ? (b[0] * g.n[1] + b[1]) * g.n[2] + b[2] : 0;
+}
+
+// ---------------------------------------------------------------------------
+// 2. stable LSD radix sort of (key, original index), 8-bit digits.
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 8;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const int32_t *__restrict__ keys, int64_t N, int shift,
+                                                        int32_t *__restrict__ hist, int nblk)
+{
+    __shared__ int h[256];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        int64_t i = base + r * RS_THREADS + tid;
+        if (i < N) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)tid * nblk + blockIdx.x] = h[tid];
+}
+
+// exclusive scan of a[0..n) in place, one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void k_scan_excl(int32_t *__restrict__ a, int64_t n)
+{
+    __shared__ int s[1024];
+    __shared__ int carry_s;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry_s = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < n; base += 1024) {
+        int v = (base + tid < n) ? a[base + tid] : 0;
+        s[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            int w = (tid >= off) ? s[tid - off] : 0;
+            __syncthreads();
+            s[tid] += w;
+            __syncthreads();
+        }
+        int incl = s[tid];
+        int carry = carry_s;
+        if (base + tid < n) a[base + tid] = carry + incl - v;
+        __syncthreads();
+        if (tid == 1023) carry_s = carry + incl;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__restrict__ kin,
+                                                           const int32_t *__restrict__ vin, int64_t N, int shift,
+                                                           const int32_t *__restrict__ hist, int nblk,
+                                                           int32_t *__restrict__ kout, int32_t *__restrict__ vout)
+{
+    __shared__ int base[256];
+    __shared__ int run[256];
+    __shared__ int wcnt[RS_THREADS / WAVE][256];
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int w = tid / WAVE;
+    base[tid] = hist[(int64_t)tid * nblk + blockIdx.x];
+    run[tid] = 0;
+    const int64_t b0 = (int64_t)blockIdx.x * RS_TILE;
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        for (int q = 0; q < RS_THREADS / WAVE; ++q) wcnt[q][tid] = 0;
+        __syncthreads();
+        const int64_t i = b0 + r * RS_THREADS + tid;
+        const bool valid = i < N;
+        const int k = valid ? kin[i] : 0;
+        const int v = valid ? (vin ? vin[i] : (int)i) : 0;
+        const int d = (k >> shift) & 255;
+        uint64_t m = __ballot(valid);
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (d >> bit) & 1;
+            const uint64_t bb = __ballot(valid && on);
+            m &= on ? bb : ~bb;
+        }
+        if (!valid) m = 0;
+        const int rank = __popcll(m & below);
+        const bool last = valid && ((m >> lane) == 1ull);
+        if (last) wcnt[w][d] = __popcll(m);
+        __syncthreads();
+        if (valid) {
+            int off = base[d] + run[d];
+            for (int q = 0; q < w; ++q) off += wcnt[q][d];
+            kout[off + rank] = k;
+            vout[off + rank] = v;
+        }
+        __syncthreads();
+        int add = 0;
+        for (int q = 0; q < RS_THREADS / WAVE; ++q) add += wcnt[q][tid];
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3.-5. box_start, sorted coordinates, axis tables
+__global__ void k_box_start(const int32_t *__restrict__ skey, int64_t N, int64_t nbox, int32_t *__restrict__ bs)
+{
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nbox) return;
+    // first sorted position with skey >= b
+    int64_t lo = 0, hi = N;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (skey[mid] < b)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    bs[b] = (int32_t)lo;
+}
+
+__global__ void k_gather_ys(const double *__restrict__ x, const int32_t *__restrict__ perm, int64_t N, BinGeom g,
+                            double *__restrict__ ys)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const int64_t i = perm[j];
+    for (int ax = 0; ax < 3; ++ax) {
+        double y = 0.0;
+        wrap_coord(x[3 * i + ax], ax, g, y);
+        ys[(int64_t)ax * N + j] = y;
+    }
+}
+
+// row r of the table (axes stacked: rows [0,n0) axis 0, [n0,n0+n1) axis 1, rest axis 2),
+// column c = offset + 1 for offsets -1, 0, +1.
+__global__ void k_axis_tables(BinGeom g, int32_t *__restrict__ nbr, int8_t *__restrict__ img)
+{
+    const int total = g.n[0] + g.n[1] + g.n[2];
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 3 * total) return;
+    const int row = e / 3, c = e % 3;
+    int ax = 0, b = row;
+    if (b >= g.n[0]) {
+        b -= g.n[0];
+        ax = 1;
+        if (b >= g.n[1]) {
+            b -= g.n[1];
+            ax = 2;
+        }
+    }
+    const int n = g.n[ax];
+    int nb = b + (c - 1);
+    int s = 0;
+    if (ax < g.D) {
+        if (nb < 0) {
+            nb += n;
+            s = -1;
+        } else if (nb >= n) {
+            nb -= n;
+            s = 1;
+        }
+    } else if (nb < 0 || nb >= n) {
+        nb = -1;
+    }
+    nbr[e] = nb;
+    img[e] = (int8_t)s;
+}
+
+// ---------------------------------------------------------------------------
+// 6. target tiles.  One thread walks one leaf column (b0, b1) in z.
+struct TileGeom {
+    int n[3];
+    const int32_t *bs;
+    const int32_t *nbr;
+};
+
+__device__ inline int box_count(const TileGeom &g, int col, int zp)
+{
+    if (col < 0 || zp < 0) return 0;
+    const int64_t b = (int64_t)col * g.n[2] + zp;
+    return g.bs[b + 1] - g.bs[b];
+}
+
+// physical z of virtual z in [-1, n2], or -1 if it does not exist (free axis)
+__device__ inline int phys_z(const TileGeom &g, int zv)
+{
+    if (zv >= 0 && zv < g.n[2]) return zv;
+    const int r0 = g.n[0] + g.n[1];
+    if (zv == -1) return g.nbr[3 * r0 + 0];
+    return g.nbr[3 * (r0 + g.n[2] - 1) + 2];
+}
+
+__device__ inline int slab_count(const TileGeom &g, const int ccol[9], int zv)
+{
+    const int zp = phys_z(g, zv);
+    if (zp < 0) return 0;
+    int s = 0;
+    for (int k = 0; k < 9; ++k) s += box_count(g, ccol[k], zp);
+    return s;
+}
+
+template <bool WRITE>
+__global__ void k_tiles(TileGeom g, int32_t *__restrict__ counts, int4 *__restrict__ tiles)
+{
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= g.n[0] * g.n[1]) return;
+    const int b0 = col / g.n[1], b1 = col % g.n[1];
+    int ccol[9];
+    for (int k = 0; k < 9; ++k) {
+        const int nb0 = g.nbr[3 * b0 + (k / 3)];
+        const int nb1 = g.nbr[3 * (g.n[0] + b1) + (k % 3)];
+        ccol[k] = (nb0 < 0 || nb1 < 0) ? -1 : nb0 * g.n[1] + nb1;
+    }
+    const int n2 = g.n[2];
+    int cnt = 0;
+    int out = WRITE ? counts[col] : 0;
+    int z = 0;
+    while (z < n2) {
+        const int nt = box_count(g, col, z);
+        if (nt == 0) {
+            ++z;
+            continue;
+        }
+        const int q1 = slab_count(g, ccol, z - 1) + slab_count(g, ccol, z) + slab_count(g, ccol, z + 1);
+        const int first = g.bs[(int64_t)col * n2 + z];
+        if (nt > TILE_T || q1 > TILE_CAP) {
+            for (int c = 0; c < nt; c += TILE_T) {
+                if (WRITE) tiles[out + cnt] = make_int4(col, z, -(z + 1), first + c);
+                ++cnt;
+            }
+            ++z;
+            continue;
+        }
+        int z1 = z, tacc = nt, q = q1;
+        while (z1 + 1 < n2 && (z1 + 1 - z + 1) <= TILE_ZMAX) {
+            const int nn = box_count(g, col, z1 + 1);
+            const int qn = q + slab_count(g, ccol, z1 + 2);
+            if (tacc + nn > TILE_T || qn > TILE_CAP) break;
+            ++z1;
+            tacc += nn;
+            q = qn;
+        }
+        if (WRITE) tiles[out + cnt] = make_int4(col, z, z1, first);
+        ++cnt;
+        z = z1 + 1;
+    }
+    if (!WRITE) counts[col] = cnt;
+}
+
+__global__ void k_tile_total(const int32_t *__restrict__ counts, int ncol, const int32_t *__restrict__ last_raw,
+                             int32_t *__restrict__ status)
+{
+    // counts holds the exclusive scan; last_raw the raw count of the last column
+    status[1] = (ncol > 0) ? counts[ncol - 1] + *last_raw : 0;
+}
+
+}  // namespace dmk
+
+using namespace dmk;
+
+// ---------------------------------------------------------------------------
+// host side
+namespace {
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int check_grid(const dmk_grid *g)
+{
+    if (!g) return DMK_EINVAL;
+    if (g->D < 0 || g->D > 3) return DMK_EINVAL;
+    for (int i = 0; i < 3; ++i) {
+        if (g->n[i] < 1) return DMK_EINVAL;
+        if (!(g->L[i] > 0.0) || !isfinite(g->L[i])) return DMK_EINVAL;
+    }
+    const int64_t nbox = (int64_t)g->n[0] * g->n[1] * g->n[2];
+    if (nbox > (int64_t)0x3fffffff) return DMK_ESIZE;
+    return DMK_OK;
+}
+
+struct Layout {
+    size_t key, perm, skey, bs, ys, nbr, img, tiles, status, tmp, total;
+    int64_t max_tiles, tmp_ints;
+};
+
+Layout layout_for(const dmk_grid *g, int64_t N)
+{
+    Layout l{};
+    const int64_t nbox = (int64_t)g->n[0] * g->n[1] * g->n[2];
+    const int64_t rows = (int64_t)g->n[0] + g->n[1] + g->n[2];
+    const int64_t ncol = (int64_t)g->n[0] * g->n[1];
+    const int64_t nblk = (N + RS_TILE - 1) / RS_TILE;
+    l.max_tiles = max_tiles_for(N, nbox);
+    l.tmp_ints = 2 * N + 256 * (nblk > 0 ? nblk : 1) + ncol + 64;
+    size_t off = 0;
+    l.key = off;
+    off = align256(off + sizeof(int32_t) * N);
+    l.perm = off;
+    off = align256(off + sizeof(int32_t) * N);
+    l.skey = off;
+    off = align256(off + sizeof(int32_t) * N);
+    l.bs = off;
+    off = align256(off + sizeof(int32_t) * (nbox + 1));
+    l.ys = off;
+    off = align256(off + sizeof(double) * 3 * N);
+    l.nbr = off;
+    off = align256(off + sizeof(int32_t) * 3 * rows);
+    l.img = off;
+    off = align256(off + sizeof(int8_t) * 3 * rows);
+    l.tiles = off;
+    off = align256(off + sizeof(int32_t) * 4 * l.max_tiles);
+    l.status = off;
+    off = align256(off + sizeof(int32_t) * 64);
+    l.tmp = off;
+    off = align256(off + sizeof(int32_t) * l.tmp_ints);
+    l.total = off;
+    return l;
+}
+
+BinGeom make_geom(const dmk_grid *g)
+{
+    BinGeom b{};
+    for (int i = 0; i < 3; ++i) {
+        b.L[i] = g->L[i];
+        b.inv[i] = (double)g->n[i] / g->L[i];
+        b.n[i] = g->n[i];
+    }
+    b.D = g->D;
+    return b;
+}
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+extern "C" size_t dmk_bins_bytes(const dmk_grid *grid, int64_t N)
+{
+    if (check_grid(grid) != DMK_OK || N < 0 || N > (int64_t)0x3fffffff) return 0;
+    return layout_for(grid, N).total;
+}
+
+extern "C" int dmk_bins_carve(const dmk_grid *grid, int64_t N, void *arena, size_t bytes, dmk_bins *bins)
+{
+    int rc = check_grid(grid);
+    if (rc != DMK_OK) return rc;
+    if (!bins || N < 0) return DMK_EINVAL;
+    if (N > (int64_t)0x3fffffff) return DMK_ESIZE;
+    if (!arena || ((uintptr_t)arena & 255)) return DMK_EINVAL;
+    Layout l = layout_for(grid, N);
+    if (bytes < l.total) return DMK_ESIZE;
+    char *a = (char *)arena;
+    memset(bins, 0, sizeof(*bins));
+    bins->N = N;
+    bins->nbox = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+    bins->ntiles = 0;
+    bins->max_tiles = l.max_tiles;
+    bins->key = (int32_t *)(a + l.key);
+    bins->perm = (int32_t *)(a + l.perm);
+    bins->skey = (int32_t *)(a + l.skey);
+    bins->box_start = (int32_t *)(a + l.bs);
+    bins->ys = (double *)(a + l.ys);
+    bins->axis_nbr = (int32_t *)(a + l.nbr);
+    bins->axis_img = (int8_t *)(a + l.img);
+    bins->tiles = (int32_t *)(a + l.tiles);
+    bins->status = (int32_t *)(a + l.status);
+    bins->tmp = (int32_t *)(a + l.tmp);
+    bins->tmp_ints = l.tmp_ints;
+    return DMK_OK;
+}
+
+extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bins, hipStream_t stream)
+{
+    int rc = check_grid(grid);
+    if (rc != DMK_OK) return rc;
+    if (!bins || !bins->key || !bins->status || !bins->tmp) return DMK_EINVAL;
+    const int64_t N = bins->N;
+    const int64_t nbox = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+    if (bins->nbox != nbox) return DMK_EINVAL;
+    if (N > 0 && !x) return DMK_EINVAL;
+    Layout l = layout_for(grid, N);
+    if (bins->tmp_ints < l.tmp_ints || bins->max_tiles < l.max_tiles) return DMK_ESIZE;
+
+    const BinGeom g = make_geom(grid);
+    const int64_t nblk = (N + RS_TILE - 1) / RS_TILE;
+    const int64_t ncol = (int64_t)grid->n[0] * grid->n[1];
+    int32_t *altk = bins->tmp;
+    int32_t *altv = bins->tmp + N;
+    int32_t *hist = bins->tmp + 2 * N;
+    int32_t *colcnt = hist + 256 * (nblk > 0 ? nblk : 1);
+
+    DMK_HIP_CHECK(hipMemsetAsync(bins->status, 0, sizeof(int32_t) * 4, stream));
+    if (N > 0) {
+        hipLaunchKernelGGL(k_bin_keys, dim3(nblocks(N, 256)), dim3(256), 0, stream, x, N, g, bins->key,
+                           bins->status);
+        // radix passes over ceil(log2(nbox)) bits
+        int bits = 0;
+        while (bits < 31 && ((int64_t)1 << bits) < nbox) ++bits;
+        int passes = (bits + 7) / 8;
+        if (passes < 1) passes = 1;
+        const int32_t *kin = bins->key;
+        const int32_t *vin = nullptr;
+        for (int p = 0; p < passes; ++p) {
+            const bool to_final = ((passes - 1 - p) % 2) == 0;
+            int32_t *kout = to_final ? bins->skey : altk;
+            int32_t *vout = to_final ? bins->perm : altv;
+            hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_THREADS), 0, stream, kin, N, 8 * p, hist,
+                               (int)nblk);
+            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, stream, hist, (int64_t)256 * nblk);
+            hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(RS_THREADS), 0, stream, kin, vin, N, 8 * p,
+                               hist, (int)nblk, kout, vout);
+            kin = kout;
+            vin = vout;
+        }
+        hipLaunchKernelGGL(k_gather_ys, dim3(nblocks(N, 256)), dim3(256), 0, stream, x, bins->perm, N, g,
+                           bins->ys);
+    }
+    hipLaunchKernelGGL(k_box_start, dim3(nblocks(nbox + 1, 256)), dim3(256), 0, stream, bins->skey, N, nbox,
+                       bins->box_start);
+    const int rows = grid->n[0] + grid->n[1] + grid->n[2];
+    hipLaunchKernelGGL(k_axis_tables, dim3(nblocks(3 * rows, 256)), dim3(256), 0, stream, g, bins->axis_nbr,
+                       bins->axis_img);
+    TileGeom tg{};
+    for (int i = 0; i < 3; ++i) tg.n[i] = grid->n[i];
+    tg.bs = bins->box_start;
+    tg.nbr = bins->axis_nbr;
+    hipLaunchKernelGGL(k_tiles<false>, dim3(nblocks(ncol, 64)), dim3(64), 0, stream, tg, colcnt,
+                       (int4 *)bins->tiles);
+    // keep the raw count of the last column, scan, then total
+    DMK_HIP_CHECK(hipMemcpyAsync(bins->status + 2, colcnt + ncol - 1, sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                 stream));
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, stream, colcnt, ncol);
+    hipLaunchKernelGGL(k_tiles<true>, dim3(nblocks(ncol, 64)), dim3(64), 0, stream, tg, colcnt,
+                       (int4 *)bins->tiles);
+    hipLaunchKernelGGL(k_tile_total, dim3(1), dim3(1), 0, stream, colcnt, (int)ncol, bins->status + 2,
+                       bins->status);
+    DMK_HIP_CHECK(hipGetLastError());
+    int32_t st[4] = {0, 0, 0, 0};
+    DMK_HIP_CHECK(hipMemcpyAsync(st, bins->status, sizeof(st), hipMemcpyDeviceToHost, stream));
+    DMK_HIP_CHECK(hipStreamSynchronize(stream));
+    if (st[0] != 0) return DMK_EDOMAIN;
+    if (st[1] < 0 || st[1] > bins->max_tiles) return DMK_ESIZE;
+    bins->ntiles = st[1];
+    return DMK_OK;
+}
+
+extern "C" const char *dmk_strerror(int s)
+{
+    switch (s) {
+    case DMK_OK: return "ok";
+    case DMK_EINVAL: return "invalid argument";
+    case DMK_EDOMAIN: return "coordinate not finite or outside [0,L) along a free axis";
+    case DMK_ECUTOFF: return "cutoff must satisfy 0 < rc <= min_i L_i/n_i and sigma > 0";
+    case DMK_EUNSUPPORTED: return "unsupported kernel / precision combination";
+    case DMK_EHIP: return "HIP runtime error";
+    case DMK_ESIZE: return "arena or workspace too small, or size limit exceeded";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *dmk_version(void) { return "libdmkloc 0.1 (gfx950)"; }

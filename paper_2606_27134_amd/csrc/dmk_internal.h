@@ -1,0 +1,41 @@
+// dmk_internal.h -- constants and helpers shared by the binning and residual
+// translation units of libdmkloc (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dmk.h"
+
+namespace dmk {
+
+// A target tile is worked on by one wavefront (64 lanes): at most TILE_T
+// targets, all in one leaf column (b0, b1) and in consecutive z-boxes
+// [z0, z1].  A multi-box tile stages at most TILE_CAP neighbour sources in
+// LDS at once; a box whose targets or neighbourhood exceed that becomes
+// "dense" tiles of up to TILE_T targets that stream their neighbourhood
+// through LDS in chunks of TILE_CAP sources.
+constexpr int WAVE = 64;
+constexpr int TILE_T = 64;
+constexpr int TILE_CAP = 512;
+constexpr int TILE_ZMAX = 62;     // z-boxes per multi-box tile (<= 64 slabs)
+constexpr int TILE_PAD = 64;      // sentinel slots after the staged sources
+
+// tiles[t] = {col, z0, z1 or -(z+1) for a dense tile, first target}
+struct TileDesc {
+    int col, z0, z1, tstart;
+};
+
+inline int64_t max_tiles_for(int64_t N, int64_t nbox)
+{
+    int64_t m = N < nbox ? N : nbox;
+    return 2 * m + N / TILE_T + 2;
+}
+
+#define DMK_HIP_CHECK(call)                         \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return DMK_EHIP;      \
+    } while (0)
+
+}  // namespace dmk

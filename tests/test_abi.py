@@ -1,0 +1,97 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/dmk.h, sizes its arena, and rejects bad arguments on the
+host before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2606_27134_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "dmk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmk_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = _declared_functions()
+    assert len(names) >= 8
+    for name in names:
+        assert hasattr(lib, name), name
+        assert getattr(lib, name) is not None
+
+
+def test_version_and_strerror():
+    assert "gfx950" in L.dmk_version()
+    for code in range(7):
+        assert L.strerror(code)
+    assert L.strerror(DMK_UNKNOWN := 99) == "unknown status"
+
+
+def test_bins_bytes_and_carve_host_only():
+    g = L.make_grid((1, 1, 1), 3, (64, 64, 64))
+    nb = L.dmk_bins_bytes(g, 1_000_000)
+    assert nb > 1_000_000 * (4 * 3 + 24)
+    b = L.dmk_bins()
+    fake = 1 << 40  # carve only computes pointers
+    assert L.dmk_bins_carve(g, 1_000_000, fake, nb, b) == L.DMK_OK
+    assert b.N == 1_000_000 and b.nbox == 64 ** 3 and b.ntiles == 0
+    ptrs = [b.key, b.perm, b.skey, b.box_start, b.ys, b.axis_nbr, b.axis_img, b.tiles, b.status, b.tmp]
+    assert all(p % 256 == 0 for p in ptrs)
+    assert max(ptrs) < fake + nb
+    assert L.dmk_bins_carve(g, 1_000_000, fake, nb - 1, b) == L.DMK_ESIZE
+    assert L.dmk_bins_carve(g, 1_000_000, fake + 8, nb, b) == L.DMK_EINVAL
+
+
+@pytest.mark.parametrize("L_,D,n", [((1, 1, 1), 4, (4, 4, 4)), ((1, 1, 1), 3, (0, 4, 4)),
+                                    ((0, 1, 1), 3, (4, 4, 4)), ((1, -1, 1), 1, (4, 4, 4))])
+def test_bad_grid_rejected(L_, D, n):
+    g = L.make_grid(L_, D, n)
+    assert L.dmk_bins_bytes(g, 10) == 0
+    b = L.dmk_bins()
+    assert L.dmk_bins_carve(g, 10, 1 << 40, 1 << 30, b) == L.DMK_EINVAL
+    assert L.dmk_tree_bin(g, 0, b, 0) == L.DMK_EINVAL
+
+
+def _carved(N=100):
+    g = L.make_grid((1, 1, 1), 3, (4, 4, 4))
+    b = L.dmk_bins()
+    assert L.dmk_bins_carve(g, N, 1 << 40, L.dmk_bins_bytes(g, N), b) == L.DMK_OK
+    return g, b
+
+
+def test_eval_argument_errors_before_launch():
+    g, b = _carved()
+    P = 1 << 41
+    ws = L.dmk_residual_ws_bytes(g, b, 0, 0, 0)
+    assert ws >= 100 * 8
+    # cutoff larger than the leaf box, non-positive cutoff, bad sigma
+    assert L.dmk_residual_eval(g, b, 0, 0, 0.05, 0.3, P, P, P, ws, 0) == L.DMK_ECUTOFF
+    assert L.dmk_residual_eval(g, b, 0, 0, 0.05, 0.0, P, P, P, ws, 0) == L.DMK_ECUTOFF
+    assert L.dmk_residual_eval(g, b, 0, 0, -1.0, 0.1, P, P, P, ws, 0) == L.DMK_ECUTOFF
+    assert L.dmk_residual_eval(g, b, 0, 0, float("nan"), 0.1, P, P, P, ws, 0) == L.DMK_ECUTOFF
+    # unsupported kernel / precision
+    assert L.dmk_residual_eval(g, b, 7, 0, 0.05, 0.1, P, P, P, ws, 0) == L.DMK_EUNSUPPORTED
+    assert L.dmk_residual_eval(g, b, 0, 5, 0.05, 0.1, P, P, P, ws, 0) == L.DMK_EUNSUPPORTED
+    # null pointers and small workspace
+    assert L.dmk_residual_eval(g, b, 0, 0, 0.05, 0.1, 0, P, P, ws, 0) == L.DMK_EINVAL
+    assert L.dmk_residual_eval(g, b, 0, 0, 0.05, 0.1, P, P, P, ws - 8, 0) == L.DMK_ESIZE
+    wsb = L.dmk_residual_ws_bytes(g, b, 1, 1, 1)
+    assert L.dmk_residual_backward(g, b, 1, 1, 0.05, 0.1, P, 0, P, P, P, wsb, 0) == L.DMK_EINVAL
+    assert L.dmk_residual_backward(g, b, 1, 1, 0.05, 0.1, P, P, P, P, P, wsb - 8, 0) == L.DMK_ESIZE
+    # grid / bins mismatch
+    g2 = L.make_grid((1, 1, 1), 3, (5, 4, 4))
+    assert L.dmk_residual_eval(g2, b, 0, 0, 0.05, 0.1, P, P, P, ws, 0) == L.DMK_EINVAL
+
+
+def test_workspace_sizes_grow_with_components():
+    g, b = _carved(1000)
+    sizes = [L.dmk_residual_ws_bytes(g, b, k, 0, bw) for k in range(4) for bw in (0, 1)]
+    assert all(s >= 1000 * 8 for s in sizes)
+    assert L.dmk_residual_ws_bytes(g, b, 2, 0, 1) > L.dmk_residual_ws_bytes(g, b, 0, 0, 0)

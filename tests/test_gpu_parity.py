@@ -1,0 +1,193 @@
+"""Parity of the HIP residual kernels (through the C ABI) with the CPU oracle.
+
+Bars: FP64 path rel l2 <= 1e-12, FP32-compensated path rel l2 <= 1e-6, and
+every element within 10x that bar relative to the largest reference value.
+Small cases compare every output; full-size workloads (the sizes the bench
+runs) compare a seeded sample of targets that the oracle evaluates one by
+one.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import HAVE_GPU, assert_parity, dev, host, needs_gpu
+from paper_2606_27134_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+if HAVE_GPU:
+    import torch
+    from paper_2606_27134_amd import residual as R
+
+TOL = {"fp64": 1e-12, "fp32c": 1e-6}
+KERNELS = ["laplace", "stokeslet", "stresslet", "rotlet"]
+
+
+def run_fwd(w, prec, x=None, rho=None):
+    x = w.x if x is None else x
+    rho = w.rho if rho is None else rho
+    b = R.tree_bin(w.L, w.D, w.n, dev(x))
+    u = R.residual_eval(b, w.kernel, prec, w.sigma, w.rc, dev(rho))
+    return host(u), b
+
+
+def run_bwd(w, prec, G):
+    b = R.tree_bin(w.L, w.D, w.n, dev(w.x))
+    gr, gx = R.residual_backward(b, w.kernel, prec, w.sigma, w.rc, dev(w.rho), dev(G))
+    return host(gr), host(gx)
+
+
+def oracle_fwd(w, targets=None):
+    return oracle.residual(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, targets=targets)
+
+
+# --------------------------------------------------------------------------
+# small cases: all outputs compared
+SMALL = []
+for k in KERNELS:
+    SMALL += [
+        (k, 3, (1.0, 1.0, 1.0), (8, 8, 8), 3000, "uniform"),
+        (k, 2, (1.0, 1.0, 2.0), (6, 6, 12), 2500, "clustered"),
+        (k, 1, (4.0, 1.0, 1.0), (20, 5, 5), 3000, "uniform"),
+        (k, 0, (1.0, 1.0, 1.0), (7, 5, 6), 2000, "uniform"),
+    ]
+
+
+def _case(i):
+    k, D, Lv, n, N, dist = SMALL[i]
+    return W.random_case(seed=500 + i, kernel=k, D=D, L=Lv, n=n, N=N, dist=dist)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("i", range(len(SMALL)))
+def test_forward_small(i, prec):
+    w = _case(i)
+    print("case", SMALL[i], prec, flush=True)
+    got, b = run_fwd(w, prec)
+    assert_parity(got, oracle_fwd(w), TOL[prec], "fwd %s %s D=%d" % (w.kernel, prec, w.D))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("i", range(len(SMALL)))
+def test_backward_small(i, prec):
+    w = _case(i)
+    print("case", SMALL[i], prec, flush=True)
+    G = W.cotangent(w.seed, w.N, W.M_OUT[w.kernel])
+    gr, gx = run_bwd(w, prec, G)
+    rr, rx = oracle.residual_vjp(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, G)
+    assert_parity(gr, rr, TOL[prec], "grad_rho %s %s D=%d" % (w.kernel, prec, w.D))
+    assert_parity(gx, rx, TOL[prec], "grad_x %s %s D=%d" % (w.kernel, prec, w.D))
+
+
+@pytest.mark.parametrize("prec", ["fp64"])
+def test_c1_full(prec):
+    w = W.make("C1")
+    got, _ = run_fwd(w, prec)
+    assert_parity(got, oracle_fwd(w), TOL[prec], "C1 fwd")
+    G = w.rho.copy()
+    gr, gx = run_bwd(w, prec, G)
+    rr, rx = oracle.residual_vjp(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, G)
+    assert_parity(gr, rr, TOL[prec], "C1 grad_rho")
+    assert_parity(gx, rx, TOL[prec], "C1 grad_x")
+
+
+# --------------------------------------------------------------------------
+# dense boxes: tiles that stream their neighbourhood through LDS in chunks
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_dense_boxes(kernel, prec):
+    rng = np.random.default_rng(77)
+    N = 6000
+    x = np.concatenate([0.5 + 0.03 * rng.standard_normal((4000, 3)), rng.random((2000, 3))])
+    x = np.mod(x, 1.0)
+    w = W.random_case(seed=78, kernel=kernel, D=3, L=(1, 1, 1), n=(5, 5, 5), N=N)
+    w.x = x
+    got, b = run_fwd(w, prec)
+    tiles = host(b.tiles())
+    assert (tiles[:, 2] < 0).sum() >= 20, "expected dense tiles"
+    assert_parity(got, oracle_fwd(w), TOL[prec], "dense fwd %s %s" % (kernel, prec))
+    G = W.cotangent(78, N, W.M_OUT[kernel])
+    gr, gx = run_bwd(w, prec, G)
+    rr, rx = oracle.residual_vjp(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, G)
+    assert_parity(gr, rr, TOL[prec], "dense grad_rho")
+    assert_parity(gx, rx, TOL[prec], "dense grad_x")
+
+
+# --------------------------------------------------------------------------
+# edge cases
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_edge_cases(prec):
+    rng = np.random.default_rng(11)
+    # tiny periodic tilings (n_i = 1, 2): a box is its own neighbour via images
+    for D, Lv, n in [(3, (0.3, 0.3, 0.3), (1, 1, 1)), (3, (0.5, 0.4, 0.6), (2, 2, 2)),
+                     (2, (0.4, 0.4, 0.8), (1, 2, 3)), (1, (0.5, 1.0, 1.0), (2, 4, 3))]:
+        for k in KERNELS:
+            w = W.random_case(seed=12, kernel=k, D=D, L=Lv, n=n, N=150)
+            got, _ = run_fwd(w, prec)
+            assert_parity(got, oracle_fwd(w), TOL[prec], "tiny %s D=%d n=%s" % (k, D, n))
+    # rc below the box size, points on faces and duplicates, periodic inputs outside the cell
+    w = W.random_case(seed=13, kernel="stokeslet", D=3, L=(1, 1, 1), n=(6, 6, 6), N=1500, rc_frac=0.6)
+    x = w.x.copy()
+    x[:100] = np.round(x[:100] * 6) / 6
+    x[100:110] = x[110:120]
+    x[200:300, 0] += 1.0
+    x[300:400, 1] -= 2.0
+    got, _ = run_fwd(w, prec, x=x)
+    ref = oracle.residual(w.kernel, w.D, w.L, w.sigma, w.rc, x, w.rho)
+    assert_parity(got, ref, TOL[prec], "faces/duplicates/outside")
+    # single point, and a pair across a periodic face
+    w1 = W.random_case(seed=14, kernel="laplace", D=3, L=(1, 1, 1), n=(4, 4, 4), N=1)
+    got, _ = run_fwd(w1, prec)
+    assert got.shape == (1, 1) and got[0, 0] == 0.0
+    w2 = W.random_case(seed=15, kernel="rotlet", D=3, L=(1, 1, 1), n=(4, 4, 4), N=2)
+    w2.x = np.array([[0.01, 0.5, 0.5], [0.99, 0.52, 0.49]])
+    got, _ = run_fwd(w2, prec)
+    assert_parity(got, oracle_fwd(w2), TOL[prec], "pair across face")
+
+
+def test_deterministic():
+    w = W.random_case(seed=21, kernel="stokeslet", D=2, L=(1, 1, 2), n=(8, 8, 16), N=20000, dist="clustered")
+    for prec in ("fp64", "fp32c"):
+        a, _ = run_fwd(w, prec)
+        b, _ = run_fwd(w, prec)
+        assert a.tobytes() == b.tobytes()
+
+
+# --------------------------------------------------------------------------
+# full-size workloads, sampled targets
+def _sample(w, k=64, seed=0):
+    rng = np.random.default_rng(seed)
+    t = rng.choice(w.N, size=k, replace=False)
+    return np.sort(t)
+
+
+FULL = [("C2", "laplace"), ("C3", "stokeslet"), ("C4", "stresslet"), ("C4", "rotlet")]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("name,kernel", FULL)
+def test_full_size_sampled(name, kernel, prec):
+    w = W.make(name, kernel=kernel)
+    print("full", name, kernel, prec, w.N, flush=True)
+    got, b = run_fwd(w, prec)
+    t = _sample(w)
+    if name == "C3":  # include targets of the densest boxes
+        sk = host(b.skey())
+        perm = host(b.perm())
+        dense_box = np.bincount(sk).argmax()
+        t = np.unique(np.concatenate([t, perm[sk == dense_box][:32]]))
+    ref = oracle_fwd(w, targets=t)
+    assert_parity(got[t], ref, TOL[prec], "%s %s %s sampled" % (name, kernel, prec))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("name,kernel", [("C2", "laplace"), ("C3", "stokeslet")])
+def test_full_size_backward_sampled(name, kernel, prec):
+    w = W.make(name, kernel=kernel)
+    print("full bwd", name, kernel, prec, flush=True)
+    G = W.cotangent(w.seed, w.N, W.M_OUT[kernel])
+    gr, gx = run_bwd(w, prec, G)
+    t = _sample(w, seed=1)
+    rr, rx = oracle.residual_vjp(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, G, targets=t)
+    assert_parity(gr[t], rr, TOL[prec], "%s grad_rho %s" % (name, prec))
+    assert_parity(gx[t], rx, TOL[prec], "%s grad_x %s" % (name, prec))
