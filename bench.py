@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the leaf-level residual interaction on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C2]
+
+One step = dmk_residual_eval (forward) + dmk_residual_backward (adjoint) of
+the whole workload, with the points already binned and all inputs resident
+in HBM (the binning, the paper's tree construction, is timed separately and
+reported as bin_ms).  The headline is the FP32-compensated path; the FP64
+path is timed the same way and reported beside it.
+
+Metric: in-cutoff ordered pair interactions (0 < r < rc, P_in) per second of
+forward + backward.  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2606_27134_amd import workloads as W  # noqa: E402
+
+METRIC = "residual pair-interactions/s fwd+bwd, FP32-compensated vs FP64 at stated rel err"
+
+# Algorithmic flops per in-cutoff pair (add/mul = 1, fma = 2, each elementary
+# function rsqrt/exp/erfc = 1), counted from the kernel formulas.
+FLOPS_PER_PAIR = {
+    ("laplace", "fwd"): 19, ("laplace", "bwd"): 34,
+    ("stokeslet", "fwd"): 42, ("stokeslet", "bwd"): 95,
+    ("stresslet", "fwd"): 68, ("stresslet", "bwd"): 190,
+    ("rotlet", "fwd"): 33, ("rotlet", "bwd"): 70,
+}
+PEAK_TFLOPS = {"fp32c": 157.3, "fp64": 78.6}  # MI355X vector peaks
+HBM_PEAK_GBS = 8000.0
+
+
+def count_pairs(w, targets=None):
+    """Ordered in-cutoff pairs (0 < r < rc) over the images of the first D axes."""
+    from scipy.spatial import cKDTree
+    L = np.asarray(w.L, dtype=np.float64)
+    box = np.array([L[i] if i < w.D else 2.0 * L[i] + 4.0 * w.rc for i in range(3)])
+    x = np.mod(w.x, L) if w.D == 3 else w.x.copy()
+    for i in range(w.D):
+        x[:, i] = np.mod(w.x[:, i], L[i])
+        x[:, i] = np.where(x[:, i] >= L[i], 0.0, x[:, i])
+    tree = cKDTree(x, boxsize=box)
+    if targets is None:
+        return int(tree.count_neighbors(tree, w.rc)) - len(x)
+    q = cKDTree(x[targets], boxsize=box)
+    return int(q.count_neighbors(tree, w.rc)) - len(targets)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2606_27134_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2606_27134_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload, prec, khash):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_hash") != khash:
+        return None
+    return d.get(prec)
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The oracle (fwd + vjp) on a bounded sample of targets of the same workload."""
+    import oracle
+    oracle.build()
+    rng = np.random.default_rng(123)
+    G = W.cotangent(w.seed, w.N, W.M_OUT[w.kernel])
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = min(cores, os.cpu_count() or cores)
+    n_try = 2 * cores
+    t = np.sort(rng.choice(w.N, size=n_try, replace=False))
+    t0 = time.perf_counter()
+    oracle.residual(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, targets=t)
+    oracle.residual_vjp(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, G, targets=t)
+    dt = time.perf_counter() - t0
+    n = int(max(n_try, min(w.N, n_try * budget_s / max(dt, 1e-3))))
+    n = max(cores, (n // cores) * cores)
+    t = np.sort(rng.choice(w.N, size=n, replace=False))
+    t0 = time.perf_counter()
+    u = oracle.residual(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, targets=t)
+    gr, gx = oracle.residual_vjp(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, G, targets=t)
+    dt = time.perf_counter() - t0
+    pin = count_pairs(w, targets=t)
+    return dict(value=pin / dt, unit="pair-interactions/s", cores=cores, kind="oracle",
+                sample="%d seeded targets of %s (all %d sources, every image), fwd + vjp, %.1f s, "
+                       "P_in(sample)=%d" % (n, w.name, w.N, dt, pin)), (t, u, gr, gx, G)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--kernel", default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precs", default="fp32c,fp64")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    ws_env = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or ws_env != 1:
+        print("bench.py runs on exactly one GPU: this library has no multi-GPU path "
+              "(--gpus %d requested)." % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        n = 1 << 27  # 128 Mi doubles = 1 GiB
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+        return
+
+    from paper_2606_27134_amd import residual as R
+
+    w = W.make(args.workload, kernel=args.kernel)
+    stream = torch.cuda.current_stream()
+    x = torch.as_tensor(w.x).cuda()
+    rho = torch.as_tensor(w.rho).cuda()
+    G = torch.as_tensor(W.cotangent(w.seed, w.N, W.M_OUT[w.kernel])).cuda()
+
+    # binning (setup), timed on its own
+    bins = R.Bins(w.L, w.D, w.n, w.N)
+    bins.bin(x)
+    torch.cuda.synchronize()
+    tb = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        bins.bin(x)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+    bin_ms = 1e3 * float(np.median(tb))
+
+    P_in = count_pairs(w)
+    precs = [p for p in args.precs.split(",") if p]
+    res = {}
+    outs = {}
+    for prec in precs:
+        ws_f = R.workspace(bins, w.kernel, prec, False)
+        ws_b = R.workspace(bins, w.kernel, prec, True)
+        u = torch.empty((w.N, W.M_OUT[w.kernel]), dtype=torch.float64, device="cuda")
+        gr = torch.empty((w.N, W.M_IN[w.kernel]), dtype=torch.float64, device="cuda")
+        gx = torch.empty((w.N, 3), dtype=torch.float64, device="cuda")
+
+        def step():
+            R.residual_eval(bins, w.kernel, prec, w.sigma, w.rc, rho, out=u, ws=ws_f)
+            R.residual_backward(bins, w.kernel, prec, w.sigma, w.rc, rho, G, out=(gr, gx), ws=ws_b)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.steps + 2)]
+        start, stop = ev[-2], ev[-1]
+        t_wall = time.perf_counter()
+        start.record(stream)
+        for k in range(args.steps):
+            ev[3 * k].record(stream)
+            R.residual_eval(bins, w.kernel, prec, w.sigma, w.rc, rho, out=u, ws=ws_f)
+            ev[3 * k + 1].record(stream)
+            R.residual_backward(bins, w.kernel, prec, w.sigma, w.rc, rho, G, out=(gr, gx), ws=ws_b)
+            ev[3 * k + 2].record(stream)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        t_wall = time.perf_counter() - t_wall
+        total_ms = start.elapsed_time(stop)
+        fwd = [ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in range(args.steps)]
+        bwd = [ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in range(args.steps)]
+        ms_step = total_ms / args.steps
+        res[prec] = dict(ms_per_step=ms_step, fwd_ms=float(np.mean(fwd)), bwd_ms=float(np.mean(bwd)),
+                         fwd_ms_median=float(np.median(fwd)), bwd_ms_median=float(np.median(bwd)),
+                         value=P_in / (ms_step * 1e-3), wall_s=t_wall)
+        outs[prec] = (u.cpu().numpy(), gr.cpu().numpy(), gx.cpu().numpy())
+
+    head = "fp32c" if "fp32c" in res else precs[0]
+    r = res[head]
+    # dominant kernel: the larger of the two launches of the headline step
+    dom = "bwd" if r["bwd_ms"] >= r["fwd_ms"] else "fwd"
+    dur_ms = r[dom + "_ms"]
+    flops = FLOPS_PER_PAIR[(w.kernel, dom)] * P_in
+    achieved = flops / (dur_ms * 1e-3) / 1e12
+    khash = kernel_hash()
+    tr = read_traffic(w.name, head, khash)
+    traffic = None if tr is None else tr.get(dom)
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS[head], "traffic": traffic,
+            "kernel": "k_residual<%s,%s,%s> (+ payload gather)" % (w.kernel, head, dom),
+            "flops_per_pair": FLOPS_PER_PAIR[(w.kernel, dom)], "launch_ms": dur_ms}
+
+    line = {
+        "metric": METRIC, "value": r["value"], "unit": "pair-interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if head == "fp32c" else "f64", "data": "synthetic",
+        "config": {"workload": "%s: %s D=%d L=%s n=%s N=%d sigma=%.6g rc=%.6g" % (
+            w.name, w.kernel, w.D, list(w.L), list(w.n), w.N, w.sigma, w.rc),
+            "precision": head, "step": "residual forward + adjoint (points pre-binned)"},
+        "P_in": P_in, "bin_ms": bin_ms,
+        "fwd_ms": r["fwd_ms"], "bwd_ms": r["bwd_ms"],
+        "roofline": roof, "kernel_hash": khash,
+    }
+    if "fp64" in res and head != "fp64":
+        f = res["fp64"]
+        line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "fwd_ms": f["fwd_ms"],
+                        "bwd_ms": f["bwd_ms"]}
+        line["fp32c_speedup_vs_fp64"] = f["ms_per_step"] / r["ms_per_step"]
+
+    if not args.no_cpu_baseline:
+        cb, (t, u_o, gr_o, gx_o, _) = cpu_baseline(w)
+        line["cpu_baseline"] = cb
+        errs = {}
+        for prec, (u, gr, gx) in outs.items():
+            def rl2(a, b):
+                return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+            errs[prec] = {"u": rl2(u[t], u_o), "grad_rho": rl2(gr[t], gr_o), "grad_x": rl2(gx[t], gx_o)}
+        line["rel_l2_vs_oracle"] = errs
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

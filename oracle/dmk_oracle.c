@@ -226,7 +226,7 @@ int oracle_residual(int kern, int D, const double L[3], double sigma, double rc,
     if (check_common(kern, D, L, sigma, rc, N)) return 1;
     const int mi = m_in_of(kern), mo = m_out_of(kern);
     const long double rcl = rc;
-#pragma omp parallel for schedule(dynamic, 4)
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t ib = 0; ib < ntgt; ib++) {
         const int64_t b = tgt ? tgt[ib] : ib;
         long double acc[3] = {0.0L, 0.0L, 0.0L};
@@ -273,7 +273,7 @@ int oracle_residual_vjp(int kern, int D, const double L[3], double sigma, double
     if (check_common(kern, D, L, sigma, rc, N)) return 1;
     const int mi = m_in_of(kern), mo = m_out_of(kern);
     const long double rcl = rc;
-#pragma omp parallel for schedule(dynamic, 4)
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t ic = 0; ic < ntgt; ic++) {
         const int64_t c = tgt ? tgt[ic] : ic;
         long double gr[9] = {0}, gx[3] = {0};
@@ -326,7 +326,7 @@ int oracle_direct_free(int kern, int64_t N, const double *x, const double *rho, 
 {
     if (kern < 0 || kern > 3 || N < 0) return 1;
     const int mi = m_in_of(kern), mo = m_out_of(kern);
-#pragma omp parallel for schedule(dynamic, 4)
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t ib = 0; ib < ntgt; ib++) {
         const int64_t b = tgt ? tgt[ib] : ib;
         long double acc[3] = {0, 0, 0};

@@ -35,6 +35,7 @@
 #include <math.h>
 
 #include "dmk_internal.h"
+#include "erfcx_f32.h"
 
 namespace dmk {
 
@@ -52,9 +53,13 @@ struct Cfg {
     static constexpr int NTP = BWD ? MIN + MOUT : 0;     // payload per target
     static constexpr int NC = BWD ? MIN + 3 : MOUT;      // sums per target
     static constexpr bool F32 = sizeof(FP) == 4;
-    static constexpr int CAPP = TILE_CAP + TILE_PAD;
+    static constexpr int NW = 4;                         // wavefronts per tile
+    static constexpr int TPW = TILE_T / NW;              // targets per wavefront
+    static constexpr int SCAN = 2 * WAVE;                // sources tested per scan step
+    static constexpr int CAPP = TILE_CAP + SCAN;         // staged slots incl. sentinels
     static constexpr int QB = NC * (int)sizeof(FP);
-    static constexpr int QCAP = (QB <= 16) ? 512 : (QB <= 48 ? 256 : 128);
+    static constexpr int QCAP = (QB <= 24) ? 256 : 128;  // queue entries per wavefront
+    static constexpr int LPT = WAVE / TPW;               // lanes summing one target's run
 };
 
 struct ResParams {
@@ -89,17 +94,22 @@ struct Smem {
     float sp[NX32][(C::F32 && C::NPL > 2) ? C::CAPP : 1];  // FP32 payload 2..
     double sx[S64], sy[S64], sz[S64];
     double spd[NX64][S64];
-    float4 tc[TILE_T];
+    float4 tc[TILE_T];           // target hi coords, w = target payload 0 (FP32 path)
     float4 tl[C::F32 ? TILE_T : 1];
     float tp[TX32][(C::F32 && C::NTP > 2) ? TILE_T : 1];
     double tx[C::F32 ? 1 : TILE_T], ty[C::F32 ? 1 : TILE_T], tz[C::F32 ? 1 : TILE_T];
     double tpd[TX64][(!C::F32 && C::NTP > 0) ? TILE_T : 1];
-    uint32_t queue[C::QCAP];
-    typename std::conditional<C::F32, float, double>::type contrib[C::NC][C::QCAP];
-    int dtab[(TILE_ZMAX + 2) * 9];
-    int soff[TILE_ZMAX + 4];
+    int ta[TILE_T], tb[TILE_T];  // stencil range of each target in the staged order
+    union {
+        uint32_t queue[C::NW][C::QCAP];   // pair queue of each wavefront (scan / pair step)
+        int dgs[(TILE_ZMAX + 2) * 9];     // box start of each (slab, column) (set-up only)
+    };
+    typename std::conditional<C::F32, float, double>::type contrib[C::NW][C::NC][C::QCAP];
+    int dtab[(TILE_ZMAX + 2) * 9];  // box counts, then slab-major offset - box start
+    int soff[TILE_ZMAX + 4];        // slab offsets in the staged order
     int ccol[9];
     int qtot;
+    int segso[32];                  // piece offsets in the concatenated order (padded)
     Seg seg[27];
 };
 
@@ -135,8 +145,20 @@ __device__ inline Rad<T> radial(T r2, T isig, T isig2)
     R.r = r2 * R.ri;
     R.t = R.r * isig;
     R.t2 = r2 * isig2;
-    R.phi = expneg_(R.t2) * (T)0.56418958354775628695;  // 1/sqrt(pi)
-    R.Phi = erfc_(R.t);
+    if constexpr (sizeof(T) == 4) {
+        // one exponential serves both the window phi(t) = e^{-t^2}/sqrt(pi) and
+        // Phi(t) = erfc(t) = e^{-t^2} erfcx(t); erfcx from the fitted polynomial
+        const float e = __builtin_amdgcn_exp2f(-R.t2 * 1.4426950408889634f);
+        const float u = __builtin_amdgcn_rcpf(1.0f + ERFCX_F32_SHIFT * R.t);
+        float pol = ERFCX_F32_C[ERFCX_F32_DEG];
+#pragma unroll
+        for (int k = ERFCX_F32_DEG - 1; k >= 0; --k) pol = pol * u + ERFCX_F32_C[k];
+        R.phi = e * 0.56418958354775628695f;
+        R.Phi = e * (u * pol);
+    } else {
+        R.phi = expneg_(R.t2) * (T)0.56418958354775628695;  // 1/sqrt(pi)
+        R.Phi = erfc_(R.t);
+    }
     return R;
 }
 
@@ -277,37 +299,93 @@ __device__ inline void pair_bwd(const T d[3], T r2, T isig, T isig2, const T *ps
 
 // --------------------------------------------------------------------------
 template <class C>
-__device__ inline void stage_source(Smem<C> &S, const ResParams &P, int dest, int64_t j, double ox, double oy,
-                                    double oz)
+__device__ inline void store_source(Smem<C> &S, int dest, double X, double Y, double Z, const double *pl)
 {
-    const int64_t N = P.N;
-    const double X = P.ys[j] + ox;
-    const double Y = P.ys[N + j] + oy;
-    const double Z = P.ys[2 * N + j] + oz;
     if constexpr (C::F32) {
         const float hx = (float)X, hy = (float)Y, hz = (float)Z;
         const float lx = (float)(X - (double)hx), ly = (float)(Y - (double)hy), lz = (float)(Z - (double)hz);
-        const float p0 = (float)P.pl[j];
-        const float p1 = (C::NPL > 1) ? (float)P.pl[N + j] : 0.0f;
-        S.sc[dest] = make_float4(hx, hy, hz, p0);
-        S.sl[dest] = make_float4(lx, ly, lz, p1);
-        for (int c = 2; c < C::NPL; ++c) S.sp[c - 2][dest] = (float)P.pl[c * N + j];
+        S.sc[dest] = make_float4(hx, hy, hz, (float)pl[0]);
+        S.sl[dest] = make_float4(lx, ly, lz, (C::NPL > 1) ? (float)pl[C::NPL > 1 ? 1 : 0] : 0.0f);
+        for (int c = 2; c < C::NPL; ++c) S.sp[c - 2][dest] = (float)pl[c];
     } else {
         S.sc[dest] = make_float4((float)X, (float)Y, (float)Z, 0.0f);
         S.sx[dest] = X;
         S.sy[dest] = Y;
         S.sz[dest] = Z;
-        for (int c = 0; c < C::NPL; ++c) S.spd[c][dest] = P.pl[c * N + j];
+        for (int c = 0; c < C::NPL; ++c) S.spd[c][dest] = pl[c];
     }
 }
 
+// Stage the sources of one chunk [c0, c0+clen) of the tile's concatenated
+// pieces.  Multi-box tiles (dense == false, one chunk) place every source at
+// its slab-major slot dtab[slab*9 + column] + j; dense tiles keep the
+// concatenated order.  Each thread handles up to PER sources and issues all
+// of their global loads before its first LDS store.
+template <class C>
+__device__ inline void stage_chunk(Smem<C> &S, const ResParams &P, bool dense, int c0, int clen, int za, int n2,
+                                   int tid)
+{
+    constexpr int NT = C::NW * WAVE;
+    constexpr int PER = (TILE_CAP + NT - 1) / NT;
+    const int64_t N = P.N;
+    int sgi[PER], sk[PER];
+    int64_t jj[PER];
+    double X[PER], Y[PER], Z[PER], pl[PER][C::NPL];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int q = tid + u * NT;
+        const int qc = (dense ? c0 : 0) + (q < clen ? q : 0);
+        int lo = 0;  // last piece whose offset is <= qc
+#pragma unroll
+        for (int step = 16; step > 0; step >>= 1)
+            if (S.segso[lo + step] <= qc) lo += step;
+        sgi[u] = lo;
+        jj[u] = (int64_t)S.seg[lo].gstart + (qc - S.seg[lo].so);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        if (tid + u * NT < clen) {
+            const int64_t j = jj[u];
+            const Seg &g = S.seg[sgi[u]];
+            X[u] = P.ys[j] + g.offx;
+            Y[u] = P.ys[N + j] + g.offy;
+            Z[u] = P.ys[2 * N + j] + g.offz;
+            for (int c = 0; c < C::NPL; ++c) pl[u][c] = P.pl[c * N + j];
+            sk[u] = dense ? 0 : P.skey[j];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int q = tid + u * NT;
+        if (q < clen) {
+            int dest = q;
+            if (!dense) {
+                const Seg &g = S.seg[sgi[u]];
+                const int slab = (sk[u] - S.ccol[g.k] * n2) + g.vshift - za;
+                dest = S.dtab[slab * 9 + g.k] + (int)jj[u];
+            }
+            store_source<C>(S, dest, X[u], Y[u], Z[u], pl[u]);
+        }
+    }
+}
+
+// wavefront-local ordering of LDS accesses (the LDS unit serves one
+// wavefront's instructions in order; this stops compiler reordering)
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int KERN, typename FP, bool BWD>
-__global__ __launch_bounds__(64) void k_residual(ResParams P)
+__global__ __launch_bounds__(256) void k_residual(ResParams P)
 {
     using C = Cfg<KERN, FP, BWD>;
     using T = FP;
     __shared__ Smem<C> S;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int w = tid / WAVE;
     const int per = (P.ntiles + 7) >> 3;
     const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);  // XCD-contiguous tile runs
     if (tile >= P.ntiles) return;
@@ -325,98 +403,116 @@ __global__ __launch_bounds__(64) void k_residual(ResParams P)
     const int za = z0 - 1, zb = z1 + 1, nslab = z1 - z0 + 3;
     const int r0 = n0 + n1;
 
-    // ---- neighbour columns and their contiguous source pieces (<= 3 each)
-    if (lane < 27) S.seg[lane].glen = 0;
-    if (lane < 9) S.ccol[lane] = -1;
-    __syncthreads();
-    if (lane < 9) {
-        const int k = lane, c0 = k / 3, c1 = k % 3;
+    const T isig = (T)(1.0 / P.sigma);
+    const T isig2 = isig * isig;
+    const T rc2 = (T)(P.rc * P.rc);
+    const float rc2s = (float)(P.rc * P.rc * (1.0 + 4e-4));  // scan margin; exact test in the pair step
+
+    // ---- phase A: every independent global load of the tile set-up at once
+    //  * tid < 27: source piece (neighbour column k = tid/3, z piece tid%3)
+    //  * all threads: box counts of the slab-major table (multi-box tiles)
+    //  * tid < ntgt: target coordinates and payload
+    if (tid < 27) {
+        const int k = tid / 3, piece = tid % 3, c0 = k / 3, c1 = k % 3;
+        Seg g;
+        g.glen = 0;
+        g.gstart = 0;
+        g.k = k;
+        g.vshift = 0;
+        g.offx = g.offy = g.offz = 0.0;
         const int nb0 = P.nbr[3 * b0 + c0], nb1 = P.nbr[3 * (n0 + b1) + c1];
         if (nb0 >= 0 && nb1 >= 0) {
-            const int s0 = P.img[3 * b0 + c0], s1 = P.img[3 * (n0 + b1) + c1];
             const int cc = nb0 * n1 + nb1;
             const int64_t cb = (int64_t)cc * n2;
-            S.ccol[k] = cc;
-            const double ox = s0 * P.L[0] - crx, oy = s1 * P.L[1] - cry;
-            // piece 0: virtual z = -1
-            if (za == -1) {
-                const int zp = P.nbr[3 * r0 + 0];
-                if (zp >= 0) {
-                    Seg &g = S.seg[3 * k + 0];
-                    g.gstart = P.bs[cb + zp];
-                    g.glen = P.bs[cb + zp + 1] - g.gstart;
-                    g.k = k;
-                    g.vshift = -1 - zp;
-                    g.offx = ox;
-                    g.offy = oy;
-                    g.offz = P.img[3 * r0 + 0] * P.L[2] - crz;
-                }
+            g.offx = P.img[3 * b0 + c0] * P.L[0] - crx;
+            g.offy = P.img[3 * (n0 + b1) + c1] * P.L[1] - cry;
+            int lo = 1, hi = 0, zimg = 0;
+            if (piece == 0 && za == -1) {  // virtual z = -1
+                lo = hi = P.nbr[3 * r0 + 0];
+                zimg = P.img[3 * r0 + 0];
+                g.vshift = -1 - lo;
+            } else if (piece == 1) {       // virtual z in [max(za,0), min(zb,n2-1)]
+                lo = za < 0 ? 0 : za;
+                hi = zb > n2 - 1 ? n2 - 1 : zb;
+            } else if (piece == 2 && zb == n2) {  // virtual z = n2
+                lo = hi = P.nbr[3 * (r0 + n2 - 1) + 2];
+                zimg = P.img[3 * (r0 + n2 - 1) + 2];
+                g.vshift = n2 - lo;
             }
-            // piece 1: virtual z in [max(za,0), min(zb,n2-1)], no z image
-            {
-                const int lo = za < 0 ? 0 : za, hi = zb > n2 - 1 ? n2 - 1 : zb;
-                if (lo <= hi) {
-                    Seg &g = S.seg[3 * k + 1];
-                    g.gstart = P.bs[cb + lo];
-                    g.glen = P.bs[cb + hi + 1] - g.gstart;
-                    g.k = k;
-                    g.vshift = 0;
-                    g.offx = ox;
-                    g.offy = oy;
-                    g.offz = -crz;
-                }
+            if (lo >= 0 && lo <= hi) {
+                g.gstart = P.bs[cb + lo];
+                g.glen = P.bs[cb + hi + 1] - g.gstart;
+                g.offz = zimg * P.L[2] - crz;
             }
-            // piece 2: virtual z = n2
-            if (zb == n2) {
-                const int zp = P.nbr[3 * (r0 + n2 - 1) + 2];
-                if (zp >= 0) {
-                    Seg &g = S.seg[3 * k + 2];
-                    g.gstart = P.bs[cb + zp];
-                    g.glen = P.bs[cb + zp + 1] - g.gstart;
-                    g.k = k;
-                    g.vshift = n2 - zp;
-                    g.offx = ox;
-                    g.offy = oy;
-                    g.offz = P.img[3 * (r0 + n2 - 1) + 2] * P.L[2] - crz;
-                }
-            }
+            if (piece == 1) S.ccol[k] = cc;
+        } else if (piece == 1) {
+            S.ccol[k] = -1;
         }
+        S.seg[tid] = g;
     }
-    __syncthreads();
-    if (lane == 0) {
-        int so = 0;
-        for (int s = 0; s < 27; ++s) {
-            S.seg[s].so = so;
-            so += S.seg[s].glen;
-        }
-        S.qtot = so;
-    }
-    // ---- slab-major offsets for multi-box tiles
     if (!dense) {
         const int M = nslab * 9;
-        int carry = 0;
-        for (int base = 0; base < M; base += 64) {
-            const int idx = base + lane;
+        for (int idx = tid; idx < M; idx += C::NW * WAVE) {
+            const int sl = idx / 9, k = idx - (idx / 9) * 9;
+            const int nb0 = P.nbr[3 * b0 + k / 3], nb1 = P.nbr[3 * (n0 + b1) + k % 3];
+            const int zv = za + sl;
+            int zp = zv;
+            if (zv < 0)
+                zp = P.nbr[3 * r0 + 0];
+            else if (zv >= n2)
+                zp = P.nbr[3 * (r0 + n2 - 1) + 2];
             int cnt = 0, gs = 0;
-            if (idx < M) {
-                const int s = idx / 9, k = idx - (idx / 9) * 9;
-                const int cc = S.ccol[k];
-                const int zv = za + s;
-                int zp = zv;
-                if (zv < 0)
-                    zp = P.nbr[3 * r0 + 0];
-                else if (zv >= n2)
-                    zp = P.nbr[3 * (r0 + n2 - 1) + 2];
-                if (cc >= 0 && zp >= 0) {
-                    const int64_t b = (int64_t)cc * n2 + zp;
-                    gs = P.bs[b];
-                    cnt = P.bs[b + 1] - gs;
-                }
+            if (nb0 >= 0 && nb1 >= 0 && zp >= 0) {
+                const int64_t bb = (int64_t)(nb0 * n1 + nb1) * n2 + zp;
+                gs = P.bs[bb];
+                cnt = P.bs[bb + 1] - gs;
             }
+            S.dtab[idx] = cnt;
+            S.dgs[idx] = gs;
+        }
+    }
+    int my_zt = 0;
+    if (tid < TILE_T && tstart + tid < P.N) {  // all 64 slots; ones past ntgt are never used
+        const int64_t j = tstart + tid;
+        const double X = P.ys[j] - crx, Y = P.ys[P.N + j] - cry, Z = P.ys[2 * P.N + j] - crz;
+        const float hx = (float)X, hy = (float)Y, hz = (float)Z;
+        if constexpr (C::F32) {
+            const float t0 = (C::NTP > 0) ? (float)P.pl[j] : 0.0f;
+            const float t1 = (C::NTP > 1) ? (float)P.pl[P.N + j] : 0.0f;
+            S.tc[tid] = make_float4(hx, hy, hz, t0);
+            S.tl[tid] = make_float4((float)(X - (double)hx), (float)(Y - (double)hy), (float)(Z - (double)hz), t1);
+            for (int c = 2; c < C::NTP; ++c) S.tp[c - 2][tid] = (float)P.pl[c * P.N + j];
+        } else {
+            S.tc[tid] = make_float4(hx, hy, hz, 0.0f);
+            S.tx[tid] = X;
+            S.ty[tid] = Y;
+            S.tz[tid] = Z;
+            for (int c = 0; c < C::NTP; ++c) S.tpd[c][tid] = P.pl[c * P.N + j];
+        }
+        if (!dense) my_zt = P.skey[j] - (int)colb;
+    }
+    __syncthreads();
+
+    // ---- phase B (LDS only): piece offsets in the concatenated order, and the
+    // slab-major offsets dtab[s*9+k] - box start (multi-box tiles)
+    if (tid < 32) {
+        // inclusive scan of the 27 piece lengths by one wavefront's lanes
+        const int gl = tid < 27 ? S.seg[tid].glen : 0;
+        const int incl = wave_incl_scan(gl);
+        if (tid < 27) S.seg[tid].so = incl - gl;
+        S.segso[tid] = tid < 27 ? incl - gl : 0x7fffffff;
+        if (tid == 26) S.qtot = incl;
+    }
+    if (!dense && w == 1) {
+        const int M = nslab * 9;
+        int carry = 0;
+        for (int base = 0; base < M; base += WAVE) {
+            const int idx = base + lane;
+            const int cnt = idx < M ? S.dtab[idx] : 0;
             const int incl = wave_incl_scan(cnt);
             if (idx < M) {
                 const int off = carry + incl - cnt;
-                S.dtab[idx] = off - gs;
+                S.dtab[idx] = off - S.dgs[idx];
                 if (idx % 9 == 0) S.soff[idx / 9] = off;
             }
             carry += __shfl(incl, 63, 64);
@@ -424,39 +520,13 @@ __global__ __launch_bounds__(64) void k_residual(ResParams P)
         if (lane == 0) S.soff[nslab] = carry;
     }
     __syncthreads();
-
-    // ---- targets: tile-relative coordinates, payload, stencil range
-    const T isig = (T)(1.0 / P.sigma);
-    const T isig2 = isig * isig;
-    const T rc2 = (T)(P.rc * P.rc);
-    const float rc2s = (float)(P.rc * P.rc * (1.0 + 4e-4));  // scan margin; exact test in the pair step
-    float thx = 0.f, thy = 0.f, thz = 0.f;
-    int my_a = 0, my_b = 0;
-    if (lane < ntgt) {
-        const int64_t j = tstart + lane;
-        const double X = P.ys[j] - crx, Y = P.ys[P.N + j] - cry, Z = P.ys[2 * P.N + j] - crz;
-        thx = (float)X;
-        thy = (float)Y;
-        thz = (float)Z;
-        if constexpr (C::F32) {
-            const float t0 = (C::NTP > 0) ? (float)P.pl[j] : 0.0f;
-            const float t1 = (C::NTP > 1) ? (float)P.pl[P.N + j] : 0.0f;
-            S.tc[lane] = make_float4(thx, thy, thz, t0);
-            S.tl[lane] = make_float4((float)(X - (double)thx), (float)(Y - (double)thy), (float)(Z - (double)thz), t1);
-            for (int c = 2; c < C::NTP; ++c) S.tp[c - 2][lane] = (float)P.pl[c * P.N + j];
-        } else {
-            S.tx[lane] = X;
-            S.ty[lane] = Y;
-            S.tz[lane] = Z;
-            for (int c = 0; c < C::NTP; ++c) S.tpd[c][lane] = P.pl[c * P.N + j];
-        }
-        if (!dense) {
-            const int zt = P.skey[j] - (int)colb;
-            my_a = S.soff[zt - z0];
-            my_b = S.soff[zt - z0 + 3];
-        }
+    if (!dense && tid < ntgt) {
+        S.ta[tid] = S.soff[my_zt - z0];
+        S.tb[tid] = S.soff[my_zt - z0 + 3];
     }
 
+    // target t = w + NW*i belongs to lanes [LPT*i, LPT*i + LPT) of wavefront w;
+    // those lanes sum interleaved parts of its pair run
     T acc[C::NC], cmp[C::NC];
     for (int c = 0; c < C::NC; ++c) {
         acc[c] = 0;
@@ -464,13 +534,14 @@ __global__ __launch_bounds__(64) void k_residual(ResParams P)
     }
     int qn = 0;
     int rs = 0, re = 0;
+    uint32_t *queue = S.queue[w];
 
     auto flush = [&]() {
-        __syncthreads();
-        for (int base = 0; base < qn; base += 64) {
+        wave_sync();
+        for (int base = 0; base < qn; base += WAVE) {
             const int i = base + lane;
             if (i < qn) {
-                const uint32_t e = S.queue[i];
+                const uint32_t e = queue[i];
                 const int t = (int)(e >> 16), q = (int)(e & 0xffffu);
                 T d[3], ps[C::NPL], pt[C::NTP > 0 ? C::NTP : 1];
                 if constexpr (C::F32) {
@@ -501,14 +572,14 @@ __global__ __launch_bounds__(64) void k_residual(ResParams P)
                     pair_bwd<KERN, T>(d, r2, isig, isig2, ps, pt, v);
                 else
                     pair_fwd<KERN, T>(d, r2, isig, isig2, ps, v);
-                for (int c = 0; c < C::NC; ++c) S.contrib[c][i] = ok ? v[c] : (T)0;
+                for (int c = 0; c < C::NC; ++c) S.contrib[w][c][i] = ok ? v[c] : (T)0;
             }
         }
-        __syncthreads();
-        // each target lane sums its own run, in queue order
-        for (int i = rs; i < re; ++i) {
+        wave_sync();
+        // the lanes of each target sum interleaved parts of its run (fixed order)
+        for (int i = rs + (lane % C::LPT); i < re; i += C::LPT) {
             for (int c = 0; c < C::NC; ++c) {
-                const T x = S.contrib[c][i];
+                const T x = S.contrib[w][c][i];
                 if constexpr (C::F32) {
                     const T y = x - cmp[c];
                     const T s = acc[c] + y;
@@ -519,7 +590,7 @@ __global__ __launch_bounds__(64) void k_residual(ResParams P)
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
         qn = 0;
         rs = 0;
         re = 0;
@@ -528,62 +599,67 @@ __global__ __launch_bounds__(64) void k_residual(ResParams P)
     const int qtot = dense ? S.qtot : S.soff[nslab];
     for (int c0 = 0; c0 < qtot || c0 == 0; c0 += TILE_CAP) {
         const int clen = dense ? min(TILE_CAP, qtot - c0) : qtot;
-        // ---- stage sources of this chunk
-        for (int sg = 0; sg < 27; ++sg) {
-            const Seg g = S.seg[sg];
-            if (g.glen == 0) continue;
-            if (dense) {
-                const int lo = max(g.so, c0), hi = min(g.so + g.glen, c0 + clen);
-                for (int p = lo + lane; p < hi; p += 64)
-                    stage_source<C>(S, P, p - c0, (int64_t)g.gstart + (p - g.so), g.offx, g.offy, g.offz);
-            } else {
-                const int cb = S.ccol[g.k] * n2;
-                for (int j = g.gstart + lane; j < g.gstart + g.glen; j += 64) {
-                    const int s = (P.skey[j] - cb) + g.vshift - za;
-                    stage_source<C>(S, P, S.dtab[s * 9 + g.k] + j, (int64_t)j, g.offx, g.offy, g.offz);
-                }
-            }
-        }
-        if (clen + lane < C::CAPP) S.sc[clen + lane] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
+        // ---- stage sources of this chunk: flat over the concatenated pieces,
+        // all loads of a thread issued before any of its LDS stores
+        stage_chunk<C>(S, P, dense, c0, clen, za, n2, tid);
+        if (tid < C::SCAN) S.sc[clen + tid] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
         __syncthreads();
 
         // ---- scan: one target at a time over its contiguous stencil range
-        for (int t = 0; t < ntgt; ++t) {
-            const float tx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(thx), t));
-            const float ty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(thy), t));
-            const float tz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(thz), t));
-            const int a = dense ? 0 : __builtin_amdgcn_readlane(my_a, t);
-            const int b = dense ? clen : __builtin_amdgcn_readlane(my_b, t);
-            if (lane == t) rs = qn;
-            for (int p = a; p < b; p += 64) {
-                if (qn + 64 > C::QCAP) {
-                    if (lane == t) re = qn;
+        for (int i = 0; i < C::TPW; ++i) {
+            const int t = w + C::NW * i;
+            if (t >= ntgt) break;
+            const float4 tt = S.tc[t];
+            const float tx = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tt.x)));
+            const float ty = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tt.y)));
+            const float tz = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tt.z)));
+            const int a = dense ? 0 : __builtin_amdgcn_readfirstlane(S.ta[t]);
+            const int b = dense ? clen : __builtin_amdgcn_readfirstlane(S.tb[t]);
+            const uint32_t tag = (uint32_t)t << 16;
+            const bool mine = (lane / C::LPT) == i;
+            if (mine) rs = qn;
+            for (int p = a; p < b; p += C::SCAN) {
+                if (qn + C::SCAN > C::QCAP) {
+                    if (mine) re = qn;
                     flush();
                 }
-                const int q = p + lane;
-                const float4 s = S.sc[q];
-                const float dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                const bool hit = r2 < rc2s;
-                const uint64_t m = __ballot(hit);
-                if (hit) {
-                    const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    S.queue[pos] = ((uint32_t)t << 16) | (uint32_t)q;
-                }
-                qn += __popcll(m);
+                const int q0 = p + lane, q1 = q0 + WAVE;
+                const float4 s0 = S.sc[q0];
+                const float4 s1 = S.sc[q1];
+                const float ax = s0.x - tx, ay = s0.y - ty, az = s0.z - tz;
+                const float bx = s1.x - tx, by = s1.y - ty, bz = s1.z - tz;
+                const float ra = ax * ax + ay * ay + az * az;
+                const float rb = bx * bx + by * by + bz * bz;
+                const bool ha = ra < rc2s, hb = rb < rc2s;
+                const uint64_t ma = __ballot(ha);
+                const uint64_t mb = __ballot(hb);
+                const int na = __popcll(ma);
+                const int pa = qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u));
+                const int pb = qn + na + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
+                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+                if (ha) queue[pa] = tag | (uint32_t)q0;
+                if (hb) queue[pb] = tag | (uint32_t)q1;
+                qn += na + __popcll(mb);
             }
-            if (lane == t) re = qn;
+            if (mine) re = qn;
         }
         flush();
+        __syncthreads();
         if (!dense) break;
     }
 
-    // ---- write back in the original order
-    if (lane < ntgt) {
-        const int64_t orig = P.perm[tstart + lane];
-        double res[C::NC];
-        for (int c = 0; c < C::NC; ++c) res[c] = C::F32 ? (double)acc[c] - (double)cmp[c] : (double)acc[c];
+    // ---- combine the LPT partial sums of each target in FP64, write back in
+    // the original order
+    const int tmine = w + C::NW * (lane / C::LPT);
+    double res[C::NC];
+    for (int c = 0; c < C::NC; ++c) {
+        double v = C::F32 ? (double)acc[c] - (double)cmp[c] : (double)acc[c];
+        for (int off = 1; off < C::LPT; off <<= 1) v += __shfl_xor(v, off, WAVE);
+        res[c] = v;
+    }
+    if ((lane % C::LPT) == 0 && tmine < ntgt) {
+        const int64_t orig = P.perm[tstart + tmine];
         if constexpr (BWD) {
             for (int c = 0; c < C::MIN; ++c) P.out0[orig * C::MIN + c] = res[c];
             for (int c = 0; c < 3; ++c) P.out1[orig * 3 + c] = res[C::MIN + c];
@@ -644,7 +720,7 @@ template <int KERN, typename FP, bool BWD>
 void launch_one(const ResParams &P, hipStream_t s)
 {
     const unsigned per = (unsigned)((P.ntiles + 7) / 8);
-    hipLaunchKernelGGL((k_residual<KERN, FP, BWD>), dim3(8 * per), dim3(64), 0, s, P);
+    hipLaunchKernelGGL((k_residual<KERN, FP, BWD>), dim3(8 * per), dim3(256), 0, s, P);
 }
 
 template <bool BWD>

@@ -54,14 +54,12 @@ class Bins:
         code = L.dmk_bins_carve(self.grid, self.N, base + self._off, nbytes, self.c)
         if code != L.DMK_OK:
             raise L.DmkError(code, "dmk_bins_carve")
-        self.version = None
 
     def bin(self, x: torch.Tensor):
         _require_dev_f64(x, "x", (self.N, 3))
         code = L.dmk_tree_bin(self.grid, x.data_ptr(), self.c, _stream())
         if code != L.DMK_OK:
             raise L.DmkError(code, "dmk_tree_bin")
-        self.version = (x.data_ptr(), x._version)
         return self
 
     @property
@@ -151,28 +149,25 @@ class ResidualSpec:
     prec: str
     sigma: float
     rc: float
-    _bins: Bins = None
-
-    def bins_for(self, x: torch.Tensor) -> Bins:
-        key = (x.data_ptr(), x._version)
-        if self._bins is None or self._bins.N != x.shape[0] or self._bins.version != key:
-            self._bins = tree_bin(self.L, self.D, self.n, x)
-        return self._bins
 
 
 class DmkResidual(torch.autograd.Function):
     """u = residual sum of K_R over the leaf neighbourhood (HIP kernels).
 
-    forward(x[N,3], rho[N,m_in], spec) -> u[N,m_out]; backward gives
-    (grad_x, grad_rho) from the library's adjoint kernel.  The binning is
-    cached on x's storage and version counter.
+    forward(x[N,3], rho[N,m_in], spec, bins=None) -> u[N,m_out]; backward
+    gives (grad_x, grad_rho) from the library's adjoint kernel.  The points
+    are binned on every forward call unless a Bins built from these exact
+    positions is passed in (then the caller vouches that it matches x).
     """
 
     @staticmethod
-    def forward(ctx, x, rho, spec: ResidualSpec):
+    def forward(ctx, x, rho, spec: ResidualSpec, bins: Bins = None):
         x_ = x.detach().contiguous()
         rho_ = rho.detach().contiguous()
-        bins = spec.bins_for(x_)
+        if bins is None:
+            bins = tree_bin(spec.L, spec.D, spec.n, x_)
+        elif bins.N != x_.shape[0]:
+            raise ValueError("bins were built for %d points, x has %d" % (bins.N, x_.shape[0]))
         u = residual_eval(bins, spec.kernel, spec.prec, spec.sigma, spec.rc, rho_)
         ctx.spec = spec
         ctx.bins = bins
@@ -184,8 +179,8 @@ class DmkResidual(torch.autograd.Function):
         (rho_,) = ctx.saved_tensors
         s = ctx.spec
         grho, gx = residual_backward(ctx.bins, s.kernel, s.prec, s.sigma, s.rc, rho_, gu.contiguous())
-        return gx, grho, None
+        return gx, grho, None, None
 
 
-def dmk_residual(x, rho, spec: ResidualSpec):
-    return DmkResidual.apply(x, rho, spec)
+def dmk_residual(x, rho, spec: ResidualSpec, bins: Bins = None):
+    return DmkResidual.apply(x, rho, spec, bins)
