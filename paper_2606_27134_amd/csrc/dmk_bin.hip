@@ -262,8 +262,18 @@ __device__ inline int slab_count(const TileGeom &g, const int ccol[9], int zv)
     return s;
 }
 
+// Cost of a tile = sum over its targets of the size of their stencil ranges.
+// The key orders tiles heavy-first by power-of-two cost bucket, so a stable
+// sort by key keeps spatially adjacent tiles of similar cost together.
+__device__ inline int cost_key(int64_t cost)
+{
+    const int bucket = 64 - __clzll((unsigned long long)(cost + 1));
+    return 64 - bucket;
+}
+
 template <bool WRITE>
-__global__ void k_tiles(TileGeom g, int32_t *__restrict__ counts, int4 *__restrict__ tiles)
+__global__ void k_tiles(TileGeom g, int32_t *__restrict__ counts, int4 *__restrict__ tiles,
+                        int32_t *__restrict__ tkey)
 {
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= g.n[0] * g.n[1]) return;
@@ -288,26 +298,44 @@ __global__ void k_tiles(TileGeom g, int32_t *__restrict__ counts, int4 *__restri
         const int first = g.bs[(int64_t)col * n2 + z];
         if (nt > TILE_T || q1 > TILE_CAP) {
             for (int c = 0; c < nt; c += TILE_T) {
-                if (WRITE) tiles[out + cnt] = make_int4(col, z, -(z + 1), first + c);
+                if (WRITE) {
+                    const int m = nt - c < TILE_T ? nt - c : TILE_T;
+                    tiles[out + cnt] = make_int4(col, z, -(z + 1), first + c);
+                    tkey[out + cnt] = cost_key((int64_t)m * q1);
+                }
                 ++cnt;
             }
             ++z;
             continue;
         }
         int z1 = z, tacc = nt, q = q1;
+        int64_t cost = (int64_t)nt * q1;
         while (z1 + 1 < n2 && (z1 + 1 - z + 1) <= TILE_ZMAX) {
             const int nn = box_count(g, col, z1 + 1);
-            const int qn = q + slab_count(g, ccol, z1 + 2);
+            const int s2 = slab_count(g, ccol, z1 + 2);
+            const int qn = q + s2;
             if (tacc + nn > TILE_T || qn > TILE_CAP) break;
+            if (WRITE && nn > 0)
+                cost += (int64_t)nn * (slab_count(g, ccol, z1) + slab_count(g, ccol, z1 + 1) + s2);
             ++z1;
             tacc += nn;
             q = qn;
         }
-        if (WRITE) tiles[out + cnt] = make_int4(col, z, z1, first);
+        if (WRITE) {
+            tiles[out + cnt] = make_int4(col, z, z1, first);
+            tkey[out + cnt] = cost_key(cost);
+        }
         ++cnt;
         z = z1 + 1;
     }
     if (!WRITE) counts[col] = cnt;
+}
+
+__global__ void k_gather_tiles(const int4 *__restrict__ tin, const int32_t *__restrict__ order, int64_t n,
+                               int4 *__restrict__ tout)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) tout[i] = tin[order[i]];
 }
 
 __global__ void k_tile_total(const int32_t *__restrict__ counts, int ncol, const int32_t *__restrict__ last_raw,
@@ -353,7 +381,10 @@ Layout layout_for(const dmk_grid *g, int64_t N)
     const int64_t ncol = (int64_t)g->n[0] * g->n[1];
     const int64_t nblk = (N + RS_TILE - 1) / RS_TILE;
     l.max_tiles = max_tiles_for(N, nbox);
-    l.tmp_ints = 2 * N + 256 * (nblk > 0 ? nblk : 1) + ncol + 64;
+    const int64_t tblk = (l.max_tiles + RS_TILE - 1) / RS_TILE;
+    const int64_t phase1 = 2 * N + 256 * (nblk > 0 ? nblk : 1) + 64;
+    const int64_t phase2 = (ncol + 64) + 7 * l.max_tiles + 256 * (tblk > 0 ? tblk : 1) + 64;
+    l.tmp_ints = phase1 > phase2 ? phase1 : phase2;
     size_t off = 0;
     l.key = off;
     off = align256(off + sizeof(int32_t) * N);
@@ -448,7 +479,6 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     int32_t *altk = bins->tmp;
     int32_t *altv = bins->tmp + N;
     int32_t *hist = bins->tmp + 2 * N;
-    int32_t *colcnt = hist + 256 * (nblk > 0 ? nblk : 1);
 
     DMK_HIP_CHECK(hipMemsetAsync(bins->status, 0, sizeof(int32_t) * 4, stream));
     if (N > 0) {
@@ -485,14 +515,19 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     for (int i = 0; i < 3; ++i) tg.n[i] = grid->n[i];
     tg.bs = bins->box_start;
     tg.nbr = bins->axis_nbr;
-    hipLaunchKernelGGL(k_tiles<false>, dim3(nblocks(ncol, 64)), dim3(64), 0, stream, tg, colcnt,
-                       (int4 *)bins->tiles);
+    // tile scratch (the point sort is done with tmp by now)
+    int32_t *colcnt = bins->tmp;
+    int4 *tiles_u = (int4 *)(bins->tmp + ((ncol + 64 + 3) & ~(int64_t)3));
+    int32_t *tkey = (int32_t *)(tiles_u + bins->max_tiles);
+    int32_t *tkey2 = tkey + bins->max_tiles;
+    int32_t *torder = tkey2 + bins->max_tiles;
+    int32_t *thist = torder + bins->max_tiles;
+    hipLaunchKernelGGL(k_tiles<false>, dim3(nblocks(ncol, 64)), dim3(64), 0, stream, tg, colcnt, tiles_u, tkey);
     // keep the raw count of the last column, scan, then total
     DMK_HIP_CHECK(hipMemcpyAsync(bins->status + 2, colcnt + ncol - 1, sizeof(int32_t), hipMemcpyDeviceToDevice,
                                  stream));
     hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, stream, colcnt, ncol);
-    hipLaunchKernelGGL(k_tiles<true>, dim3(nblocks(ncol, 64)), dim3(64), 0, stream, tg, colcnt,
-                       (int4 *)bins->tiles);
+    hipLaunchKernelGGL(k_tiles<true>, dim3(nblocks(ncol, 64)), dim3(64), 0, stream, tg, colcnt, tiles_u, tkey);
     hipLaunchKernelGGL(k_tile_total, dim3(1), dim3(1), 0, stream, colcnt, (int)ncol, bins->status + 2,
                        bins->status);
     DMK_HIP_CHECK(hipGetLastError());
@@ -501,6 +536,18 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     DMK_HIP_CHECK(hipStreamSynchronize(stream));
     if (st[0] != 0) return DMK_EDOMAIN;
     if (st[1] < 0 || st[1] > bins->max_tiles) return DMK_ESIZE;
+    // order the tiles heavy-first (stable within a cost bucket)
+    const int64_t nt = st[1];
+    if (nt > 0) {
+        const int64_t tb = (nt + RS_TILE - 1) / RS_TILE;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tb), dim3(RS_THREADS), 0, stream, tkey, nt, 0, thist, (int)tb);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, stream, thist, (int64_t)256 * tb);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tb), dim3(RS_THREADS), 0, stream, tkey,
+                           (const int32_t *)nullptr, nt, 0, thist, (int)tb, tkey2, torder);
+        hipLaunchKernelGGL(k_gather_tiles, dim3(nblocks(nt, 256)), dim3(256), 0, stream, tiles_u, torder, nt,
+                           (int4 *)bins->tiles);
+        DMK_HIP_CHECK(hipGetLastError());
+    }
     bins->ntiles = st[1];
     return DMK_OK;
 }

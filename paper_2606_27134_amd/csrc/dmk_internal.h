@@ -15,9 +15,16 @@ namespace dmk {
 // LDS at once; a box whose targets or neighbourhood exceed that becomes
 // "dense" tiles of up to TILE_T targets that stream their neighbourhood
 // through LDS in chunks of TILE_CAP sources.
+#ifndef DMK_TILE_CAP
+#define DMK_TILE_CAP 512
+#endif
+#ifndef DMK_WAVES_PER_TILE
+#define DMK_WAVES_PER_TILE 4
+#endif
 constexpr int WAVE = 64;
 constexpr int TILE_T = 64;
-constexpr int TILE_CAP = 512;
+constexpr int TILE_CAP = DMK_TILE_CAP;
+constexpr int TILE_NW = DMK_WAVES_PER_TILE;  // wavefronts per tile workgroup
 constexpr int TILE_ZMAX = 62;     // z-boxes per multi-box tile (<= 64 slabs)
 constexpr int TILE_PAD = 64;      // sentinel slots after the staged sources
 

@@ -53,12 +53,15 @@ struct Cfg {
     static constexpr int NTP = BWD ? MIN + MOUT : 0;     // payload per target
     static constexpr int NC = BWD ? MIN + 3 : MOUT;      // sums per target
     static constexpr bool F32 = sizeof(FP) == 4;
-    static constexpr int NW = 4;                         // wavefronts per tile
-    static constexpr int TPW = TILE_T / NW;              // targets per wavefront
     static constexpr int SCAN = 2 * WAVE;                // sources tested per scan step
     static constexpr int CAPP = TILE_CAP + SCAN;         // staged slots incl. sentinels
-    static constexpr int QB = NC * (int)sizeof(FP);
-    static constexpr int QCAP = (QB <= 24) ? 256 : 128;  // queue entries per wavefront
+    static constexpr int QCAP = 256;                     // queue entries per wavefront
+    // LDS bytes of the staged sources and of one wavefront's queue; tiles use
+    // TILE_NW wavefronts unless that would not fit in the 160 KiB of a CU
+    static constexpr int STAGE_B = CAPP * (16 + (F32 ? 16 + 4 * (NPL > 2 ? NPL - 2 : 0) : 8 * (3 + NPL)));
+    static constexpr int WAVE_B = QCAP * (4 + NC * (int)sizeof(FP));
+    static constexpr int NW = (STAGE_B + TILE_NW * WAVE_B <= 150 * 1024) ? TILE_NW : 2;
+    static constexpr int TPW = TILE_T / NW;              // targets per wavefront
     static constexpr int LPT = WAVE / TPW;               // lanes summing one target's run
 };
 
@@ -378,7 +381,7 @@ __device__ inline void wave_sync()
 }
 
 template <int KERN, typename FP, bool BWD>
-__global__ __launch_bounds__(256) void k_residual(ResParams P)
+__global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
 {
     using C = Cfg<KERN, FP, BWD>;
     using T = FP;
@@ -386,8 +389,9 @@ __global__ __launch_bounds__(256) void k_residual(ResParams P)
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int w = tid / WAVE;
-    const int per = (P.ntiles + 7) >> 3;
-    const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);  // XCD-contiguous tile runs
+    // tiles are ordered heavy-first by the binning; consecutive workgroups go
+    // to different XCDs, which spreads the heavy tiles over all of them
+    const int tile = blockIdx.x;
     if (tile >= P.ntiles) return;
 
     const int4 TD = P.tiles[tile];
@@ -536,64 +540,100 @@ __global__ __launch_bounds__(256) void k_residual(ResParams P)
     int rs = 0, re = 0;
     uint32_t *queue = S.queue[w];
 
+    // pair step for queue entry i: contribution v[NC] (zero when the exact
+    // test rejects the pair: self / coincident, or outside the cutoff)
+    auto pair_value = [&](int i, T *v) {
+        const uint32_t e = queue[i];
+        const int t = (int)(e >> 16), q = (int)(e & 0xffffu);
+        T d[3], ps[C::NPL], pt[C::NTP > 0 ? C::NTP : 1];
+        if constexpr (C::F32) {
+            const float4 sh = S.sc[q], sl = S.sl[q], th = S.tc[t], tl = S.tl[t];
+            d[0] = (th.x - sh.x) + (tl.x - sl.x);
+            d[1] = (th.y - sh.y) + (tl.y - sl.y);
+            d[2] = (th.z - sh.z) + (tl.z - sl.z);
+            ps[0] = sh.w;
+            if (C::NPL > 1) ps[1] = sl.w;
+            for (int c = 2; c < C::NPL; ++c) ps[c] = S.sp[c - 2][q];
+            if constexpr (C::NTP > 0) {
+                pt[0] = th.w;
+                pt[1] = tl.w;
+                for (int c = 2; c < C::NTP; ++c) pt[c] = S.tp[c - 2][t];
+            }
+        } else {
+            d[0] = S.tx[t] - S.sx[q];
+            d[1] = S.ty[t] - S.sy[q];
+            d[2] = S.tz[t] - S.sz[q];
+            for (int c = 0; c < C::NPL; ++c) ps[c] = S.spd[c][q];
+            for (int c = 0; c < C::NTP; ++c) pt[c] = S.tpd[c][t];
+        }
+        T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        const bool ok = (r2 > (T)0) && (r2 < rc2);
+        if (!ok) r2 = rc2;  // keeps the math finite; result discarded
+        if constexpr (BWD)
+            pair_bwd<KERN, T>(d, r2, isig, isig2, ps, pt, v);
+        else
+            pair_fwd<KERN, T>(d, r2, isig, isig2, ps, v);
+        for (int c = 0; c < C::NC; ++c) v[c] = ok ? v[c] : (T)0;
+    };
+
+    auto kahan_add = [&](const T *x) {
+        for (int c = 0; c < C::NC; ++c) {
+            if constexpr (C::F32) {
+                const T y = x[c] - cmp[c];
+                const T s2 = acc[c] + y;
+                cmp[c] = (s2 - acc[c]) - y;
+                acc[c] = s2;
+            } else {
+                acc[c] += x[c];
+            }
+        }
+    };
+
+    // Multi-box tiles: the queue holds the runs of several targets; pair values
+    // go to the LDS contribution array and the LPT lanes of each target sum
+    // interleaved parts of its run in a fixed order.
     auto flush = [&]() {
         wave_sync();
         for (int base = 0; base < qn; base += WAVE) {
             const int i = base + lane;
             if (i < qn) {
-                const uint32_t e = queue[i];
-                const int t = (int)(e >> 16), q = (int)(e & 0xffffu);
-                T d[3], ps[C::NPL], pt[C::NTP > 0 ? C::NTP : 1];
-                if constexpr (C::F32) {
-                    const float4 sh = S.sc[q], sl = S.sl[q], th = S.tc[t], tl = S.tl[t];
-                    d[0] = (th.x - sh.x) + (tl.x - sl.x);
-                    d[1] = (th.y - sh.y) + (tl.y - sl.y);
-                    d[2] = (th.z - sh.z) + (tl.z - sl.z);
-                    ps[0] = sh.w;
-                    if (C::NPL > 1) ps[1] = sl.w;
-                    for (int c = 2; c < C::NPL; ++c) ps[c] = S.sp[c - 2][q];
-                    if constexpr (C::NTP > 0) {
-                        pt[0] = th.w;
-                        pt[1] = tl.w;
-                        for (int c = 2; c < C::NTP; ++c) pt[c] = S.tp[c - 2][t];
-                    }
-                } else {
-                    d[0] = S.tx[t] - S.sx[q];
-                    d[1] = S.ty[t] - S.sy[q];
-                    d[2] = S.tz[t] - S.sz[q];
-                    for (int c = 0; c < C::NPL; ++c) ps[c] = S.spd[c][q];
-                    for (int c = 0; c < C::NTP; ++c) pt[c] = S.tpd[c][t];
-                }
-                T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                const bool ok = (r2 > (T)0) && (r2 < rc2);
-                if (!ok) r2 = rc2;  // keeps the math finite; result discarded
                 T v[C::NC];
-                if constexpr (BWD)
-                    pair_bwd<KERN, T>(d, r2, isig, isig2, ps, pt, v);
-                else
-                    pair_fwd<KERN, T>(d, r2, isig, isig2, ps, v);
-                for (int c = 0; c < C::NC; ++c) S.contrib[w][c][i] = ok ? v[c] : (T)0;
+                pair_value(i, v);
+                for (int c = 0; c < C::NC; ++c) S.contrib[w][c][i] = v[c];
             }
         }
         wave_sync();
-        // the lanes of each target sum interleaved parts of its run (fixed order)
         for (int i = rs + (lane % C::LPT); i < re; i += C::LPT) {
-            for (int c = 0; c < C::NC; ++c) {
-                const T x = S.contrib[w][c][i];
-                if constexpr (C::F32) {
-                    const T y = x - cmp[c];
-                    const T s = acc[c] + y;
-                    cmp[c] = (s - acc[c]) - y;
-                    acc[c] = s;
-                } else {
-                    acc[c] += x;
-                }
-            }
+            T x[C::NC];
+            for (int c = 0; c < C::NC; ++c) x[c] = S.contrib[w][c][i];
+            kahan_add(x);
         }
         wave_sync();
         qn = 0;
         rs = 0;
         re = 0;
+    };
+
+    // Dense tiles: every queue epoch holds one target's run (the scan flushes
+    // at each target change), so each lane sums its pair values in registers
+    // and one butterfly gives the epoch's total to the target's lane.
+    auto flush_one = [&](int owner) {
+        wave_sync();
+        T part[C::NC];
+        for (int c = 0; c < C::NC; ++c) part[c] = 0;
+        for (int base = 0; base < qn; base += WAVE) {
+            const int i = base + lane;
+            if (i < qn) {
+                T v[C::NC];
+                pair_value(i, v);
+                for (int c = 0; c < C::NC; ++c) part[c] += v[c];
+            }
+        }
+        for (int off = WAVE / 2; off >= 1; off >>= 1)
+            for (int c = 0; c < C::NC; ++c) part[c] += __shfl_xor(part[c], off, WAVE);
+        if (lane == owner) kahan_add(part);
+        wave_sync();
+        qn = 0;
     };
 
     const int qtot = dense ? S.qtot : S.soff[nslab];
@@ -620,12 +660,16 @@ __global__ __launch_bounds__(256) void k_residual(ResParams P)
             if (mine) rs = qn;
             for (int p = a; p < b; p += C::SCAN) {
                 if (qn + C::SCAN > C::QCAP) {
-                    if (mine) re = qn;
-                    flush();
+                    if (dense) {
+                        flush_one(i * C::LPT);
+                    } else {
+                        if (mine) re = qn;
+                        flush();
+                    }
                 }
-                const int q0 = p + lane, q1 = q0 + WAVE;
+                const int q0 = p + lane;
                 const float4 s0 = S.sc[q0];
-                const float4 s1 = S.sc[q1];
+                const float4 s1 = S.sc[q0 + WAVE];
                 const float ax = s0.x - tx, ay = s0.y - ty, az = s0.z - tz;
                 const float bx = s1.x - tx, by = s1.y - ty, bz = s1.z - tz;
                 const float ra = ax * ax + ay * ay + az * az;
@@ -634,17 +678,23 @@ __global__ __launch_bounds__(256) void k_residual(ResParams P)
                 const uint64_t ma = __ballot(ha);
                 const uint64_t mb = __ballot(hb);
                 const int na = __popcll(ma);
-                const int pa = qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u));
-                const int pb = qn + na + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
-                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
-                if (ha) queue[pa] = tag | (uint32_t)q0;
-                if (hb) queue[pb] = tag | (uint32_t)q1;
-                qn += na + __popcll(mb);
+                // queue slot = running count + rank among the hits of this half;
+                // entry = (t << 16) | source slot
+                const uint32_t ea = (tag | (uint32_t)p) + (uint32_t)lane;
+                if (ha) queue[__builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)ma, (uint32_t)qn))] = ea;
+                if (hb) queue[__builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mb, (uint32_t)(qn + na)))] =
+                    ea + (uint32_t)WAVE;
+                qn = __builtin_amdgcn_readfirstlane(qn + na + __popcll(mb));
             }
-            if (mine) re = qn;
+            if (dense) {
+                if (qn > 0) flush_one(i * C::LPT);
+            } else if (mine) {
+                re = qn;
+            }
         }
-        flush();
+        if (!dense) flush();
         __syncthreads();
         if (!dense) break;
     }
@@ -719,8 +769,8 @@ size_t ws_need(int64_t N, int kernel, int backward)
 template <int KERN, typename FP, bool BWD>
 void launch_one(const ResParams &P, hipStream_t s)
 {
-    const unsigned per = (unsigned)((P.ntiles + 7) / 8);
-    hipLaunchKernelGGL((k_residual<KERN, FP, BWD>), dim3(8 * per), dim3(256), 0, s, P);
+    hipLaunchKernelGGL((k_residual<KERN, FP, BWD>), dim3((unsigned)P.ntiles), dim3(Cfg<KERN, FP, BWD>::NW * WAVE), 0,
+                       s, P);
 }
 
 template <bool BWD>
