@@ -103,6 +103,7 @@ struct Smem {
     double tx[C::F32 ? 1 : TILE_T], ty[C::F32 ? 1 : TILE_T], tz[C::F32 ? 1 : TILE_T];
     double tpd[TX64][(!C::F32 && C::NTP > 0) ? TILE_T : 1];
     int ta[TILE_T], tb[TILE_T];  // stencil range of each target in the staged order
+    int tperm[TILE_T];           // original index of each target
     union {
         uint32_t queue[C::NW][C::QCAP];   // pair queue of each wavefront (scan / pair step)
         int dgs[(TILE_ZMAX + 2) * 9];     // box start of each (slab, column) (set-up only)
@@ -372,6 +373,28 @@ __device__ inline void stage_chunk(Smem<C> &S, const ResParams &P, bool dense, i
     }
 }
 
+// neighbour box index along one axis for offset off in {-1,0,1}, with the
+// image index of the neighbour's points (periodic axes wrap, free axes end);
+// the same definition as the binning's axis tables, evaluated in registers
+__device__ inline int axis_nb(const ResParams &P, int ax, int b, int off, int &img)
+{
+    const int n = P.n[ax];
+    int nb = b + off;
+    img = 0;
+    if (ax < P.D) {
+        if (nb < 0) {
+            nb += n;
+            img = -1;
+        } else if (nb >= n) {
+            nb -= n;
+            img = 1;
+        }
+    } else if (nb < 0 || nb >= n) {
+        nb = -1;
+    }
+    return nb;
+}
+
 // wavefront-local ordering of LDS accesses (the LDS unit serves one
 // wavefront's instructions in order; this stops compiler reordering)
 __device__ inline void wave_sync()
@@ -405,7 +428,6 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
     const int b0 = col / n1, b1 = col - (col / n1) * n1;
     const double crx = (b0 + 0.5) * P.h[0], cry = (b1 + 0.5) * P.h[1], crz = (z0 + 0.5) * P.h[2];
     const int za = z0 - 1, zb = z1 + 1, nslab = z1 - z0 + 3;
-    const int r0 = n0 + n1;
 
     const T isig = (T)(1.0 / P.sigma);
     const T isig2 = isig * isig;
@@ -424,23 +446,22 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         g.k = k;
         g.vshift = 0;
         g.offx = g.offy = g.offz = 0.0;
-        const int nb0 = P.nbr[3 * b0 + c0], nb1 = P.nbr[3 * (n0 + b1) + c1];
+        int i0, i1;
+        const int nb0 = axis_nb(P, 0, b0, c0 - 1, i0), nb1 = axis_nb(P, 1, b1, c1 - 1, i1);
         if (nb0 >= 0 && nb1 >= 0) {
             const int cc = nb0 * n1 + nb1;
             const int64_t cb = (int64_t)cc * n2;
-            g.offx = P.img[3 * b0 + c0] * P.L[0] - crx;
-            g.offy = P.img[3 * (n0 + b1) + c1] * P.L[1] - cry;
+            g.offx = i0 * P.L[0] - crx;
+            g.offy = i1 * P.L[1] - cry;
             int lo = 1, hi = 0, zimg = 0;
             if (piece == 0 && za == -1) {  // virtual z = -1
-                lo = hi = P.nbr[3 * r0 + 0];
-                zimg = P.img[3 * r0 + 0];
+                lo = hi = axis_nb(P, 2, 0, -1, zimg);
                 g.vshift = -1 - lo;
             } else if (piece == 1) {       // virtual z in [max(za,0), min(zb,n2-1)]
                 lo = za < 0 ? 0 : za;
                 hi = zb > n2 - 1 ? n2 - 1 : zb;
             } else if (piece == 2 && zb == n2) {  // virtual z = n2
-                lo = hi = P.nbr[3 * (r0 + n2 - 1) + 2];
-                zimg = P.img[3 * (r0 + n2 - 1) + 2];
+                lo = hi = axis_nb(P, 2, n2 - 1, 1, zimg);
                 g.vshift = n2 - lo;
             }
             if (lo >= 0 && lo <= hi) {
@@ -458,13 +479,10 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         const int M = nslab * 9;
         for (int idx = tid; idx < M; idx += C::NW * WAVE) {
             const int sl = idx / 9, k = idx - (idx / 9) * 9;
-            const int nb0 = P.nbr[3 * b0 + k / 3], nb1 = P.nbr[3 * (n0 + b1) + k % 3];
+            int i0, i1, iz;
+            const int nb0 = axis_nb(P, 0, b0, k / 3 - 1, i0), nb1 = axis_nb(P, 1, b1, k % 3 - 1, i1);
             const int zv = za + sl;
-            int zp = zv;
-            if (zv < 0)
-                zp = P.nbr[3 * r0 + 0];
-            else if (zv >= n2)
-                zp = P.nbr[3 * (r0 + n2 - 1) + 2];
+            const int zp = (zv < 0) ? axis_nb(P, 2, 0, -1, iz) : (zv >= n2 ? axis_nb(P, 2, n2 - 1, 1, iz) : zv);
             int cnt = 0, gs = 0;
             if (nb0 >= 0 && nb1 >= 0 && zp >= 0) {
                 const int64_t bb = (int64_t)(nb0 * n1 + nb1) * n2 + zp;
@@ -494,6 +512,7 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
             for (int c = 0; c < C::NTP; ++c) S.tpd[c][tid] = P.pl[c * P.N + j];
         }
         if (!dense) my_zt = P.skey[j] - (int)colb;
+        S.tperm[tid] = P.perm[j];
     }
     __syncthreads();
 
@@ -709,7 +728,7 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         res[c] = v;
     }
     if ((lane % C::LPT) == 0 && tmine < ntgt) {
-        const int64_t orig = P.perm[tstart + tmine];
+        const int64_t orig = S.tperm[tmine];
         if constexpr (BWD) {
             for (int c = 0; c < C::MIN; ++c) P.out0[orig * C::MIN + c] = res[c];
             for (int c = 0; c < 3; ++c) P.out1[orig * 3 + c] = res[C::MIN + c];
