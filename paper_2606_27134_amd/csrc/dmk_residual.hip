@@ -664,16 +664,41 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         if (tid < C::SCAN) S.sc[clen + tid] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
         __syncthreads();
 
-        // ---- scan: one target at a time over its contiguous stencil range
-        for (int i = 0; i < C::TPW; ++i) {
-            const int t = w + C::NW * i;
-            if (t >= ntgt) break;
+        // ---- scan: one target at a time over its contiguous stencil range.
+        // Lane i of wavefront w holds target w + NW*i (coordinates, range) in
+        // registers; the first 128 sources of the next target are read from
+        // LDS while the current one is tested.
+        float vtx = 0.f, vty = 0.f, vtz = 0.f;
+        int va = 0, vb = 0;
+        const int nmine = ntgt > w ? min(C::TPW, (ntgt - w + C::NW - 1) / C::NW) : 0;
+        if (lane < nmine) {
+            const int t = w + C::NW * lane;
             const float4 tt = S.tc[t];
-            const float tx = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tt.x)));
-            const float ty = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tt.y)));
-            const float tz = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tt.z)));
-            const int a = dense ? 0 : __builtin_amdgcn_readfirstlane(S.ta[t]);
-            const int b = dense ? clen : __builtin_amdgcn_readfirstlane(S.tb[t]);
+            vtx = tt.x;
+            vty = tt.y;
+            vtz = tt.z;
+            va = dense ? 0 : S.ta[t];
+            vb = dense ? clen : S.tb[t];
+        }
+        float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0;
+        if (nmine > 0) {
+            const int a0 = __builtin_amdgcn_readlane(va, 0);
+            n0 = S.sc[a0 + lane];
+            n1 = S.sc[a0 + WAVE + lane];
+        }
+        for (int i = 0; i < nmine; ++i) {
+            const int t = w + C::NW * i;
+            const float tx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vtx), i));
+            const float ty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vty), i));
+            const float tz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vtz), i));
+            const int a = __builtin_amdgcn_readlane(va, i);
+            const int b = __builtin_amdgcn_readlane(vb, i);
+            const float4 c0 = n0, c1 = n1;
+            if (i + 1 < nmine) {
+                const int an = __builtin_amdgcn_readlane(va, i + 1);
+                n0 = S.sc[an + lane];
+                n1 = S.sc[an + WAVE + lane];
+            }
             const uint32_t tag = (uint32_t)t << 16;
             const bool mine = (lane / C::LPT) == i;
             if (mine) rs = qn;
@@ -686,9 +711,11 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
                         flush();
                     }
                 }
-                const int q0 = p + lane;
-                const float4 s0 = S.sc[q0];
-                const float4 s1 = S.sc[q0 + WAVE];
+                float4 s0 = c0, s1 = c1;
+                if (p != a) {
+                    s0 = S.sc[p + lane];
+                    s1 = S.sc[p + WAVE + lane];
+                }
                 const float ax = s0.x - tx, ay = s0.y - ty, az = s0.z - tz;
                 const float bx = s1.x - tx, by = s1.y - ty, bz = s1.z - tz;
                 const float ra = ax * ax + ay * ay + az * az;
