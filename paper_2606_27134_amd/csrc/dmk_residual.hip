@@ -58,7 +58,7 @@ struct Cfg {
     static constexpr int QCAP = 256;                     // queue entries per wavefront
     // LDS bytes of the staged sources and of one wavefront's queue; tiles use
     // TILE_NW wavefronts unless that would not fit in the 160 KiB of a CU
-    static constexpr int STAGE_B = CAPP * (16 + (F32 ? 16 + 4 * (NPL > 2 ? NPL - 2 : 0) : 8 * (3 + NPL)));
+    static constexpr int STAGE_B = CAPP * (16 + (F32 ? 16 + 4 * (NPL - 1) : 8 * (3 + NPL)));
     static constexpr int WAVE_B = QCAP * (4 + NC * (int)sizeof(FP));
     static constexpr int NW = (STAGE_B + TILE_NW * WAVE_B <= 150 * 1024) ? TILE_NW : 2;
     static constexpr int TPW = TILE_T / NW;              // targets per wavefront
@@ -88,13 +88,13 @@ template <class C>
 struct Smem {
     static constexpr int S32 = C::F32 ? C::CAPP : 1;
     static constexpr int S64 = C::F32 ? 1 : C::CAPP;
-    static constexpr int NX32 = (C::F32 && C::NPL > 2) ? C::NPL - 2 : 1;
+    static constexpr int NX32 = (C::F32 && C::NPL > 1) ? C::NPL - 1 : 1;
     static constexpr int NX64 = C::F32 ? 1 : C::NPL;
     static constexpr int TX32 = (C::F32 && C::NTP > 2) ? C::NTP - 2 : 1;
     static constexpr int TX64 = (!C::F32 && C::NTP > 0) ? C::NTP : 1;
-    float4 sc[C::CAPP];          // FP32 hi coords (scan), w = payload 0 (FP32 path)
-    float4 sl[S32];              // FP32 lo coords, w = payload 1
-    float sp[NX32][(C::F32 && C::NPL > 2) ? C::CAPP : 1];  // FP32 payload 2..
+    float4 sc[C::CAPP];          // FP32 (hi) coords s and |s|^2 (scan test)
+    float4 sl[S32];              // FP32 lo coords, w = payload 0 (FP32 path)
+    float sp[NX32][(C::F32 && C::NPL > 1) ? C::CAPP : 1];  // FP32 payload 1..
     double sx[S64], sy[S64], sz[S64];
     double spd[NX64][S64];
     float4 tc[TILE_T];           // target hi coords, w = target payload 0 (FP32 path)
@@ -308,11 +308,12 @@ __device__ inline void store_source(Smem<C> &S, int dest, double X, double Y, do
     if constexpr (C::F32) {
         const float hx = (float)X, hy = (float)Y, hz = (float)Z;
         const float lx = (float)(X - (double)hx), ly = (float)(Y - (double)hy), lz = (float)(Z - (double)hz);
-        S.sc[dest] = make_float4(hx, hy, hz, (float)pl[0]);
-        S.sl[dest] = make_float4(lx, ly, lz, (C::NPL > 1) ? (float)pl[C::NPL > 1 ? 1 : 0] : 0.0f);
-        for (int c = 2; c < C::NPL; ++c) S.sp[c - 2][dest] = (float)pl[c];
+        S.sc[dest] = make_float4(hx, hy, hz, hx * hx + hy * hy + hz * hz);
+        S.sl[dest] = make_float4(lx, ly, lz, (float)pl[0]);
+        for (int c = 1; c < C::NPL; ++c) S.sp[c - 1][dest] = (float)pl[c];
     } else {
-        S.sc[dest] = make_float4((float)X, (float)Y, (float)Z, 0.0f);
+        const float fx = (float)X, fy = (float)Y, fz = (float)Z;
+        S.sc[dest] = make_float4(fx, fy, fz, fx * fx + fy * fy + fz * fz);
         S.sx[dest] = X;
         S.sy[dest] = Y;
         S.sz[dest] = Z;
@@ -411,7 +412,9 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
     __shared__ Smem<C> S;
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
-    const int w = tid / WAVE;
+    // wavefront index, uniform across the wavefront (readfirstlane tells the
+    // compiler so: loops bounded by it then keep their control in scalar regs)
+    const int w = __builtin_amdgcn_readfirstlane(tid / WAVE);
     // tiles are ordered heavy-first by the binning; consecutive workgroups go
     // to different XCDs, which spreads the heavy tiles over all of them
     const int tile = blockIdx.x;
@@ -426,13 +429,21 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
     const int64_t colb = (int64_t)col * n2;
     const int ntgt = dense ? min(TILE_T, P.bs[colb + z0 + 1] - tstart) : (P.bs[colb + z1 + 1] - tstart);
     const int b0 = col / n1, b1 = col - (col / n1) * n1;
-    const double crx = (b0 + 0.5) * P.h[0], cry = (b1 + 0.5) * P.h[1], crz = (z0 + 0.5) * P.h[2];
+    // tile frame: origin at the centre of the column's middle z-box range
+    const double crx = (b0 + 0.5) * P.h[0], cry = (b1 + 0.5) * P.h[1], crz = ((z0 + z1) * 0.5 + 0.5) * P.h[2];
     const int za = z0 - 1, zb = z1 + 1, nslab = z1 - z0 + 3;
 
     const T isig = (T)(1.0 / P.sigma);
     const T isig2 = isig * isig;
     const T rc2 = (T)(P.rc * P.rc);
-    const float rc2s = (float)(P.rc * P.rc * (1.0 + 4e-4));  // scan margin; exact test in the pair step
+    // Scan test (FP32, conservative): source s is queued for target t when
+    // |s|^2 - 2 s.t < rc2s - |t|^2.  The rounding error of that expansion and
+    // of the FP32 coordinates is a few ulp of (|s| + |t|)^2 <= 4 R^2, with R
+    // the largest coordinate norm in the tile frame; the margin exceeds it
+    // twentyfold.  The pair step then applies the exact test.
+    const double ext_z = (z1 - z0) * 0.5 + 1.5;
+    const double R2 = 2.25 * (P.h[0] * P.h[0] + P.h[1] * P.h[1]) + ext_z * ext_z * P.h[2] * P.h[2];
+    const float rc2s = (float)(P.rc * P.rc * (1.0 + 4e-4) + 4.2e-5 * R2);
 
     // ---- phase A: every independent global load of the tile set-up at once
     //  * tid < 27: source piece (neighbour column k = tid/3, z piece tid%3)
@@ -570,9 +581,8 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
             d[0] = (th.x - sh.x) + (tl.x - sl.x);
             d[1] = (th.y - sh.y) + (tl.y - sl.y);
             d[2] = (th.z - sh.z) + (tl.z - sl.z);
-            ps[0] = sh.w;
-            if (C::NPL > 1) ps[1] = sl.w;
-            for (int c = 2; c < C::NPL; ++c) ps[c] = S.sp[c - 2][q];
+            ps[0] = sl.w;
+            for (int c = 1; c < C::NPL; ++c) ps[c] = S.sp[c - 1][q];
             if constexpr (C::NTP > 0) {
                 pt[0] = th.w;
                 pt[1] = tl.w;
@@ -661,44 +671,33 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         // ---- stage sources of this chunk: flat over the concatenated pieces,
         // all loads of a thread issued before any of its LDS stores
         stage_chunk<C>(S, P, dense, c0, clen, za, n2, tid);
-        if (tid < C::SCAN) S.sc[clen + tid] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
+        if (tid < C::SCAN) S.sc[clen + tid] = make_float4(0.0f, 0.0f, 0.0f, 1e30f);  // never queued
         __syncthreads();
 
         // ---- scan: one target at a time over its contiguous stencil range.
-        // Lane i of wavefront w holds target w + NW*i (coordinates, range) in
-        // registers; the first 128 sources of the next target are read from
-        // LDS while the current one is tested.
-        float vtx = 0.f, vty = 0.f, vtz = 0.f;
+        // Lane i of wavefront w holds target w + NW*i in registers: -2 t, the
+        // threshold rc2s - |t|^2 and the range [a, b).
+        float ux = 0.f, uy = 0.f, uz = 0.f, uthr = -1.f;
         int va = 0, vb = 0;
         const int nmine = ntgt > w ? min(C::TPW, (ntgt - w + C::NW - 1) / C::NW) : 0;
         if (lane < nmine) {
             const int t = w + C::NW * lane;
             const float4 tt = S.tc[t];
-            vtx = tt.x;
-            vty = tt.y;
-            vtz = tt.z;
+            ux = -2.0f * tt.x;
+            uy = -2.0f * tt.y;
+            uz = -2.0f * tt.z;
+            uthr = rc2s - (tt.x * tt.x + tt.y * tt.y + tt.z * tt.z);
             va = dense ? 0 : S.ta[t];
             vb = dense ? clen : S.tb[t];
         }
-        float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0;
-        if (nmine > 0) {
-            const int a0 = __builtin_amdgcn_readlane(va, 0);
-            n0 = S.sc[a0 + lane];
-            n1 = S.sc[a0 + WAVE + lane];
-        }
         for (int i = 0; i < nmine; ++i) {
             const int t = w + C::NW * i;
-            const float tx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vtx), i));
-            const float ty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vty), i));
-            const float tz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vtz), i));
+            const float tx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ux), i));
+            const float ty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(uy), i));
+            const float tz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(uz), i));
+            const float thr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(uthr), i));
             const int a = __builtin_amdgcn_readlane(va, i);
             const int b = __builtin_amdgcn_readlane(vb, i);
-            const float4 c0 = n0, c1 = n1;
-            if (i + 1 < nmine) {
-                const int an = __builtin_amdgcn_readlane(va, i + 1);
-                n0 = S.sc[an + lane];
-                n1 = S.sc[an + WAVE + lane];
-            }
             const uint32_t tag = (uint32_t)t << 16;
             const bool mine = (lane / C::LPT) == i;
             if (mine) rs = qn;
@@ -711,28 +710,24 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
                         flush();
                     }
                 }
-                float4 s0 = c0, s1 = c1;
-                if (p != a) {
-                    s0 = S.sc[p + lane];
-                    s1 = S.sc[p + WAVE + lane];
-                }
-                const float ax = s0.x - tx, ay = s0.y - ty, az = s0.z - tz;
-                const float bx = s1.x - tx, by = s1.y - ty, bz = s1.z - tz;
-                const float ra = ax * ax + ay * ay + az * az;
-                const float rb = bx * bx + by * by + bz * bz;
-                const bool ha = ra < rc2s, hb = rb < rc2s;
+                const float4 s0 = S.sc[p + lane], s1 = S.sc[p + WAVE + lane];
+                const float ra = fmaf(s0.x, tx, fmaf(s0.y, ty, fmaf(s0.z, tz, s0.w)));
+                const float rb = fmaf(s1.x, tx, fmaf(s1.y, ty, fmaf(s1.z, tz, s1.w)));
+                const bool ha = ra < thr, hb = rb < thr;
                 const uint64_t ma = __ballot(ha);
                 const uint64_t mb = __ballot(hb);
-                const int na = __popcll(ma);
-                // queue slot = running count + rank among the hits of this half;
+                // hits of the first half go to queue[qn ..), those of the second
+                // after them, each at its rank among the hits of its half;
                 // entry = (t << 16) | source slot
+                const int na = __popcll(ma), nb = __popcll(mb);
+                uint32_t *qa = queue + qn;
+                uint32_t *qb = qa + na;
                 const uint32_t ea = (tag | (uint32_t)p) + (uint32_t)lane;
-                if (ha) queue[__builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)ma, (uint32_t)qn))] = ea;
-                if (hb) queue[__builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mb, (uint32_t)(qn + na)))] =
-                    ea + (uint32_t)WAVE;
-                qn = __builtin_amdgcn_readfirstlane(qn + na + __popcll(mb));
+                if (ha) qa[__builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u))] = ea;
+                if (hb)
+                    qb[__builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u))] =
+                        ea + (uint32_t)WAVE;
+                qn += na + nb;
             }
             if (dense) {
                 if (qn > 0) flush_one(i * C::LPT);
