@@ -54,15 +54,16 @@ struct Cfg {
     static constexpr int NC = BWD ? MIN + 3 : MOUT;      // sums per target
     static constexpr bool F32 = sizeof(FP) == 4;
     static constexpr int SCAN = 2 * WAVE;                // sources tested per scan step
-    static constexpr int CAPP = TILE_CAP + SCAN;         // staged slots incl. sentinels
-    static constexpr int QCAP = 256;                     // queue entries per wavefront
+    static constexpr int CAPP = TILE_CAP + SCAN;         // scan slots incl. sentinels
+    // queue entries per wavefront: fewer than WAVE wait between scan steps,
+    // and one step adds at most SCAN
+    static constexpr int QCAP = WAVE + SCAN;
     // LDS bytes of the staged sources and of one wavefront's queue; tiles use
     // TILE_NW wavefronts unless that would not fit in the 160 KiB of a CU
-    static constexpr int STAGE_B = CAPP * (16 + (F32 ? 16 + 4 * (NPL - 1) : 8 * (3 + NPL)));
-    static constexpr int WAVE_B = QCAP * (4 + NC * (int)sizeof(FP));
+    static constexpr int STAGE_B = CAPP * 16 + TILE_CAP * (F32 ? 16 + 4 * (NPL - 1) : 8 * (3 + NPL));
+    static constexpr int WAVE_B = QCAP * 4;
     static constexpr int NW = (STAGE_B + TILE_NW * WAVE_B <= 150 * 1024) ? TILE_NW : 2;
     static constexpr int TPW = TILE_T / NW;              // targets per wavefront
-    static constexpr int LPT = WAVE / TPW;               // lanes summing one target's run
 };
 
 struct ResParams {
@@ -86,15 +87,15 @@ struct Seg {
 
 template <class C>
 struct Smem {
-    static constexpr int S32 = C::F32 ? C::CAPP : 1;
-    static constexpr int S64 = C::F32 ? 1 : C::CAPP;
+    static constexpr int S32 = C::F32 ? TILE_CAP : 1;
+    static constexpr int S64 = C::F32 ? 1 : TILE_CAP;
     static constexpr int NX32 = (C::F32 && C::NPL > 1) ? C::NPL - 1 : 1;
     static constexpr int NX64 = C::F32 ? 1 : C::NPL;
     static constexpr int TX32 = (C::F32 && C::NTP > 2) ? C::NTP - 2 : 1;
     static constexpr int TX64 = (!C::F32 && C::NTP > 0) ? C::NTP : 1;
     float4 sc[C::CAPP];          // FP32 (hi) coords s and |s|^2 (scan test)
     float4 sl[S32];              // FP32 lo coords, w = payload 0 (FP32 path)
-    float sp[NX32][(C::F32 && C::NPL > 1) ? C::CAPP : 1];  // FP32 payload 1..
+    float sp[NX32][(C::F32 && C::NPL > 1) ? TILE_CAP : 1];  // FP32 payload 1..
     double sx[S64], sy[S64], sz[S64];
     double spd[NX64][S64];
     float4 tc[TILE_T];           // target hi coords, w = target payload 0 (FP32 path)
@@ -106,10 +107,13 @@ struct Smem {
     int tperm[TILE_T];           // original index of each target
     union {
         uint32_t queue[C::NW][C::QCAP];   // pair queue of each wavefront (scan / pair step)
-        int dgs[(TILE_ZMAX + 2) * 9];     // box start of each (slab, column) (set-up only)
+        struct {
+            int dgs[(TILE_ZMAX + 2) * 9];   // box start of each (slab, column)
+            int dtab[(TILE_ZMAX + 2) * 9];  // box counts, then slab-major offset - box start
+        } st;                               // set-up and staging only
     };
-    typename std::conditional<C::F32, float, double>::type contrib[C::NW][C::NC][C::QCAP];
-    int dtab[(TILE_ZMAX + 2) * 9];  // box counts, then slab-major offset - box start
+    typename std::conditional<C::F32, float, double>::type tacc[C::NC][TILE_T];  // per-target sums
+    float tcmp[C::F32 ? C::NC : 1][C::F32 ? TILE_T : 1];  // their Kahan compensation (FP32 path)
     int soff[TILE_ZMAX + 4];        // slab offsets in the staged order
     int ccol[9];
     int qtot;
@@ -367,7 +371,7 @@ __device__ inline void stage_chunk(Smem<C> &S, const ResParams &P, bool dense, i
             if (!dense) {
                 const Seg &g = S.seg[sgi[u]];
                 const int slab = (sk[u] - S.ccol[g.k] * n2) + g.vshift - za;
-                dest = S.dtab[slab * 9 + g.k] + (int)jj[u];
+                dest = S.st.dtab[slab * 9 + g.k] + (int)jj[u];
             }
             store_source<C>(S, dest, X[u], Y[u], Z[u], pl[u]);
         }
@@ -402,6 +406,75 @@ __device__ inline void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
+}
+
+// ---- cross-lane sums with DPP moves (GFX9 data-parallel primitives).
+// DPP_* are dpp_ctrl codes; a lane whose source lane is outside its row (or
+// whose row is masked out) keeps the `old` operand.
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_WAVE_SHL1 = 0x130, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
+
+template <int CTRL, int RM>
+__device__ inline int dpp_int(int x, int old)
+{
+    return __builtin_amdgcn_update_dpp(old, x, CTRL, RM, 0xf, false);
+}
+template <int CTRL, int RM>
+__device__ inline float dpp_val(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, RM, 0xf, false));
+}
+template <int CTRL, int RM>
+__device__ inline double dpp_val(double x)
+{
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, RM, 0xf, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, RM, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// One step of a segmented inclusive sum over the 64 lanes: add the value of
+// the source lane selected by CTRL / RM when it carries the same tag (tags
+// are >= 1, so neither a kept `old` of -1 nor a zero ever matches).
+template <int CTRL, int RM, int NC, typename T>
+__device__ inline void seg_step(int tag, T *v)
+{
+    const bool same = dpp_int<CTRL, RM>(tag, -1) == tag;
+    for (int c = 0; c < NC; ++c) {
+        const T x = dpp_val<CTRL, RM>(v[c]);
+        v[c] += same ? x : (T)0;
+    }
+}
+
+// Segmented inclusive sum: lanes hold values whose tags are non-decreasing
+// along the lanes; afterwards the last lane of each run of equal tags holds
+// the run's total.  Shifts by 1, 2, 4, 8 within each row of 16 lanes, then
+// the row totals are carried into rows 1 and 3 (lane 15, 47) and into rows 2
+// and 3 (lane 31), the usual wavefront scan pattern.
+template <int NC, typename T>
+__device__ inline void seg_sum(int tag, T *v)
+{
+    seg_step<DPP_ROW_SHR1, 0xf, NC>(tag, v);
+    seg_step<DPP_ROW_SHR2, 0xf, NC>(tag, v);
+    seg_step<DPP_ROW_SHR4, 0xf, NC>(tag, v);
+    seg_step<DPP_ROW_SHR8, 0xf, NC>(tag, v);
+    seg_step<DPP_ROW_BCAST15, 0xa, NC>(tag, v);
+    seg_step<DPP_ROW_BCAST31, 0xc, NC>(tag, v);
+}
+
+// plain wavefront sum by the same pattern; lane 63 holds the total
+template <int NC, typename T>
+__device__ inline void wave_sum(T *v)
+{
+    for (int c = 0; c < NC; ++c) {
+        T x = v[c];
+        x += dpp_val<DPP_ROW_SHR1, 0xf>(x);
+        x += dpp_val<DPP_ROW_SHR2, 0xf>(x);
+        x += dpp_val<DPP_ROW_SHR4, 0xf>(x);
+        x += dpp_val<DPP_ROW_SHR8, 0xf>(x);
+        x += dpp_val<DPP_ROW_BCAST15, 0xa>(x);
+        x += dpp_val<DPP_ROW_BCAST31, 0xc>(x);
+        v[c] = x;
+    }
 }
 
 template <int KERN, typename FP, bool BWD>
@@ -500,9 +573,13 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
                 gs = P.bs[bb];
                 cnt = P.bs[bb + 1] - gs;
             }
-            S.dtab[idx] = cnt;
-            S.dgs[idx] = gs;
+            S.st.dtab[idx] = cnt;
+            S.st.dgs[idx] = gs;
         }
+    }
+    for (int idx = tid; idx < C::NC * TILE_T; idx += C::NW * WAVE) {
+        (&S.tacc[0][0])[idx] = 0;
+        if constexpr (C::F32) (&S.tcmp[0][0])[idx] = 0.0f;
     }
     int my_zt = 0;
     if (tid < TILE_T && tstart + tid < P.N) {  // all 64 slots; ones past ntgt are never used
@@ -542,11 +619,11 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         int carry = 0;
         for (int base = 0; base < M; base += WAVE) {
             const int idx = base + lane;
-            const int cnt = idx < M ? S.dtab[idx] : 0;
+            const int cnt = idx < M ? S.st.dtab[idx] : 0;
             const int incl = wave_incl_scan(cnt);
             if (idx < M) {
                 const int off = carry + incl - cnt;
-                S.dtab[idx] = off - S.dgs[idx];
+                S.st.dtab[idx] = off - S.st.dgs[idx];
                 if (idx % 9 == 0) S.soff[idx / 9] = off;
             }
             carry += __shfl(incl, 63, 64);
@@ -559,21 +636,13 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         S.tb[tid] = S.soff[my_zt - z0 + 3];
     }
 
-    // target t = w + NW*i belongs to lanes [LPT*i, LPT*i + LPT) of wavefront w;
-    // those lanes sum interleaved parts of its pair run
-    T acc[C::NC], cmp[C::NC];
-    for (int c = 0; c < C::NC; ++c) {
-        acc[c] = 0;
-        cmp[c] = 0;
-    }
-    int qn = 0;
-    int rs = 0, re = 0;
+    int qn = 0;  // entries in this wavefront's queue (uniform)
     uint32_t *queue = S.queue[w];
 
-    // pair step for queue entry i: contribution v[NC] (zero when the exact
-    // test rejects the pair: self / coincident, or outside the cutoff)
-    auto pair_value = [&](int i, T *v) {
-        const uint32_t e = queue[i];
+    // pair step for queue entry e = (t << 16) | source slot: contribution
+    // v[NC] (zero when the exact test rejects the pair: self / coincident, or
+    // outside the cutoff)
+    auto pair_value = [&](uint32_t e, T *v) {
         const int t = (int)(e >> 16), q = (int)(e & 0xffffu);
         T d[3], ps[C::NPL], pt[C::NTP > 0 ? C::NTP : 1];
         if constexpr (C::F32) {
@@ -605,64 +674,59 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         for (int c = 0; c < C::NC; ++c) v[c] = ok ? v[c] : (T)0;
     };
 
-    auto kahan_add = [&](const T *x) {
+    // add x[NC] to target t's sums (Kahan-compensated in the FP32 path)
+    auto add_target = [&](int t, const T *x) {
         for (int c = 0; c < C::NC; ++c) {
             if constexpr (C::F32) {
-                const T y = x[c] - cmp[c];
-                const T s2 = acc[c] + y;
-                cmp[c] = (s2 - acc[c]) - y;
-                acc[c] = s2;
+                const float acc = S.tacc[c][t];
+                const float y = x[c] - S.tcmp[c][t];
+                const float s2 = acc + y;
+                S.tcmp[c][t] = (s2 - acc) - y;
+                S.tacc[c][t] = s2;
             } else {
-                acc[c] += x[c];
+                S.tacc[c][t] += x[c];
             }
         }
     };
 
-    // Multi-box tiles: the queue holds the runs of several targets; pair values
-    // go to the LDS contribution array and the LPT lanes of each target sum
-    // interleaved parts of its run in a fixed order.
-    auto flush = [&]() {
-        wave_sync();
-        for (int base = 0; base < qn; base += WAVE) {
-            const int i = base + lane;
-            if (i < qn) {
-                T v[C::NC];
-                pair_value(i, v);
-                for (int c = 0; c < C::NC; ++c) S.contrib[w][c][i] = v[c];
-            }
+    // Pair step over queue entries [base, base + cnt), cnt <= 64, one per lane.
+    //  * multi-box tiles: a batch holds the runs of several targets in order;
+    //    a segmented sum gives each run's total to its last lane, which adds
+    //    it to the target's sums;
+    //  * dense tiles: a batch holds one target's pairs; each lane keeps a
+    //    running sum part[] that is reduced when the target's range is done.
+    T part[C::NC];
+    for (int c = 0; c < C::NC; ++c) part[c] = 0;
+    auto batch = [&](int base, int cnt) {
+        T v[C::NC];
+        for (int c = 0; c < C::NC; ++c) v[c] = 0;
+        int tag = 127;  // lanes past cnt: a run of their own, never added
+        if (lane < cnt) {
+            const uint32_t e = queue[base + lane];
+            pair_value(e, v);
+            tag = (int)(e >> 16) + 1;
         }
-        wave_sync();
-        for (int i = rs + (lane % C::LPT); i < re; i += C::LPT) {
-            T x[C::NC];
-            for (int c = 0; c < C::NC; ++c) x[c] = S.contrib[w][c][i];
-            kahan_add(x);
+        if (dense) {
+            for (int c = 0; c < C::NC; ++c) part[c] += v[c];
+        } else {
+            seg_sum<C::NC>(tag, v);
+            const int tnext = dpp_int<DPP_WAVE_SHL1, 0xf>(tag, -1);
+            if (lane < cnt && tnext != tag) add_target(tag - 1, v);
         }
-        wave_sync();
-        qn = 0;
-        rs = 0;
-        re = 0;
     };
 
-    // Dense tiles: every queue epoch holds one target's run (the scan flushes
-    // at each target change), so each lane sums its pair values in registers
-    // and one butterfly gives the epoch's total to the target's lane.
-    auto flush_one = [&](int owner) {
+    // evaluate every full batch of the queue, keep the rest (< 64 entries)
+    auto drain = [&]() {
         wave_sync();
-        T part[C::NC];
-        for (int c = 0; c < C::NC; ++c) part[c] = 0;
-        for (int base = 0; base < qn; base += WAVE) {
-            const int i = base + lane;
-            if (i < qn) {
-                T v[C::NC];
-                pair_value(i, v);
-                for (int c = 0; c < C::NC; ++c) part[c] += v[c];
-            }
-        }
-        for (int off = WAVE / 2; off >= 1; off >>= 1)
-            for (int c = 0; c < C::NC; ++c) part[c] += __shfl_xor(part[c], off, WAVE);
-        if (lane == owner) kahan_add(part);
+        const int nfull = qn / WAVE;
+        for (int k = 0; k < nfull; ++k) batch(k * WAVE, WAVE);
+        const int left = qn - nfull * WAVE;
+        uint32_t e = 0;
+        if (lane < left) e = queue[nfull * WAVE + lane];
         wave_sync();
-        qn = 0;
+        if (lane < left) queue[lane] = e;
+        wave_sync();
+        qn = left;
     };
 
     const int qtot = dense ? S.qtot : S.soff[nslab];
@@ -699,17 +763,7 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
             const int a = __builtin_amdgcn_readlane(va, i);
             const int b = __builtin_amdgcn_readlane(vb, i);
             const uint32_t tag = (uint32_t)t << 16;
-            const bool mine = (lane / C::LPT) == i;
-            if (mine) rs = qn;
             for (int p = a; p < b; p += C::SCAN) {
-                if (qn + C::SCAN > C::QCAP) {
-                    if (dense) {
-                        flush_one(i * C::LPT);
-                    } else {
-                        if (mine) re = qn;
-                        flush();
-                    }
-                }
                 const float4 s0 = S.sc[p + lane], s1 = S.sc[p + WAVE + lane];
                 const float ra = fmaf(s0.x, tx, fmaf(s0.y, ty, fmaf(s0.z, tz, s0.w)));
                 const float rb = fmaf(s1.x, tx, fmaf(s1.y, ty, fmaf(s1.z, tz, s1.w)));
@@ -728,29 +782,35 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
                     qb[__builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u))] =
                         ea + (uint32_t)WAVE;
                 qn += na + nb;
+                if (qn >= WAVE) drain();
             }
             if (dense) {
-                if (qn > 0) flush_one(i * C::LPT);
-            } else if (mine) {
-                re = qn;
+                // the rest of this target's pairs, then its total
+                wave_sync();
+                if (qn > 0) batch(0, qn);
+                qn = 0;
+                wave_sum<C::NC>(part);
+                if (lane == WAVE - 1) add_target(t, part);
+                for (int c = 0; c < C::NC; ++c) part[c] = 0;
+                wave_sync();
             }
         }
-        if (!dense) flush();
+        if (!dense && qn > 0) {
+            wave_sync();
+            batch(0, qn);
+            qn = 0;
+        }
         __syncthreads();
         if (!dense) break;
     }
 
-    // ---- combine the LPT partial sums of each target in FP64, write back in
-    // the original order
-    const int tmine = w + C::NW * (lane / C::LPT);
-    double res[C::NC];
-    for (int c = 0; c < C::NC; ++c) {
-        double v = C::F32 ? (double)acc[c] - (double)cmp[c] : (double)acc[c];
-        for (int off = 1; off < C::LPT; off <<= 1) v += __shfl_xor(v, off, WAVE);
-        res[c] = v;
-    }
-    if ((lane % C::LPT) == 0 && tmine < ntgt) {
-        const int64_t orig = S.tperm[tmine];
+    // ---- each target's sums (FP32 sum minus its compensation, in FP64),
+    // written back in the original order
+    if (tid < ntgt) {
+        const int64_t orig = S.tperm[tid];
+        double res[C::NC];
+        for (int c = 0; c < C::NC; ++c)
+            res[c] = C::F32 ? (double)S.tacc[c][tid] - (double)S.tcmp[c][tid] : (double)S.tacc[c][tid];
         if constexpr (BWD) {
             for (int c = 0; c < C::MIN; ++c) P.out0[orig * C::MIN + c] = res[c];
             for (int c = 0; c < 3; ++c) P.out1[orig * 3 + c] = res[C::MIN + c];
