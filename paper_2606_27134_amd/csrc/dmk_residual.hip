@@ -91,20 +91,19 @@ struct Smem {
     static constexpr int S64 = C::F32 ? 1 : TILE_CAP;
     static constexpr int NX32 = (C::F32 && C::NPL > 1) ? C::NPL - 1 : 1;
     static constexpr int NX64 = C::F32 ? 1 : C::NPL;
-    static constexpr int TX32 = (C::F32 && C::NTP > 2) ? C::NTP - 2 : 1;
+    static constexpr int TX32 = (C::F32 && C::NTP > 1) ? C::NTP - 1 : 1;
     static constexpr int TX64 = (!C::F32 && C::NTP > 0) ? C::NTP : 1;
     float4 sc[C::CAPP];          // FP32 (hi) coords s and |s|^2 (scan test)
     float4 sl[S32];              // FP32 lo coords, w = payload 0 (FP32 path)
     float sp[NX32][(C::F32 && C::NPL > 1) ? TILE_CAP : 1];  // FP32 payload 1..
     double sx[S64], sy[S64], sz[S64];
     double spd[NX64][S64];
-    float4 tc[TILE_T];           // target hi coords, w = target payload 0 (FP32 path)
-    float4 tl[C::F32 ? TILE_T : 1];
-    float tp[TX32][(C::F32 && C::NTP > 2) ? TILE_T : 1];
+    float4 tc[TILE_T];           // target (hi) coords t, w = scan threshold (rc2s - |t|^2) / 2
+    float4 tl[C::F32 ? TILE_T : 1];  // FP32 lo coords, w = target payload 0
+    float tp[TX32][(C::F32 && C::NTP > 1) ? TILE_T : 1];  // FP32 target payload 1..
     double tx[C::F32 ? 1 : TILE_T], ty[C::F32 ? 1 : TILE_T], tz[C::F32 ? 1 : TILE_T];
     double tpd[TX64][(!C::F32 && C::NTP > 0) ? TILE_T : 1];
-    int ta[TILE_T], tb[TILE_T];  // stencil range of each target in the staged order
-    int tperm[TILE_T];           // original index of each target
+    int2 trange[TILE_T];         // stencil range of each target in the staged order
     union {
         uint32_t queue[C::NW][C::QCAP];   // pair queue of each wavefront (scan / pair step)
         struct {
@@ -312,12 +311,12 @@ __device__ inline void store_source(Smem<C> &S, int dest, double X, double Y, do
     if constexpr (C::F32) {
         const float hx = (float)X, hy = (float)Y, hz = (float)Z;
         const float lx = (float)(X - (double)hx), ly = (float)(Y - (double)hy), lz = (float)(Z - (double)hz);
-        S.sc[dest] = make_float4(hx, hy, hz, hx * hx + hy * hy + hz * hz);
+        S.sc[dest] = make_float4(hx, hy, hz, 0.5f * (hx * hx + hy * hy + hz * hz));
         S.sl[dest] = make_float4(lx, ly, lz, (float)pl[0]);
         for (int c = 1; c < C::NPL; ++c) S.sp[c - 1][dest] = (float)pl[c];
     } else {
         const float fx = (float)X, fy = (float)Y, fz = (float)Z;
-        S.sc[dest] = make_float4(fx, fy, fz, fx * fx + fy * fy + fz * fz);
+        S.sc[dest] = make_float4(fx, fy, fz, 0.5f * (fx * fx + fy * fy + fz * fz));
         S.sx[dest] = X;
         S.sy[dest] = Y;
         S.sz[dest] = Z;
@@ -409,56 +408,71 @@ __device__ inline void wave_sync()
 }
 
 // ---- cross-lane sums with DPP moves (GFX9 data-parallel primitives).
-// DPP_* are dpp_ctrl codes; a lane whose source lane is outside its row (or
-// whose row is masked out) keeps the `old` operand.
-constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+// DPP_* are dpp_ctrl codes.  With bound_ctrl set, a lane whose source lane
+// lies outside its row (or the wavefront) reads 0; a lane of a row masked
+// out by row_mask is not written and keeps the `old` operand.
+constexpr int DPP_ROW_SHL = 0x100, DPP_ROW_SHR = 0x110;  // + shift 1..15
 constexpr int DPP_WAVE_SHL1 = 0x130, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
 
 template <int CTRL, int RM>
 __device__ inline int dpp_int(int x, int old)
 {
-    return __builtin_amdgcn_update_dpp(old, x, CTRL, RM, 0xf, false);
+    return __builtin_amdgcn_update_dpp(old, x, CTRL, RM, 0xf, true);
 }
 template <int CTRL, int RM>
 __device__ inline float dpp_val(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, RM, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, RM, 0xf, true));
 }
 template <int CTRL, int RM>
 __device__ inline double dpp_val(double x)
 {
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, RM, 0xf, false);
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, RM, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, RM, 0xf, true);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, RM, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 
-// One step of a segmented inclusive sum over the 64 lanes: add the value of
-// the source lane selected by CTRL / RM when it carries the same tag (tags
-// are >= 1, so neither a kept `old` of -1 nor a zero ever matches).
-template <int CTRL, int RM, int NC, typename T>
-__device__ inline void seg_step(int tag, T *v)
+// Segmented inclusive sum over the 64 lanes.  Lanes hold values v[NC] whose
+// tags (>= 1) are non-decreasing along the lanes; afterwards the last lane
+// of each run of equal tags holds the run's total.  Shifts by 1, 2, 4, 8
+// within each row of 16 lanes, then the row totals are carried into rows 1
+// and 3 (from lanes 15, 47) and into rows 2 and 3 (from lane 31), the usual
+// wavefront scan pattern.  In a shift step lane l passes its partial sum to
+// lane l + s when that lane carries the same tag (tested at the sender, as
+// the tags are sorted); in a carry step the receiver tests the sender's tag.
+// Returns whether lane l is the last of its run.
+template <int S, int NC, typename T>
+__device__ inline bool seg_shift(int tag, T *v)
 {
-    const bool same = dpp_int<CTRL, RM>(tag, -1) == tag;
+    // tag of lane l + S (0 past the end of the row, or of the wavefront for
+    // S = 1, so the result also marks the last lane of each run)
+    const int tn = dpp_int<S == 1 ? DPP_WAVE_SHL1 : DPP_ROW_SHL + S, 0xf>(tag, 0);
+    const bool pass = tn == tag;
+    for (int c = 0; c < NC; ++c) {
+        const T w = pass ? v[c] : (T)0;
+        v[c] += dpp_val<DPP_ROW_SHR + S, 0xf>(w);
+    }
+    return !pass;
+}
+template <int CTRL, int RM, int NC, typename T>
+__device__ inline void seg_carry(int tag, T *v)
+{
+    const bool same = dpp_int<CTRL, RM>(tag, 0) == tag;
     for (int c = 0; c < NC; ++c) {
         const T x = dpp_val<CTRL, RM>(v[c]);
         v[c] += same ? x : (T)0;
     }
 }
-
-// Segmented inclusive sum: lanes hold values whose tags are non-decreasing
-// along the lanes; afterwards the last lane of each run of equal tags holds
-// the run's total.  Shifts by 1, 2, 4, 8 within each row of 16 lanes, then
-// the row totals are carried into rows 1 and 3 (lane 15, 47) and into rows 2
-// and 3 (lane 31), the usual wavefront scan pattern.
 template <int NC, typename T>
-__device__ inline void seg_sum(int tag, T *v)
+__device__ inline bool seg_sum(int tag, T *v)
 {
-    seg_step<DPP_ROW_SHR1, 0xf, NC>(tag, v);
-    seg_step<DPP_ROW_SHR2, 0xf, NC>(tag, v);
-    seg_step<DPP_ROW_SHR4, 0xf, NC>(tag, v);
-    seg_step<DPP_ROW_SHR8, 0xf, NC>(tag, v);
-    seg_step<DPP_ROW_BCAST15, 0xa, NC>(tag, v);
-    seg_step<DPP_ROW_BCAST31, 0xc, NC>(tag, v);
+    const bool last = seg_shift<1, NC>(tag, v);
+    seg_shift<2, NC>(tag, v);
+    seg_shift<4, NC>(tag, v);
+    seg_shift<8, NC>(tag, v);
+    seg_carry<DPP_ROW_BCAST15, 0xa, NC>(tag, v);
+    seg_carry<DPP_ROW_BCAST31, 0xc, NC>(tag, v);
+    return last;
 }
 
 // plain wavefront sum by the same pattern; lane 63 holds the total
@@ -467,10 +481,10 @@ __device__ inline void wave_sum(T *v)
 {
     for (int c = 0; c < NC; ++c) {
         T x = v[c];
-        x += dpp_val<DPP_ROW_SHR1, 0xf>(x);
-        x += dpp_val<DPP_ROW_SHR2, 0xf>(x);
-        x += dpp_val<DPP_ROW_SHR4, 0xf>(x);
-        x += dpp_val<DPP_ROW_SHR8, 0xf>(x);
+        x += dpp_val<DPP_ROW_SHR + 1, 0xf>(x);
+        x += dpp_val<DPP_ROW_SHR + 2, 0xf>(x);
+        x += dpp_val<DPP_ROW_SHR + 4, 0xf>(x);
+        x += dpp_val<DPP_ROW_SHR + 8, 0xf>(x);
         x += dpp_val<DPP_ROW_BCAST15, 0xa>(x);
         x += dpp_val<DPP_ROW_BCAST31, 0xc>(x);
         v[c] = x;
@@ -510,10 +524,11 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
     const T isig2 = isig * isig;
     const T rc2 = (T)(P.rc * P.rc);
     // Scan test (FP32, conservative): source s is queued for target t when
-    // |s|^2 - 2 s.t < rc2s - |t|^2.  The rounding error of that expansion and
-    // of the FP32 coordinates is a few ulp of (|s| + |t|)^2 <= 4 R^2, with R
-    // the largest coordinate norm in the tile frame; the margin exceeds it
-    // twentyfold.  The pair step then applies the exact test.
+    // |s|^2 - 2 s.t < rc2s - |t|^2 (both sides halved in the code).  The
+    // rounding error of that expansion and of the FP32 coordinates is a few
+    // ulp of (|s| + |t|)^2 <= 4 R^2, with R the largest coordinate norm in
+    // the tile frame; the margin exceeds it twentyfold.  The pair step then
+    // applies the exact test.
     const double ext_z = (z1 - z0) * 0.5 + 1.5;
     const double R2 = 2.25 * (P.h[0] * P.h[0] + P.h[1] * P.h[1]) + ext_z * ext_z * P.h[2] * P.h[2];
     const float rc2s = (float)(P.rc * P.rc * (1.0 + 4e-4) + 4.2e-5 * R2);
@@ -581,26 +596,24 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         (&S.tacc[0][0])[idx] = 0;
         if constexpr (C::F32) (&S.tcmp[0][0])[idx] = 0.0f;
     }
-    int my_zt = 0;
+    int my_zt = 0, my_orig = 0;
     if (tid < TILE_T && tstart + tid < P.N) {  // all 64 slots; ones past ntgt are never used
         const int64_t j = tstart + tid;
         const double X = P.ys[j] - crx, Y = P.ys[P.N + j] - cry, Z = P.ys[2 * P.N + j] - crz;
         const float hx = (float)X, hy = (float)Y, hz = (float)Z;
+        S.tc[tid] = make_float4(hx, hy, hz, 0.5f * (rc2s - (hx * hx + hy * hy + hz * hz)));
         if constexpr (C::F32) {
             const float t0 = (C::NTP > 0) ? (float)P.pl[j] : 0.0f;
-            const float t1 = (C::NTP > 1) ? (float)P.pl[P.N + j] : 0.0f;
-            S.tc[tid] = make_float4(hx, hy, hz, t0);
-            S.tl[tid] = make_float4((float)(X - (double)hx), (float)(Y - (double)hy), (float)(Z - (double)hz), t1);
-            for (int c = 2; c < C::NTP; ++c) S.tp[c - 2][tid] = (float)P.pl[c * P.N + j];
+            S.tl[tid] = make_float4((float)(X - (double)hx), (float)(Y - (double)hy), (float)(Z - (double)hz), t0);
+            for (int c = 1; c < C::NTP; ++c) S.tp[c - 1][tid] = (float)P.pl[c * P.N + j];
         } else {
-            S.tc[tid] = make_float4(hx, hy, hz, 0.0f);
             S.tx[tid] = X;
             S.ty[tid] = Y;
             S.tz[tid] = Z;
             for (int c = 0; c < C::NTP; ++c) S.tpd[c][tid] = P.pl[c * P.N + j];
         }
         if (!dense) my_zt = P.skey[j] - (int)colb;
-        S.tperm[tid] = P.perm[j];
+        my_orig = P.perm[j];
     }
     __syncthreads();
 
@@ -631,10 +644,7 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         if (lane == 0) S.soff[nslab] = carry;
     }
     __syncthreads();
-    if (!dense && tid < ntgt) {
-        S.ta[tid] = S.soff[my_zt - z0];
-        S.tb[tid] = S.soff[my_zt - z0 + 3];
-    }
+    if (!dense && tid < ntgt) S.trange[tid] = make_int2(S.soff[my_zt - z0], S.soff[my_zt - z0 + 3]);
 
     int qn = 0;  // entries in this wavefront's queue (uniform)
     uint32_t *queue = S.queue[w];
@@ -653,9 +663,8 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
             ps[0] = sl.w;
             for (int c = 1; c < C::NPL; ++c) ps[c] = S.sp[c - 1][q];
             if constexpr (C::NTP > 0) {
-                pt[0] = th.w;
-                pt[1] = tl.w;
-                for (int c = 2; c < C::NTP; ++c) pt[c] = S.tp[c - 2][t];
+                pt[0] = tl.w;
+                for (int c = 1; c < C::NTP; ++c) pt[c] = S.tp[c - 1][t];
             }
         } else {
             d[0] = S.tx[t] - S.sx[q];
@@ -709,9 +718,8 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         if (dense) {
             for (int c = 0; c < C::NC; ++c) part[c] += v[c];
         } else {
-            seg_sum<C::NC>(tag, v);
-            const int tnext = dpp_int<DPP_WAVE_SHL1, 0xf>(tag, -1);
-            if (lane < cnt && tnext != tag) add_target(tag - 1, v);
+            const bool last = seg_sum<C::NC>(tag, v);
+            if (lane < cnt && last) add_target(tag - 1, v);
         }
     };
 
@@ -738,35 +746,26 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         if (tid < C::SCAN) S.sc[clen + tid] = make_float4(0.0f, 0.0f, 0.0f, 1e30f);  // never queued
         __syncthreads();
 
-        // ---- scan: one target at a time over its contiguous stencil range.
-        // Lane i of wavefront w holds target w + NW*i in registers: -2 t, the
-        // threshold rc2s - |t|^2 and the range [a, b).
-        float ux = 0.f, uy = 0.f, uz = 0.f, uthr = -1.f;
-        int va = 0, vb = 0;
+        // ---- scan: one target at a time over its contiguous stencil range;
+        // wavefront w takes targets w, w + NW, ...  The target's coordinates
+        // and threshold are read from LDS at a uniform address (a broadcast).
         const int nmine = ntgt > w ? min(C::TPW, (ntgt - w + C::NW - 1) / C::NW) : 0;
-        if (lane < nmine) {
-            const int t = w + C::NW * lane;
-            const float4 tt = S.tc[t];
-            ux = -2.0f * tt.x;
-            uy = -2.0f * tt.y;
-            uz = -2.0f * tt.z;
-            uthr = rc2s - (tt.x * tt.x + tt.y * tt.y + tt.z * tt.z);
-            va = dense ? 0 : S.ta[t];
-            vb = dense ? clen : S.tb[t];
-        }
         for (int i = 0; i < nmine; ++i) {
             const int t = w + C::NW * i;
-            const float tx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ux), i));
-            const float ty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(uy), i));
-            const float tz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(uz), i));
-            const float thr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(uthr), i));
-            const int a = __builtin_amdgcn_readlane(va, i);
-            const int b = __builtin_amdgcn_readlane(vb, i);
+            const float4 ts = S.tc[t];
+            const float tx = ts.x, ty = ts.y, tz = ts.z, thr = ts.w;
+            int a = 0, b = clen;
+            if (!dense) {
+                const int2 rg = S.trange[t];
+                a = __builtin_amdgcn_readfirstlane(rg.x);
+                b = __builtin_amdgcn_readfirstlane(rg.y);
+            }
             const uint32_t tag = (uint32_t)t << 16;
             for (int p = a; p < b; p += C::SCAN) {
                 const float4 s0 = S.sc[p + lane], s1 = S.sc[p + WAVE + lane];
-                const float ra = fmaf(s0.x, tx, fmaf(s0.y, ty, fmaf(s0.z, tz, s0.w)));
-                const float rb = fmaf(s1.x, tx, fmaf(s1.y, ty, fmaf(s1.z, tz, s1.w)));
+                // (|s|^2 - 2 s.t) / 2 against (rc2s - |t|^2) / 2
+                const float ra = fmaf(-s0.x, tx, fmaf(-s0.y, ty, fmaf(-s0.z, tz, s0.w)));
+                const float rb = fmaf(-s1.x, tx, fmaf(-s1.y, ty, fmaf(-s1.z, tz, s1.w)));
                 const bool ha = ra < thr, hb = rb < thr;
                 const uint64_t ma = __ballot(ha);
                 const uint64_t mb = __ballot(hb);
@@ -807,7 +806,7 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
     // ---- each target's sums (FP32 sum minus its compensation, in FP64),
     // written back in the original order
     if (tid < ntgt) {
-        const int64_t orig = S.tperm[tid];
+        const int64_t orig = my_orig;
         double res[C::NC];
         for (int c = 0; c < C::NC; ++c)
             res[c] = C::F32 ? (double)S.tacc[c][tid] - (double)S.tcmp[c][tid] : (double)S.tacc[c][tid];
