@@ -47,20 +47,23 @@ struct KDim {
 
 template <int KERN, typename FP, bool BWD>
 struct Cfg {
+    static constexpr int K = KERN;
     static constexpr int MIN = KDim<KERN>::MIN;
     static constexpr int MOUT = KDim<KERN>::MOUT;
     static constexpr int NPL = BWD ? MIN + MOUT : MIN;   // payload per source
     static constexpr int NTP = BWD ? MIN + MOUT : 0;     // payload per target
     static constexpr int NC = BWD ? MIN + 3 : MOUT;      // sums per target
     static constexpr bool F32 = sizeof(FP) == 4;
-    static constexpr int SCAN = 2 * WAVE;                // sources tested per scan step
-    static constexpr int CAPP = TILE_CAP + SCAN;         // scan slots incl. sentinels
-    // queue entries per wavefront: fewer than WAVE wait between scan steps,
-    // and one step adds at most SCAN
-    static constexpr int QCAP = WAVE + SCAN;
+    // A scan step tests 128 sources.  Full batches of the queue are evaluated
+    // after each half of a step, or after the whole step for the FP64 adjoints
+    // of the Stokes-flow kernels, whose long pair code is better inlined at
+    // one call site; fewer than WAVE entries wait in between, so the queue
+    // holds 2 or 3 WAVE entries.
+    static constexpr bool DRAIN_HALF = F32 || !BWD || KERN == 0;
+    static constexpr int QCAP = DRAIN_HALF ? 2 * WAVE : 3 * WAVE;
     // LDS bytes of the staged sources and of one wavefront's queue; tiles use
     // TILE_NW wavefronts unless that would not fit in the 160 KiB of a CU
-    static constexpr int STAGE_B = CAPP * 16 + TILE_CAP * (F32 ? 16 + 4 * (NPL - 1) : 8 * (3 + NPL));
+    static constexpr int STAGE_B = TILE_CAP * (16 + (F32 ? 16 + 4 * (NPL - 1) : 8 * (3 + NPL)));
     static constexpr int WAVE_B = QCAP * 4;
     static constexpr int NW = (STAGE_B + TILE_NW * WAVE_B <= 150 * 1024) ? TILE_NW : 2;
     static constexpr int TPW = TILE_T / NW;              // targets per wavefront
@@ -80,9 +83,11 @@ struct ResParams {
     double *out0, *out1;
 };
 
+// one source piece: a z-range of one neighbour column (piece 0: the image
+// box below the domain, 1: boxes inside, 2: the image box above)
 struct Seg {
-    int gstart, glen, k, vshift, so, pad;
-    double offx, offy, offz;
+    int gstart, glen, so;               // first sorted index, length, offset in the concatenation
+    signed char k, vshift, piece, pad;  // column 0..8, virtual-z shift of an image box
 };
 
 template <class C>
@@ -93,7 +98,7 @@ struct Smem {
     static constexpr int NX64 = C::F32 ? 1 : C::NPL;
     static constexpr int TX32 = (C::F32 && C::NTP > 1) ? C::NTP - 1 : 1;
     static constexpr int TX64 = (!C::F32 && C::NTP > 0) ? C::NTP : 1;
-    float4 sc[C::CAPP];          // FP32 (hi) coords s and |s|^2 (scan test)
+    float4 sc[TILE_CAP];         // FP32 (hi) coords s and |s|^2 / 2 (scan test)
     float4 sl[S32];              // FP32 lo coords, w = payload 0 (FP32 path)
     float sp[NX32][(C::F32 && C::NPL > 1) ? TILE_CAP : 1];  // FP32 payload 1..
     double sx[S64], sy[S64], sz[S64];
@@ -103,12 +108,13 @@ struct Smem {
     float tp[TX32][(C::F32 && C::NTP > 1) ? TILE_T : 1];  // FP32 target payload 1..
     double tx[C::F32 ? 1 : TILE_T], ty[C::F32 ? 1 : TILE_T], tz[C::F32 ? 1 : TILE_T];
     double tpd[TX64][(!C::F32 && C::NTP > 0) ? TILE_T : 1];
-    int2 trange[TILE_T];         // stencil range of each target in the staged order
+    int trange[TILE_T];          // stencil range [a, b) of each target in the staged order: a | b << 16
     union {
         uint32_t queue[C::NW][C::QCAP];   // pair queue of each wavefront (scan / pair step)
         struct {
-            int dgs[(TILE_ZMAX + 2) * 9];   // box start of each (slab, column)
-            int dtab[(TILE_ZMAX + 2) * 9];  // box counts, then slab-major offset - box start
+            // per (slab, column) box: count | (start - start of its piece) << 16,
+            // then slab-major offset - (start - start of its piece)
+            int dtab[(TILE_ZMAX + 2) * 9];
         } st;                               // set-up and staging only
     };
     typename std::conditional<C::F32, float, double>::type tacc[C::NC][TILE_T];  // per-target sums
@@ -118,6 +124,8 @@ struct Smem {
     int qtot;
     int segso[32];                  // piece offsets in the concatenated order (padded)
     Seg seg[27];
+    double2 coff[9];                // tile-frame offset (x, y) of each neighbour column's points
+    double zoff[3];                 // tile-frame z offset of each piece's points
 };
 
 // --------------------------------------------------------------------------
@@ -129,23 +137,29 @@ __device__ inline double erfc_(double x) { return erfc(x); }
 __device__ inline float expneg_(float x) { return __expf(-x); }
 __device__ inline double expneg_(double x) { return exp(-x); }
 
-__device__ inline int wave_incl_scan(int v)
-{
-    const int lane = threadIdx.x & 63;
-    for (int off = 1; off < 64; off <<= 1) {
-        int w = __shfl_up(v, off, 64);
-        if (lane >= off) v += w;
-    }
-    return v;
-}
+
+#define INV4PI 0.079577471545947667884
+#define INV8PI 0.039788735772973833942
+#define INV_SQRT_PI 0.56418958354775628695
+
+// normalisation of each kernel: 1/(4 pi) for Laplace, 1/(8 pi) for the
+// Stokes-flow kernels (the stresslet's 3/(4 pi) is 6 of those).  Every pair
+// term is linear in exactly one source payload (rho_s or G_s), so the
+// constant is applied to the source payloads, in FP64, when they are staged.
+template <int KERN>
+struct KNorm {
+    static constexpr double c = KERN == 0 ? INV4PI : INV8PI;
+};
 
 template <typename T>
 struct Rad {
     T ri, r, t, t2, phi, Phi;
 };
 
+// radial quantities of a pair at squared distance r2 (isig = 1/sigma,
+// kexp = -log2(e)/sigma^2 for the FP32 exponential)
 template <typename T>
-__device__ inline Rad<T> radial(T r2, T isig, T isig2)
+__device__ inline Rad<T> radial(T r2, T isig, T isig2, T kexp)
 {
     Rad<T> R;
     R.ri = rsqrt_(r2);
@@ -155,36 +169,33 @@ __device__ inline Rad<T> radial(T r2, T isig, T isig2)
     if constexpr (sizeof(T) == 4) {
         // one exponential serves both the window phi(t) = e^{-t^2}/sqrt(pi) and
         // Phi(t) = erfc(t) = e^{-t^2} erfcx(t); erfcx from the fitted polynomial
-        const float e = __builtin_amdgcn_exp2f(-R.t2 * 1.4426950408889634f);
+        const float e = __builtin_amdgcn_exp2f(r2 * kexp);
         const float u = __builtin_amdgcn_rcpf(1.0f + ERFCX_F32_SHIFT * R.t);
         float pol = ERFCX_F32_C[ERFCX_F32_DEG];
 #pragma unroll
         for (int k = ERFCX_F32_DEG - 1; k >= 0; --k) pol = pol * u + ERFCX_F32_C[k];
-        R.phi = e * 0.56418958354775628695f;
+        R.phi = e * (float)INV_SQRT_PI;
         R.Phi = e * (u * pol);
     } else {
-        R.phi = expneg_(R.t2) * (T)0.56418958354775628695;  // 1/sqrt(pi)
+        (void)kexp;
+        R.phi = expneg_(R.t2) * (T)INV_SQRT_PI;
         R.Phi = erfc_(R.t);
     }
     return R;
 }
 
-#define INV4PI 0.079577471545947667884
-#define INV8PI 0.039788735772973833942
-#define C34PI 0.23873241463784300365
-
 // forward pair contribution v[MOUT]; ps = source strengths
 template <int KERN, typename T>
-__device__ inline void pair_fwd(const T d[3], T r2, T isig, T isig2, const T *ps, T *v)
+__device__ inline void pair_fwd(const T d[3], T r2, T isig, T isig2, T kexp, const T *ps, T *v)
 {
-    const Rad<T> R = radial(r2, isig, isig2);
+    const Rad<T> R = radial(r2, isig, isig2, kexp);
     const T tphi2 = (T)2 * R.t * R.phi;
     if constexpr (KERN == 0) {
-        v[0] = R.Phi * R.ri * (T)INV4PI * ps[0];
+        v[0] = R.Phi * R.ri * ps[0];
     } else if constexpr (KERN == 1) {
         const T ri3 = R.ri * R.ri * R.ri;
-        const T A = (R.Phi - tphi2) * R.ri * (T)INV8PI;
-        const T B = (R.Phi + tphi2) * ri3 * (T)INV8PI;
+        const T A = (R.Phi - tphi2) * R.ri;
+        const T B = (R.Phi + tphi2) * ri3;
         const T df = d[0] * ps[0] + d[1] * ps[1] + d[2] * ps[2];
         const T Bdf = B * df;
         for (int c = 0; c < 3; ++c) v[c] = A * ps[c] + Bdf * d[c];
@@ -192,8 +203,8 @@ __device__ inline void pair_fwd(const T d[3], T r2, T isig, T isig2, const T *ps
         const T ri2 = R.ri * R.ri;
         const T ri3 = ri2 * R.ri;
         const T t3phi = R.t2 * R.t * R.phi;
-        const T P = (T)4 * t3phi * ri3 * (T)INV8PI;
-        const T Qc = -(T)C34PI * (R.Phi + tphi2 + (T)(4.0 / 3.0) * t3phi) * ri3 * ri2;
+        const T P = (T)4 * t3phi * ri3;
+        const T Qc = -(T)6 * (R.Phi + tphi2 + (T)(4.0 / 3.0) * t3phi) * ri3 * ri2;
         T rd[3], rtd[3];
         for (int l = 0; l < 3; ++l) {
             rd[l] = ps[3 * l + 0] * d[0] + ps[3 * l + 1] * d[1] + ps[3 * l + 2] * d[2];
@@ -204,7 +215,7 @@ __device__ inline void pair_fwd(const T d[3], T r2, T isig, T isig2, const T *ps
         for (int c = 0; c < 3; ++c) v[c] = P * (rd[c] + rtd[c] + tr * d[c]) + Qc * drd * d[c];
     } else {
         const T ri3 = R.ri * R.ri * R.ri;
-        const T f = (R.Phi + tphi2) * ri3 * (T)INV8PI;
+        const T f = (R.Phi + tphi2) * ri3;
         v[0] = f * (ps[1] * d[2] - ps[2] * d[1]);
         v[1] = f * (ps[2] * d[0] - ps[0] * d[2]);
         v[2] = f * (ps[0] * d[1] - ps[1] * d[0]);
@@ -214,28 +225,28 @@ __device__ inline void pair_fwd(const T d[3], T r2, T isig, T isig2, const T *ps
 // adjoint pair contribution v[MIN + 3] = (d grad_rho_t, d grad_x_t);
 // ps = (rho_s, G_s), pt = (rho_t, G_t); d = x_t - x_s (+ image).
 template <int KERN, typename T>
-__device__ inline void pair_bwd(const T d[3], T r2, T isig, T isig2, const T *ps, const T *pt, T *v)
+__device__ inline void pair_bwd(const T d[3], T r2, T isig, T isig2, T kexp, const T *ps, const T *pt, T *v)
 {
     constexpr int MIN = KDim<KERN>::MIN;
     const T *rs = ps, *Gs = ps + MIN, *rt = pt, *Gt = pt + MIN;
-    const Rad<T> R = radial(r2, isig, isig2);
+    const Rad<T> R = radial(r2, isig, isig2, kexp);
     const T tphi2 = (T)2 * R.t * R.phi;
     const T ri2 = R.ri * R.ri;
     const T ri3 = ri2 * R.ri;
     if constexpr (KERN == 0) {
-        const T K = R.Phi * R.ri * (T)INV4PI;
-        const T g = -(R.Phi + tphi2) * ri3 * (T)INV4PI;
+        const T K = R.Phi * R.ri;
+        const T g = -(R.Phi + tphi2) * ri3;
         v[0] = K * Gs[0];
         const T s = g * (Gt[0] * rs[0] + Gs[0] * rt[0]);
         for (int c = 0; c < 3; ++c) v[1 + c] = s * d[c];
     } else if constexpr (KERN == 1) {
         const T Sd = R.Phi - tphi2, So = R.Phi + tphi2;
-        const T A = Sd * R.ri * (T)INV8PI;
-        const T B = So * ri3 * (T)INV8PI;
+        const T A = Sd * R.ri;
+        const T B = So * ri3;
         const T dSd = (T)4 * R.phi * (R.t2 - (T)1);
         const T dSo = -(T)4 * R.t2 * R.phi;
-        const T Ar = (dSd * isig * ri2 - Sd * ri3) * (T)INV8PI;             // A'(r)/r
-        const T Br = (dSo * isig * ri2 * ri2 - (T)3 * So * ri3 * ri2) * (T)INV8PI;  // B'(r)/r
+        const T Ar = dSd * isig * ri2 - Sd * ri3;                      // A'(r)/r
+        const T Br = dSo * isig * ri2 * ri2 - (T)3 * So * ri3 * ri2;   // B'(r)/r
         const T dGs = d[0] * Gs[0] + d[1] * Gs[1] + d[2] * Gs[2];
         const T dGt = d[0] * Gt[0] + d[1] * Gt[1] + d[2] * Gt[2];
         const T drs = d[0] * rs[0] + d[1] * rs[1] + d[2] * rs[2];
@@ -251,13 +262,13 @@ __device__ inline void pair_bwd(const T d[3], T r2, T isig, T isig2, const T *ps
         const T t3phi = R.t2 * R.t * R.phi;
         const T Td = (T)4 * t3phi;
         const T To = R.Phi + tphi2 + (T)(4.0 / 3.0) * t3phi;
-        const T P = Td * ri3 * (T)INV8PI;
+        const T P = Td * ri3;
         const T ri5 = ri3 * ri2;
-        const T Qc = -(T)C34PI * To * ri5;
+        const T Qc = -(T)6 * To * ri5;
         const T dTd = (T)4 * R.t2 * R.phi * ((T)3 - (T)2 * R.t2);
         const T dTo = -(T)(8.0 / 3.0) * R.t2 * R.t2 * R.phi;
-        const T Pr = (dTd * isig * ri2 * ri2 - (T)3 * Td * ri5) * (T)INV8PI;
-        const T Qr = -(T)C34PI * (dTo * isig * ri3 * ri3 - (T)5 * To * ri5 * ri2);
+        const T Pr = dTd * isig * ri2 * ri2 - (T)3 * Td * ri5;
+        const T Qr = -(T)6 * (dTo * isig * ri3 * ri3 - (T)5 * To * ri5 * ri2);
         const T dGs = d[0] * Gs[0] + d[1] * Gs[1] + d[2] * Gs[2];
         // grad_rho_t[l][m] = -T_jlm(d) Gs_j
         for (int l = 0; l < 3; ++l)
@@ -288,9 +299,9 @@ __device__ inline void pair_bwd(const T d[3], T r2, T isig, T isig2, const T *ps
         for (int k = 0; k < 3; ++k) v[9 + k] = gx[k];
     } else {
         const T Oo = R.Phi + tphi2;
-        const T f = Oo * ri3 * (T)INV8PI;
+        const T f = Oo * ri3;
         const T dOo = -(T)4 * R.t2 * R.phi;
-        const T fr = (dOo * isig * ri2 * ri2 - (T)3 * Oo * ri3 * ri2) * (T)INV8PI;
+        const T fr = dOo * isig * ri2 * ri2 - (T)3 * Oo * ri3 * ri2;
         // grad_rho_t = f (Gs x d)
         v[0] = f * (Gs[1] * d[2] - Gs[2] * d[1]);
         v[1] = f * (Gs[2] * d[0] - Gs[0] * d[2]);
@@ -326,7 +337,7 @@ __device__ inline void store_source(Smem<C> &S, int dest, double X, double Y, do
 
 // Stage the sources of one chunk [c0, c0+clen) of the tile's concatenated
 // pieces.  Multi-box tiles (dense == false, one chunk) place every source at
-// its slab-major slot dtab[slab*9 + column] + j; dense tiles keep the
+// its slab-major slot dtab[slab*9 + column] + rank in its piece; dense tiles keep the
 // concatenated order.  Each thread handles up to PER sources and issues all
 // of their global loads before its first LDS store.
 template <class C>
@@ -336,7 +347,7 @@ __device__ inline void stage_chunk(Smem<C> &S, const ResParams &P, bool dense, i
     constexpr int NT = C::NW * WAVE;
     constexpr int PER = (TILE_CAP + NT - 1) / NT;
     const int64_t N = P.N;
-    int sgi[PER], sk[PER];
+    int sgi[PER], sk[PER], rk[PER];
     int64_t jj[PER];
     double X[PER], Y[PER], Z[PER], pl[PER][C::NPL];
 #pragma unroll
@@ -348,17 +359,19 @@ __device__ inline void stage_chunk(Smem<C> &S, const ResParams &P, bool dense, i
         for (int step = 16; step > 0; step >>= 1)
             if (S.segso[lo + step] <= qc) lo += step;
         sgi[u] = lo;
-        jj[u] = (int64_t)S.seg[lo].gstart + (qc - S.seg[lo].so);
+        rk[u] = qc - S.seg[lo].so;  // rank within the piece
+        jj[u] = (int64_t)S.seg[lo].gstart + rk[u];
     }
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         if (tid + u * NT < clen) {
             const int64_t j = jj[u];
             const Seg &g = S.seg[sgi[u]];
-            X[u] = P.ys[j] + g.offx;
-            Y[u] = P.ys[N + j] + g.offy;
-            Z[u] = P.ys[2 * N + j] + g.offz;
-            for (int c = 0; c < C::NPL; ++c) pl[u][c] = P.pl[c * N + j];
+            const double2 co = S.coff[g.k];
+            X[u] = P.ys[j] + co.x;
+            Y[u] = P.ys[N + j] + co.y;
+            Z[u] = P.ys[2 * N + j] + S.zoff[g.piece];
+            for (int c = 0; c < C::NPL; ++c) pl[u][c] = P.pl[c * N + j] * KNorm<C::K>::c;  // normalised
             sk[u] = dense ? 0 : P.skey[j];
         }
     }
@@ -370,7 +383,7 @@ __device__ inline void stage_chunk(Smem<C> &S, const ResParams &P, bool dense, i
             if (!dense) {
                 const Seg &g = S.seg[sgi[u]];
                 const int slab = (sk[u] - S.ccol[g.k] * n2) + g.vshift - za;
-                dest = S.st.dtab[slab * 9 + g.k] + (int)jj[u];
+                dest = S.st.dtab[slab * 9 + g.k] + rk[u];
             }
             store_source<C>(S, dest, X[u], Y[u], Z[u], pl[u]);
         }
@@ -432,6 +445,20 @@ __device__ inline double dpp_val(double x)
     return __hiloint2double(hi, lo);
 }
 
+// the same move where lanes that are not written may hold any value
+template <int CTRL, int RM>
+__device__ inline float dpp_any(float x)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, RM, 0xf, true));
+}
+template <int CTRL, int RM>
+__device__ inline double dpp_any(double x)
+{
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, RM, 0xf, true);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, RM, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
 // Segmented inclusive sum over the 64 lanes.  Lanes hold values v[NC] whose
 // tags (>= 1) are non-decreasing along the lanes; afterwards the last lane
 // of each run of equal tags holds the run's total.  Shifts by 1, 2, 4, 8
@@ -457,9 +484,9 @@ __device__ inline bool seg_shift(int tag, T *v)
 template <int CTRL, int RM, int NC, typename T>
 __device__ inline void seg_carry(int tag, T *v)
 {
-    const bool same = dpp_int<CTRL, RM>(tag, 0) == tag;
+    const bool same = dpp_int<CTRL, RM>(tag, 0) == tag;  // false in rows not written
     for (int c = 0; c < NC; ++c) {
-        const T x = dpp_val<CTRL, RM>(v[c]);
+        const T x = dpp_any<CTRL, RM>(v[c]);
         v[c] += same ? x : (T)0;
     }
 }
@@ -473,6 +500,19 @@ __device__ inline bool seg_sum(int tag, T *v)
     seg_carry<DPP_ROW_BCAST15, 0xa, NC>(tag, v);
     seg_carry<DPP_ROW_BCAST31, 0xc, NC>(tag, v);
     return last;
+}
+
+// inclusive prefix sum over the 64 lanes (shifts within rows, then carries
+// into the following rows)
+__device__ inline int wave_incl_scan(int v)
+{
+    v += dpp_int<DPP_ROW_SHR + 1, 0xf>(v, 0);
+    v += dpp_int<DPP_ROW_SHR + 2, 0xf>(v, 0);
+    v += dpp_int<DPP_ROW_SHR + 4, 0xf>(v, 0);
+    v += dpp_int<DPP_ROW_SHR + 8, 0xf>(v, 0);
+    v += dpp_int<DPP_ROW_BCAST15, 0xa>(v, 0);
+    v += dpp_int<DPP_ROW_BCAST31, 0xc>(v, 0);
+    return v;
 }
 
 // plain wavefront sum by the same pattern; lane 63 holds the total
@@ -522,6 +562,7 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
 
     const T isig = (T)(1.0 / P.sigma);
     const T isig2 = isig * isig;
+    const T kexp = (T)(-1.4426950408889634 / (P.sigma * P.sigma));  // -log2(e) / sigma^2
     const T rc2 = (T)(P.rc * P.rc);
     // Scan test (FP32, conservative): source s is queued for target t when
     // |s|^2 - 2 s.t < rc2s - |t|^2 (both sides halved in the code).  The
@@ -542,16 +583,23 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         Seg g;
         g.glen = 0;
         g.gstart = 0;
-        g.k = k;
+        g.k = (signed char)k;
         g.vshift = 0;
-        g.offx = g.offy = g.offz = 0.0;
+        g.piece = (signed char)piece;
+        g.pad = 0;
         int i0, i1;
         const int nb0 = axis_nb(P, 0, b0, c0 - 1, i0), nb1 = axis_nb(P, 1, b1, c1 - 1, i1);
+        if (piece == 1) S.coff[k] = make_double2(i0 * P.L[0] - crx, i1 * P.L[1] - cry);
+        if (k == 0) {
+            // z image of each piece: -1 below, +1 above (periodic z), 0 inside
+            int zi = 0;
+            if (piece == 0) axis_nb(P, 2, 0, -1, zi);
+            if (piece == 2) axis_nb(P, 2, n2 - 1, 1, zi);
+            S.zoff[piece] = zi * P.L[2] - crz;
+        }
         if (nb0 >= 0 && nb1 >= 0) {
             const int cc = nb0 * n1 + nb1;
             const int64_t cb = (int64_t)cc * n2;
-            g.offx = i0 * P.L[0] - crx;
-            g.offy = i1 * P.L[1] - cry;
             int lo = 1, hi = 0, zimg = 0;
             if (piece == 0 && za == -1) {  // virtual z = -1
                 lo = hi = axis_nb(P, 2, 0, -1, zimg);
@@ -566,8 +614,8 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
             if (lo >= 0 && lo <= hi) {
                 g.gstart = P.bs[cb + lo];
                 g.glen = P.bs[cb + hi + 1] - g.gstart;
-                g.offz = zimg * P.L[2] - crz;
             }
+            (void)zimg;
             if (piece == 1) S.ccol[k] = cc;
         } else if (piece == 1) {
             S.ccol[k] = -1;
@@ -582,14 +630,15 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
             const int nb0 = axis_nb(P, 0, b0, k / 3 - 1, i0), nb1 = axis_nb(P, 1, b1, k % 3 - 1, i1);
             const int zv = za + sl;
             const int zp = (zv < 0) ? axis_nb(P, 2, 0, -1, iz) : (zv >= n2 ? axis_nb(P, 2, n2 - 1, 1, iz) : zv);
-            int cnt = 0, gs = 0;
+            int cnt = 0, pre = 0;
             if (nb0 >= 0 && nb1 >= 0 && zp >= 0) {
-                const int64_t bb = (int64_t)(nb0 * n1 + nb1) * n2 + zp;
-                gs = P.bs[bb];
-                cnt = P.bs[bb + 1] - gs;
+                const int64_t cb = (int64_t)(nb0 * n1 + nb1) * n2;
+                const int gs = P.bs[cb + zp];
+                cnt = P.bs[cb + zp + 1] - gs;
+                // boxes inside the domain form one piece starting at max(za, 0)
+                if (zv >= 0 && zv < n2) pre = gs - P.bs[cb + (za < 0 ? 0 : za)];
             }
-            S.st.dtab[idx] = cnt;
-            S.st.dgs[idx] = gs;
+            S.st.dtab[idx] = cnt | (pre << 16);
         }
     }
     for (int idx = tid; idx < C::NC * TILE_T; idx += C::NW * WAVE) {
@@ -618,33 +667,34 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
     __syncthreads();
 
     // ---- phase B (LDS only): piece offsets in the concatenated order, and the
-    // slab-major offsets dtab[s*9+k] - box start (multi-box tiles)
-    if (tid < 32) {
-        // inclusive scan of the 27 piece lengths by one wavefront's lanes
-        const int gl = tid < 27 ? S.seg[tid].glen : 0;
+    // slab-major offsets dtab[s*9+k] (multi-box tiles)
+    if (w == 0) {
+        // inclusive scan of the 27 piece lengths
+        const int gl = lane < 27 ? S.seg[lane].glen : 0;
         const int incl = wave_incl_scan(gl);
-        if (tid < 27) S.seg[tid].so = incl - gl;
-        S.segso[tid] = tid < 27 ? incl - gl : 0x7fffffff;
-        if (tid == 26) S.qtot = incl;
+        if (lane < 27) S.seg[lane].so = incl - gl;
+        if (lane < 32) S.segso[lane] = lane < 27 ? incl - gl : 0x7fffffff;
+        if (lane == 26) S.qtot = incl;
     }
     if (!dense && w == 1) {
         const int M = nslab * 9;
         int carry = 0;
         for (int base = 0; base < M; base += WAVE) {
             const int idx = base + lane;
-            const int cnt = idx < M ? S.st.dtab[idx] : 0;
+            const int e = idx < M ? S.st.dtab[idx] : 0;
+            const int cnt = e & 0xffff;
             const int incl = wave_incl_scan(cnt);
             if (idx < M) {
                 const int off = carry + incl - cnt;
-                S.st.dtab[idx] = off - S.st.dgs[idx];
+                S.st.dtab[idx] = off - (e >> 16);
                 if (idx % 9 == 0) S.soff[idx / 9] = off;
             }
-            carry += __shfl(incl, 63, 64);
+            carry += __builtin_amdgcn_readlane(incl, WAVE - 1);
         }
         if (lane == 0) S.soff[nslab] = carry;
     }
     __syncthreads();
-    if (!dense && tid < ntgt) S.trange[tid] = make_int2(S.soff[my_zt - z0], S.soff[my_zt - z0 + 3]);
+    if (!dense && tid < ntgt) S.trange[tid] = S.soff[my_zt - z0] | (S.soff[my_zt - z0 + 3] << 16);
 
     int qn = 0;  // entries in this wavefront's queue (uniform)
     uint32_t *queue = S.queue[w];
@@ -673,13 +723,14 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
             for (int c = 0; c < C::NPL; ++c) ps[c] = S.spd[c][q];
             for (int c = 0; c < C::NTP; ++c) pt[c] = S.tpd[c][t];
         }
-        T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        // a rejected pair (coincident points, or outside the cutoff) may give
+        // non-finite intermediates; its result is replaced by zero
+        const T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         const bool ok = (r2 > (T)0) && (r2 < rc2);
-        if (!ok) r2 = rc2;  // keeps the math finite; result discarded
         if constexpr (BWD)
-            pair_bwd<KERN, T>(d, r2, isig, isig2, ps, pt, v);
+            pair_bwd<KERN, T>(d, r2, isig, isig2, kexp, ps, pt, v);
         else
-            pair_fwd<KERN, T>(d, r2, isig, isig2, ps, v);
+            pair_fwd<KERN, T>(d, r2, isig, isig2, kexp, ps, v);
         for (int c = 0; c < C::NC; ++c) v[c] = ok ? v[c] : (T)0;
     };
 
@@ -743,7 +794,6 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         // ---- stage sources of this chunk: flat over the concatenated pieces,
         // all loads of a thread issued before any of its LDS stores
         stage_chunk<C>(S, P, dense, c0, clen, za, n2, tid);
-        if (tid < C::SCAN) S.sc[clen + tid] = make_float4(0.0f, 0.0f, 0.0f, 1e30f);  // never queued
         __syncthreads();
 
         // ---- scan: one target at a time over its contiguous stencil range;
@@ -756,32 +806,49 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
             const float tx = ts.x, ty = ts.y, tz = ts.z, thr = ts.w;
             int a = 0, b = clen;
             if (!dense) {
-                const int2 rg = S.trange[t];
-                a = __builtin_amdgcn_readfirstlane(rg.x);
-                b = __builtin_amdgcn_readfirstlane(rg.y);
+                const int rg = __builtin_amdgcn_readfirstlane(S.trange[t]);
+                a = rg & 0xffff;
+                b = rg >> 16;
             }
             const uint32_t tag = (uint32_t)t << 16;
-            for (int p = a; p < b; p += C::SCAN) {
-                const float4 s0 = S.sc[p + lane], s1 = S.sc[p + WAVE + lane];
+            // Each step tests sources [p, p + 128) (slots past b belong to other
+            // slabs, farther than the cutoff, and fail the pair step's exact
+            // test).  Hits are appended at queue[qn ..) in lane order, those of
+            // the first half first; entry = (t << 16) | source slot.  A step
+            // reaching past the staged sources clamps its reads and drops the
+            // hits there.
+            for (int p = a; p < b; p += 2 * WAVE) {
+                int i0 = p + lane, i1 = p + WAVE + lane;
+                bool in0 = true, in1 = true;
+                if (p + 2 * WAVE > clen) {
+                    in0 = i0 < clen;
+                    in1 = i1 < clen;
+                    i0 = in0 ? i0 : 0;
+                    i1 = in1 ? i1 : 0;
+                }
+                const float4 s0 = S.sc[i0], s1 = S.sc[i1];
                 // (|s|^2 - 2 s.t) / 2 against (rc2s - |t|^2) / 2
                 const float ra = fmaf(-s0.x, tx, fmaf(-s0.y, ty, fmaf(-s0.z, tz, s0.w)));
                 const float rb = fmaf(-s1.x, tx, fmaf(-s1.y, ty, fmaf(-s1.z, tz, s1.w)));
-                const bool ha = ra < thr, hb = rb < thr;
-                const uint64_t ma = __ballot(ha);
-                const uint64_t mb = __ballot(hb);
-                // hits of the first half go to queue[qn ..), those of the second
-                // after them, each at its rank among the hits of its half;
-                // entry = (t << 16) | source slot
-                const int na = __popcll(ma), nb = __popcll(mb);
-                uint32_t *qa = queue + qn;
-                uint32_t *qb = qa + na;
+                const bool ha = (ra < thr) && in0, hb = (rb < thr) && in1;
+                const uint64_t ma = __ballot(ha), mb = __ballot(hb);
                 const uint32_t ea = (tag | (uint32_t)p) + (uint32_t)lane;
-                if (ha) qa[__builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u))] = ea;
-                if (hb)
-                    qb[__builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u))] =
-                        ea + (uint32_t)WAVE;
-                qn += na + nb;
-                if (qn >= WAVE) drain();
+                const uint32_t ra_ = __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u));
+                const uint32_t rb_ = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+                if constexpr (C::DRAIN_HALF) {
+                    if (ha) queue[qn + ra_] = ea;
+                    qn += __popcll(ma);
+                    if (qn >= WAVE) drain();
+                    if (hb) queue[qn + rb_] = ea + (uint32_t)WAVE;
+                    qn += __popcll(mb);
+                    if (qn >= WAVE) drain();
+                } else {
+                    const int na = __popcll(ma);
+                    if (ha) queue[qn + ra_] = ea;
+                    if (hb) queue[qn + na + rb_] = ea + (uint32_t)WAVE;
+                    qn += na + __popcll(mb);
+                    if (qn >= WAVE) drain();
+                }
             }
             if (dense) {
                 // the rest of this target's pairs, then its total
