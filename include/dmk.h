@@ -152,6 +152,17 @@ int dmk_residual_backward(const dmk_grid *grid, const dmk_bins *bins, int kernel
                           double rc, const double *rho, const double *gu, double *grad_rho, double *grad_x,
                           void *ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Timing hook: from now on, record the device events `start` right before and
+ * `stop` right after the pair kernel of every dmk_residual_eval /
+ * dmk_residual_backward call, on that call's stream (the strength gather
+ * that precedes it stays outside the pair).  Events are owned by the caller
+ * and must stay valid while set; pass two null events to stop recording.
+ * Process-wide setting, not synchronised between host threads; meant for
+ * benchmarks.  Returns DMK_OK, or DMK_EINVAL when exactly one event is null.
+ */
+int dmk_residual_set_kernel_events(hipEvent_t start, hipEvent_t stop);
+
 /* Static description of a status code. */
 const char *dmk_strerror(int status);
 

@@ -69,6 +69,8 @@ def load():
     lib.dmk_residual_backward.argtypes = [G, B, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, P,
                                           P, P, P, ctypes.c_size_t, P]
     lib.dmk_residual_backward.restype = ctypes.c_int
+    lib.dmk_residual_set_kernel_events.argtypes = [P, P]
+    lib.dmk_residual_set_kernel_events.restype = ctypes.c_int
     lib.dmk_strerror.argtypes = [ctypes.c_int]
     lib.dmk_strerror.restype = ctypes.c_char_p
     lib.dmk_version.argtypes = []
@@ -128,6 +130,10 @@ def dmk_residual_backward(grid, bins, kernel, prec, sigma, rc, rho_ptr, gu_ptr, 
                                             ctypes.c_void_p(gu_ptr), ctypes.c_void_p(grho_ptr),
                                             ctypes.c_void_p(gx_ptr), ctypes.c_void_p(ws_ptr), int(ws_bytes),
                                             ctypes.c_void_p(stream)))
+
+
+def dmk_residual_set_kernel_events(start_ptr: int, stop_ptr: int) -> int:
+    return int(load().dmk_residual_set_kernel_events(ctypes.c_void_p(start_ptr), ctypes.c_void_p(stop_ptr)))
 
 
 def dmk_version() -> str:

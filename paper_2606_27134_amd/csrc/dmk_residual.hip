@@ -987,6 +987,29 @@ ResParams make_params(const dmk_grid *g, const dmk_bins *b, double sigma, double
 
 }  // namespace
 
+// timing events recorded around the pair kernel (see dmk_residual_set_kernel_events)
+static hipEvent_t g_kernel_ev_start = nullptr, g_kernel_ev_stop = nullptr;
+
+extern "C" int dmk_residual_set_kernel_events(hipEvent_t start, hipEvent_t stop)
+{
+    if ((start == nullptr) != (stop == nullptr)) return DMK_EINVAL;
+    g_kernel_ev_start = start;
+    g_kernel_ev_stop = stop;
+    return DMK_OK;
+}
+
+namespace {
+// launch the pair kernel between the optional timing events
+template <bool BWD>
+int launch_timed(int kernel, int prec, const ResParams &P, hipStream_t s)
+{
+    if (g_kernel_ev_start && hipEventRecord(g_kernel_ev_start, s) != hipSuccess) return DMK_EHIP;
+    const int st = P.ntiles > 0 ? dispatch<BWD>(kernel, prec, P, s) : DMK_OK;
+    if (st == DMK_OK && g_kernel_ev_stop && hipEventRecord(g_kernel_ev_stop, s) != hipSuccess) return DMK_EHIP;
+    return st;
+}
+}  // namespace
+
 extern "C" size_t dmk_residual_ws_bytes(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec,
                                         int backward)
 {
@@ -1009,10 +1032,10 @@ extern "C" int dmk_residual_eval(const dmk_grid *grid, const dmk_bins *bins, int
     double *pl = (double *)ws;
     hipLaunchKernelGGL(k_gather_payload, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, rho,
                        (const double *)nullptr, bins->perm, N, m_in_of(kernel), m_out_of(kernel), pl);
-    if (bins->ntiles == 0) return hipGetLastError() == hipSuccess ? DMK_OK : DMK_EHIP;
+    if (hipGetLastError() != hipSuccess) return DMK_EHIP;
     ResParams P = make_params(grid, bins, sigma, rc, pl);
     P.out0 = u;
-    return dispatch<false>(kernel, prec, P, stream);
+    return launch_timed<false>(kernel, prec, P, stream);
 }
 
 extern "C" int dmk_residual_backward(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec,
@@ -1031,5 +1054,5 @@ extern "C" int dmk_residual_backward(const dmk_grid *grid, const dmk_bins *bins,
     ResParams P = make_params(grid, bins, sigma, rc, pl);
     P.out0 = grad_rho;
     P.out1 = grad_x;
-    return dispatch<true>(kernel, prec, P, stream);
+    return launch_timed<true>(kernel, prec, P, stream);
 }

@@ -95,3 +95,10 @@ def test_workspace_sizes_grow_with_components():
     sizes = [L.dmk_residual_ws_bytes(g, b, k, 0, bw) for k in range(4) for bw in (0, 1)]
     assert all(s >= 1000 * 8 for s in sizes)
     assert L.dmk_residual_ws_bytes(g, b, 2, 0, 1) > L.dmk_residual_ws_bytes(g, b, 0, 0, 0)
+
+
+def test_kernel_events_argument_check():
+    # one event without the other is rejected; two null events clear the hook
+    assert L.dmk_residual_set_kernel_events(1 << 40, 0) == L.DMK_EINVAL
+    assert L.dmk_residual_set_kernel_events(0, 1 << 40) == L.DMK_EINVAL
+    assert L.dmk_residual_set_kernel_events(0, 0) == L.DMK_OK
