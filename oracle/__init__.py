@@ -17,6 +17,10 @@ Functions follow the paper's notation:
 * :func:`direct_free` -- D = 0 direct sum of the original kernels (App. B).
 * :func:`full_split_3p` -- mode F for D = 3 (eq. (ewald_far_3P) plus the
   self-interaction correction of Sec. 2.4).
+
+Every function takes ``window=None`` (the Gaussian split of width sigma) or a
+:class:`oracle.pswf.PswfWindow` (the PSWF split of Sec. 2.2, eq.
+(wfunc_pswf)); for the latter ``sigma`` is the support radius nu.
 """
 from __future__ import annotations
 
@@ -63,11 +67,25 @@ def _load():
         lib.oracle_full_split_3p.argtypes = [C, P, D, I64, P, P, D, D, I64, P, P]
         lib.oracle_kernel_tensor.argtypes = [C, P, D, P, P]
         lib.oracle_kernel_free_tensor.argtypes = [C, P, P]
+        lib.oracle_set_window.argtypes = [C, C, P, C, P, P, P]
+        lib.oracle_set_window.restype = C
         for f in (lib.oracle_residual, lib.oracle_residual_vjp, lib.oracle_direct_free,
                   lib.oracle_full_split_3p, lib.oracle_kernel_tensor, lib.oracle_kernel_free_tensor):
             f.restype = C
         _lib = lib
     return _lib
+
+
+def _set_window(window):
+    lib = _load()
+    if window is None:
+        lib.oracle_set_window(0, 0, None, 0, None, None, None)
+        return
+    n, ser, qs, qw, qf = window.packed()
+    ser = np.ascontiguousarray(ser, dtype=np.float64)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (qs, qw, qf)]
+    if lib.oracle_set_window(1, int(n), _ptr(ser), len(qs), *[_ptr(a) for a in arrs]) != 0:
+        raise ValueError("oracle_set_window: bad window")
 
 
 def _kid(kernel) -> int:
@@ -94,8 +112,9 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
-def residual(kernel, D, L, sigma, rc, x, rho, targets=None):
+def residual(kernel, D, L, sigma, rc, x, rho, targets=None, window=None):
     """Mode R residual sum; returns u[ntgt, m_out] (float64)."""
+    _set_window(window)
     k = _kid(kernel)
     x = _f64(x, (-1, 3))
     n = x.shape[0]
@@ -110,8 +129,9 @@ def residual(kernel, D, L, sigma, rc, x, rho, targets=None):
     return u
 
 
-def residual_vjp(kernel, D, L, sigma, rc, x, rho, G, targets=None):
+def residual_vjp(kernel, D, L, sigma, rc, x, rho, G, targets=None, window=None):
     """Gradients of F = sum_b G_b . u_b; returns (grad_rho[ntgt, m_in], grad_x[ntgt, 3])."""
+    _set_window(window)
     k = _kid(kernel)
     x = _f64(x, (-1, 3))
     n = x.shape[0]
@@ -142,21 +162,23 @@ def direct_free(kernel, x, rho, rc=np.inf, targets=None):
     return u
 
 
-def full_split_3p(kernel, L, sigma, x, rho, rcut_real=None, kmax=None, targets=None):
+def full_split_3p(kernel, L, sigma, x, rho, rcut_real=None, kmax=None, targets=None, window=None):
     """Mode F (D = 3): residual over all images + Fourier part (k != 0) + self term.
 
-    Defaults: real-space cutoff 7 sigma and |k| sigma <= 14, so both neglected
-    tails are below 1e-17 relative to the leading terms for the Gaussian window.
+    Defaults: Gaussian window: real-space cutoff 7 sigma and |k| sigma <= 14,
+    so both neglected tails are below 1e-17 relative to the leading terms;
+    PSWF window: the support nu = sigma and the band |k| nu <= c.
     """
+    _set_window(window)
     k = _kid(kernel)
     x = _f64(x, (-1, 3))
     n = x.shape[0]
     rho = _f64(rho, (n, M_IN[k]))
     Lv = _f64(L, (3,))
     if rcut_real is None:
-        rcut_real = 7.0 * sigma
+        rcut_real = 7.0 * sigma if window is None else sigma
     if kmax is None:
-        kmax = 14.0 / sigma
+        kmax = 14.0 / sigma if window is None else window.c / sigma
     t, nt = _targets(targets, n)
     u = np.zeros((nt, M_OUT[k]), dtype=np.float64)
     rc_ = _load().oracle_full_split_3p(k, _ptr(Lv), float(sigma), n, _ptr(x), _ptr(rho), float(rcut_real),
@@ -166,8 +188,9 @@ def full_split_3p(kernel, L, sigma, x, rho, rcut_real=None, kmax=None, targets=N
     return u
 
 
-def kernel_tensor(kernel, d, sigma):
+def kernel_tensor(kernel, d, sigma, window=None):
     """Residual kernel K[j, L] and derivative dK[k, j, L] at one displacement."""
+    _set_window(window)
     k = _kid(kernel)
     d = _f64(d, (3,))
     K = np.zeros((3, 9))

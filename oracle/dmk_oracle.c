@@ -32,11 +32,16 @@
  * Strength sizes m_in = 1, 3, 9, 3; potential sizes m_out = 1, 3, 3, 3.
  * Stresslet strengths are row-major rho[l*3+m] and u_j = T_jlm rho_lm.
  *
- * Window: the Gaussian, phi(t) = exp(-t^2)/sqrt(pi), whose Fourier transform
- * is exp(-k^2/4) (Sec. 2.2, remark after eq. (Hhatsplit_wfunc)); then
- * Phi(t) = 1 - 2 int_0^t phi = erfc(t)  (eq. (def_erfc_like_fcn)).  All
- * real-space functions are evaluated at t = r/sigma (remark
- * scaling_stokes_split, App. B).
+ * Window (Sec. 2.2), selected with oracle_set_window:
+ *  - the Gaussian (default), phi(t) = exp(-t^2)/sqrt(pi), whose Fourier
+ *    transform is exp(-k^2/4) (remark after eq. (Hhatsplit_wfunc)); then
+ *    Phi(t) = 1 - 2 int_0^t phi = erfc(t)  (eq. (def_erfc_like_fcn));
+ *  - the PSWF window of eq. (wfunc_pswf), supported on |t| < 1, given as
+ *    Legendre series of phi, int_0^t phi, phi' and phi'' (computed by the
+ *    Python side of the oracle from its own eigen-solve), with quadrature
+ *    nodes for its Fourier transform.
+ * All real-space functions are evaluated at t = r/sigma, sigma being the
+ * split length (nu for the PSWF window; remark scaling_stokes_split, App. B).
  */
 #include <math.h>
 #include <stdint.h>
@@ -48,9 +53,88 @@
 
 /* ------------------------------------------------------------------------ */
 /* window and its integral (Sec. 2.2)                                       */
-static long double win_phi(long double t) { return expl(-t * t) / sqrtl(PI_L); }
-static long double win_dphi(long double t) { return -2.0L * t * win_phi(t); }
-static long double win_Phi(long double t) { return erfcl(t); }
+#define WIN_MAXN 256
+#define WIN_MAXQ 512
+static int g_win = 0;                      /* 0 Gaussian, 1 Legendre-series window on |t| < 1 */
+static int g_win_n = 0;
+static long double g_win_ser[4][WIN_MAXN]; /* phi, int_0^t phi, phi', phi'' */
+static int g_win_nq = 0;
+static long double g_win_qs[WIN_MAXQ], g_win_qw[WIN_MAXQ], g_win_qf[WIN_MAXQ];
+
+/* sum_k a_k P_k(t), Legendre polynomials by their three-term recurrence */
+static long double leg_sum(const long double *a, int n, long double t)
+{
+    long double p0 = 1.0L, p1 = t, s = a[0];
+    if (n > 1) s += a[1] * t;
+    for (int k = 1; k + 1 < n; k++) {
+        const long double p2 = ((2.0L * k + 1.0L) * t * p1 - (long double)k * p0) / (long double)(k + 1);
+        s += a[k + 1] * p2;
+        p0 = p1;
+        p1 = p2;
+    }
+    return s;
+}
+
+static long double win_phi(long double t)
+{
+    if (g_win == 0) return expl(-t * t) / sqrtl(PI_L);
+    return fabsl(t) < 1.0L ? leg_sum(g_win_ser[0], g_win_n, t) : 0.0L;
+}
+static long double win_Phi(long double t)
+{
+    if (g_win == 0) return erfcl(t);
+    return fabsl(t) < 1.0L ? 1.0L - 2.0L * leg_sum(g_win_ser[1], g_win_n, t) : 0.0L;
+}
+static long double win_dphi(long double t)
+{
+    if (g_win == 0) return -2.0L * t * win_phi(t);
+    return fabsl(t) < 1.0L ? leg_sum(g_win_ser[2], g_win_n, t) : 0.0L;
+}
+static long double win_ddphi(long double t)
+{
+    if (g_win == 0) return (4.0L * t * t - 2.0L) * win_phi(t);
+    return fabsl(t) < 1.0L ? leg_sum(g_win_ser[3], g_win_n, t) : 0.0L;
+}
+/* phihat(q) = int phi(s) e^{iqs} ds and d phihat / dq */
+static void win_hat(long double q, long double *ph, long double *dph)
+{
+    if (g_win == 0) {
+        *ph = expl(-q * q / 4.0L);
+        *dph = -(q / 2.0L) * *ph;
+        return;
+    }
+    long double a = 0.0L, b = 0.0L;
+    for (int i = 0; i < g_win_nq; i++) {
+        a += g_win_qw[i] * g_win_qf[i] * cosl(q * g_win_qs[i]);
+        b -= g_win_qw[i] * g_win_qf[i] * g_win_qs[i] * sinl(q * g_win_qs[i]);
+    }
+    *ph = a;
+    *dph = b;
+}
+
+/* Select the window: type 0 Gaussian; type 1 Legendre-series window with
+ * ser[4][n] (row-major) and nq quadrature nodes qs / weights qw / phi values
+ * qf on [-1, 1].  Not thread-safe; set before a computation. */
+int oracle_set_window(int type, int n, const double *ser, int nq, const double *qs, const double *qw,
+                      const double *qf)
+{
+    if (type == 0) {
+        g_win = 0;
+        return 0;
+    }
+    if (type != 1 || n < 1 || n > WIN_MAXN || nq < 1 || nq > WIN_MAXQ) return 1;
+    for (int i = 0; i < 4; i++)
+        for (int k = 0; k < n; k++) g_win_ser[i][k] = ser[i * n + k];
+    for (int i = 0; i < nq; i++) {
+        g_win_qs[i] = qs[i];
+        g_win_qw[i] = qw[i];
+        g_win_qf[i] = qf[i];
+    }
+    g_win_n = n;
+    g_win_nq = nq;
+    g_win = 1;
+    return 0;
+}
 
 static int m_in_of(int k) { return k == 0 ? 1 : (k == 2 ? 9 : 3); }
 static int m_out_of(int k) { return k == 0 ? 1 : 3; }
@@ -88,7 +172,7 @@ static void kernel_tensor(int kern, const long double d[3], long double sigma,
     const long double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     const long double r = sqrtl(r2);
     const long double t = r / sigma;
-    const long double Ph = win_Phi(t), ph = win_phi(t), dph = win_dphi(t);
+    const long double Ph = win_Phi(t), ph = win_phi(t), dph = win_dphi(t), ddph = win_ddphi(t);
     /* d/dt of Phi, phi */
     const long double dPh = -2.0L * ph;
     int j, l, m, k;
@@ -120,8 +204,6 @@ static void kernel_tensor(int kern, const long double d[3], long double sigma,
                                       B * ((j == k) * d[l] + d[j] * (l == k));
             }
     } else if (kern == 2) {
-        /* phi'' = d/dt(-2 t phi) = -2 phi - 2 t phi' */
-        long double ddph = -2.0L * ph - 2.0L * t * dph;
         long double Td = -2.0L * t * t * dph;
         long double To = Ph + 2.0L * t * ph - (2.0L / 3.0L) * t * t * dph;
         long double dTd = -4.0L * t * dph - 2.0L * t * t * ddph;
@@ -369,8 +451,8 @@ static void khat_tensor(int kern, const long double k[3], long double sigma,
 {
     const long double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
     const long double q = sqrtl(k2) * sigma;
-    const long double ph = expl(-q * q / 4.0L);
-    const long double dph = -(q / 2.0L) * ph;
+    long double ph, dph;
+    win_hat(q, &ph, &dph);
     const long double gB = ph - 0.5L * q * dph;
     const long double Hh = ph / k2;
     const long double Bh = gB / (k2 * k2);
@@ -453,7 +535,7 @@ int oracle_full_split_3p(int kern, const double L[3], double sigma, int64_t N, c
                     for (int j = 0; j < mo; j++) uf[3 * ib + j] += creall(w[j] * e);
                 }
             }
-    const long double phi0 = 1.0L / sqrtl(PI_L);
+    const long double phi0 = win_phi(0.0L);
     for (int64_t ib = 0; ib < ntgt; ib++) {
         const int64_t b = tgt ? tgt[ib] : ib;
         for (int j = 0; j < mo; j++) {
