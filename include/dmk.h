@@ -153,6 +153,42 @@ int dmk_residual_backward(const dmk_grid *grid, const dmk_bins *bins, int kernel
                           void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * PSWF window (Sec. 2.2, eq. (wfunc_pswf)): phi(t) = psi_0^c(t) / int psi_0^c
+ * on |t| < 1 and Phi(t) = 1 - 2 int_0^t phi, with psi_0^c the zeroth-order
+ * prolate spheroidal wave function of bandwidth c (eq. (PSWFeig)).  The
+ * residual kernels of the split at length nu are the formulas of App. B
+ * (eqs. (Hhatsplit_wfunc), (Soffdiag), (T-offd), (ROoffd)) at t = r/nu, and
+ * vanish for r >= nu (remark on compact support).
+ *
+ * dmk_pswf_window fills w (host memory, computed on the host) for
+ * 0 < c <= DMK_PSWF_CMAX: Chebyshev coefficients, in u = 2 t^2 - 1, of
+ * phi(t), (1 - Phi(t))/t, phi'(t)/t and phi''(t), and the number of terms
+ * the FP64 / FP32 paths use.  Returns DMK_EINVAL (null w) or
+ * DMK_EUNSUPPORTED (c out of range).
+ */
+#define DMK_PSWF_MAXTERMS 32   /* terms per function, FP64 path */
+#define DMK_PSWF_MAXTERMS32 24 /* terms per function, FP32 path */
+#define DMK_PSWF_CMAX 40.0
+typedef struct {
+    double c;
+    int32_t nterms64, nterms32;
+    double cheb[4][DMK_PSWF_MAXTERMS];
+} dmk_pswf;
+int dmk_pswf_window(double c, dmk_pswf *w);
+
+/*
+ * dmk_residual_eval / dmk_residual_backward with the PSWF split of support
+ * radius nu instead of the Gaussian: same arguments, layouts, workspace and
+ * error rules, with `w` (host pointer, from dmk_pswf_window, read during the
+ * call) and 0 < nu <= min_i h_i in place of (sigma, rc).
+ */
+int dmk_residual_eval_pswf(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, const dmk_pswf *w,
+                           double nu, const double *rho, double *u, void *ws, size_t ws_bytes, hipStream_t stream);
+int dmk_residual_backward_pswf(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, const dmk_pswf *w,
+                               double nu, const double *rho, const double *gu, double *grad_rho, double *grad_x,
+                               void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * Timing hook: from now on, record the device events `start` right before and
  * `stop` right after the pair kernel of every dmk_residual_eval /
  * dmk_residual_backward call, on that call's stream (the strength gather

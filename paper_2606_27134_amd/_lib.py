@@ -34,6 +34,14 @@ class dmk_bins(ctypes.Structure):
     ]
 
 
+PSWF_MAXTERMS = 32
+
+
+class dmk_pswf(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double), ("nterms64", ctypes.c_int32), ("nterms32", ctypes.c_int32),
+                ("cheb", (ctypes.c_double * PSWF_MAXTERMS) * 4)]
+
+
 class DmkError(RuntimeError):
     def __init__(self, code, where):
         self.code = code
@@ -69,6 +77,15 @@ def load():
     lib.dmk_residual_backward.argtypes = [G, B, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, P,
                                           P, P, P, ctypes.c_size_t, P]
     lib.dmk_residual_backward.restype = ctypes.c_int
+    W = ctypes.POINTER(dmk_pswf)
+    lib.dmk_pswf_window.argtypes = [ctypes.c_double, W]
+    lib.dmk_pswf_window.restype = ctypes.c_int
+    lib.dmk_residual_eval_pswf.argtypes = [G, B, ctypes.c_int, ctypes.c_int, W, ctypes.c_double, P, P, P,
+                                           ctypes.c_size_t, P]
+    lib.dmk_residual_eval_pswf.restype = ctypes.c_int
+    lib.dmk_residual_backward_pswf.argtypes = [G, B, ctypes.c_int, ctypes.c_int, W, ctypes.c_double, P, P, P, P,
+                                               P, ctypes.c_size_t, P]
+    lib.dmk_residual_backward_pswf.restype = ctypes.c_int
     lib.dmk_residual_set_kernel_events.argtypes = [P, P]
     lib.dmk_residual_set_kernel_events.restype = ctypes.c_int
     lib.dmk_strerror.argtypes = [ctypes.c_int]
@@ -130,6 +147,26 @@ def dmk_residual_backward(grid, bins, kernel, prec, sigma, rc, rho_ptr, gu_ptr, 
                                             ctypes.c_void_p(gu_ptr), ctypes.c_void_p(grho_ptr),
                                             ctypes.c_void_p(gx_ptr), ctypes.c_void_p(ws_ptr), int(ws_bytes),
                                             ctypes.c_void_p(stream)))
+
+
+def dmk_pswf_window(c: float, w: dmk_pswf) -> int:
+    return int(load().dmk_pswf_window(float(c), ctypes.byref(w)))
+
+
+def dmk_residual_eval_pswf(grid, bins, kernel, prec, w, nu, rho_ptr, u_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return int(load().dmk_residual_eval_pswf(ctypes.byref(grid), ctypes.byref(bins), int(kernel), int(prec),
+                                             ctypes.byref(w), float(nu), ctypes.c_void_p(rho_ptr),
+                                             ctypes.c_void_p(u_ptr), ctypes.c_void_p(ws_ptr), int(ws_bytes),
+                                             ctypes.c_void_p(stream)))
+
+
+def dmk_residual_backward_pswf(grid, bins, kernel, prec, w, nu, rho_ptr, gu_ptr, grho_ptr, gx_ptr, ws_ptr,
+                               ws_bytes, stream) -> int:
+    return int(load().dmk_residual_backward_pswf(ctypes.byref(grid), ctypes.byref(bins), int(kernel), int(prec),
+                                                 ctypes.byref(w), float(nu), ctypes.c_void_p(rho_ptr),
+                                                 ctypes.c_void_p(gu_ptr), ctypes.c_void_p(grho_ptr),
+                                                 ctypes.c_void_p(gx_ptr), ctypes.c_void_p(ws_ptr), int(ws_bytes),
+                                                 ctypes.c_void_p(stream)))
 
 
 def dmk_residual_set_kernel_events(start_ptr: int, stop_ptr: int) -> int:

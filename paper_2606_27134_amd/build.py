@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdmkloc.so")
-SOURCES = ["dmk_bin.hip", "dmk_residual.hip"]
+SOURCES = ["dmk_bin.hip", "dmk_residual.hip", "dmk_pswf.cpp"]
 ARCH = os.environ.get("DMK_OFFLOAD_ARCH", "gfx950")
 
 
@@ -41,7 +41,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for s in SOURCES:
         src = os.path.join(CSRC, s)
-        obj = os.path.join(ROOT, "_build", s.replace(".hip", ".o"))
+        obj = os.path.join(ROOT, "_build", os.path.splitext(s)[0] + ".o")
         cmd = [hipcc()] + flags() + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

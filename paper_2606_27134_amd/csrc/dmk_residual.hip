@@ -151,22 +151,60 @@ struct KNorm {
     static constexpr double c = KERN == 0 ? INV4PI : INV8PI;
 };
 
+// Window of the split: WIN_GAUSS (sigma = width) or WIN_PSWF (sigma = support
+// radius nu), the latter as Chebyshev series in u = 2 t^2 - 1 of phi,
+// (1 - Phi)/t, phi'/t and phi'' with MAXT<T> terms (zero-padded by the host).
+constexpr int WIN_GAUSS = 0, WIN_PSWF = 1;
+template <typename T>
+struct WinMax {
+    static constexpr int n = sizeof(T) == 4 ? DMK_PSWF_MAXTERMS32 : DMK_PSWF_MAXTERMS;
+};
+template <typename T>
+struct WinCoef {
+    T c[4][WinMax<T>::n];
+};
+struct NoWin {
+    int unused;
+};
+template <int WIN, typename T>
+using WinArg = typename std::conditional<WIN == WIN_PSWF, WinCoef<T>, NoWin>::type;
+
 template <typename T>
 struct Rad {
-    T ri, r, t, t2, phi, Phi;
+    T ri, r, t, t2, phi, Phi, dphi, d2phi;  // window values at t: phi, Phi, phi', phi''
 };
 
 // radial quantities of a pair at squared distance r2 (isig = 1/sigma,
-// kexp = -log2(e)/sigma^2 for the FP32 exponential)
-template <typename T>
-__device__ inline Rad<T> radial(T r2, T isig, T isig2, T kexp)
+// kexp = -log2(e)/sigma^2 for the FP32 exponential of the Gaussian window)
+template <int WIN, typename T, typename W>
+__device__ inline Rad<T> radial(T r2, T isig, T isig2, T kexp, const W &wc)
 {
     Rad<T> R;
     R.ri = rsqrt_(r2);
     R.r = r2 * R.ri;
     R.t = R.r * isig;
     R.t2 = r2 * isig2;
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (WIN == WIN_PSWF) {
+        // Chebyshev polynomials T_k(u) by their recurrence, one sum per function
+        constexpr int NT = WinMax<T>::n;
+        const T u = (T)2 * R.t2 - (T)1;
+        T g[4];
+        for (int q = 0; q < 4; ++q) g[q] = wc.c[q][0] + wc.c[q][1] * u;
+        T tkm1 = (T)1, tk = u;
+#pragma unroll
+        for (int k = 2; k < NT; ++k) {
+            const T tk1 = (T)2 * u * tk - tkm1;
+            for (int q = 0; q < 4; ++q) g[q] += wc.c[q][k] * tk1;
+            tkm1 = tk;
+            tk = tk1;
+        }
+        (void)kexp;
+        R.phi = g[0];
+        R.Phi = (T)1 - R.t * g[1];
+        R.dphi = R.t * g[2];
+        R.d2phi = g[3];
+        return R;
+    } else if constexpr (sizeof(T) == 4) {
         // one exponential serves both the window phi(t) = e^{-t^2}/sqrt(pi) and
         // Phi(t) = erfc(t) = e^{-t^2} erfcx(t); erfcx from the fitted polynomial
         const float e = __builtin_amdgcn_exp2f(r2 * kexp);
@@ -181,14 +219,17 @@ __device__ inline Rad<T> radial(T r2, T isig, T isig2, T kexp)
         R.phi = expneg_(R.t2) * (T)INV_SQRT_PI;
         R.Phi = erfc_(R.t);
     }
+    (void)wc;
+    R.dphi = (T)-2 * R.t * R.phi;                  // phi' = -2 t phi
+    R.d2phi = ((T)4 * R.t2 - (T)2) * R.phi;         // phi'' = (4 t^2 - 2) phi
     return R;
 }
 
 // forward pair contribution v[MOUT]; ps = source strengths
-template <int KERN, typename T>
-__device__ inline void pair_fwd(const T d[3], T r2, T isig, T isig2, T kexp, const T *ps, T *v)
+template <int KERN, int WIN, typename T, typename W>
+__device__ inline void pair_fwd(const T d[3], T r2, T isig, T isig2, T kexp, const W &wc, const T *ps, T *v)
 {
-    const Rad<T> R = radial(r2, isig, isig2, kexp);
+    const Rad<T> R = radial<WIN, T>(r2, isig, isig2, kexp, wc);
     const T tphi2 = (T)2 * R.t * R.phi;
     if constexpr (KERN == 0) {
         v[0] = R.Phi * R.ri * ps[0];
@@ -202,9 +243,9 @@ __device__ inline void pair_fwd(const T d[3], T r2, T isig, T isig2, T kexp, con
     } else if constexpr (KERN == 2) {
         const T ri2 = R.ri * R.ri;
         const T ri3 = ri2 * R.ri;
-        const T t3phi = R.t2 * R.t * R.phi;
-        const T P = (T)4 * t3phi * ri3;
-        const T Qc = -(T)6 * (R.Phi + tphi2 + (T)(4.0 / 3.0) * t3phi) * ri3 * ri2;
+        const T t2dphi = R.t2 * R.dphi;
+        const T P = (T)-2 * t2dphi * ri3;                                       // Td = -2 t^2 phi'
+        const T Qc = -(T)6 * (R.Phi + tphi2 - (T)(2.0 / 3.0) * t2dphi) * ri3 * ri2;  // To
         T rd[3], rtd[3];
         for (int l = 0; l < 3; ++l) {
             rd[l] = ps[3 * l + 0] * d[0] + ps[3 * l + 1] * d[1] + ps[3 * l + 2] * d[2];
@@ -223,13 +264,17 @@ __device__ inline void pair_fwd(const T d[3], T r2, T isig, T isig2, T kexp, con
 }
 
 // adjoint pair contribution v[MIN + 3] = (d grad_rho_t, d grad_x_t);
-// ps = (rho_s, G_s), pt = (rho_t, G_t); d = x_t - x_s (+ image).
-template <int KERN, typename T>
-__device__ inline void pair_bwd(const T d[3], T r2, T isig, T isig2, T kexp, const T *ps, const T *pt, T *v)
+// ps = (rho_s, G_s), pt = (rho_t, G_t); d = x_t - x_s (+ image).  Radial
+// derivatives d/dt of the window parts: Sd' = -4 phi - 2 t phi',
+// So' = 2 t phi', Td' = -4 t phi' - 2 t^2 phi'', To' = (2/3)(t phi' - t^2 phi''),
+// Oo' = 2 t phi' (with Phi' = -2 phi); d/dr = (1/sigma) d/dt.
+template <int KERN, int WIN, typename T, typename W>
+__device__ inline void pair_bwd(const T d[3], T r2, T isig, T isig2, T kexp, const W &wc, const T *ps, const T *pt,
+                                T *v)
 {
     constexpr int MIN = KDim<KERN>::MIN;
     const T *rs = ps, *Gs = ps + MIN, *rt = pt, *Gt = pt + MIN;
-    const Rad<T> R = radial(r2, isig, isig2, kexp);
+    const Rad<T> R = radial<WIN, T>(r2, isig, isig2, kexp, wc);
     const T tphi2 = (T)2 * R.t * R.phi;
     const T ri2 = R.ri * R.ri;
     const T ri3 = ri2 * R.ri;
@@ -243,8 +288,9 @@ __device__ inline void pair_bwd(const T d[3], T r2, T isig, T isig2, T kexp, con
         const T Sd = R.Phi - tphi2, So = R.Phi + tphi2;
         const T A = Sd * R.ri;
         const T B = So * ri3;
-        const T dSd = (T)4 * R.phi * (R.t2 - (T)1);
-        const T dSo = -(T)4 * R.t2 * R.phi;
+        const T tdphi = R.t * R.dphi;
+        const T dSd = (T)-4 * R.phi - (T)2 * tdphi;
+        const T dSo = (T)2 * tdphi;
         const T Ar = dSd * isig * ri2 - Sd * ri3;                      // A'(r)/r
         const T Br = dSo * isig * ri2 * ri2 - (T)3 * So * ri3 * ri2;   // B'(r)/r
         const T dGs = d[0] * Gs[0] + d[1] * Gs[1] + d[2] * Gs[2];
@@ -259,14 +305,14 @@ __device__ inline void pair_bwd(const T d[3], T r2, T isig, T isig2, T kexp, con
             v[3 + c] = sd * d[c] + B * (Gt[c] * drs + rs[c] * dGt + Gs[c] * drt + rt[c] * dGs);
         }
     } else if constexpr (KERN == 2) {
-        const T t3phi = R.t2 * R.t * R.phi;
-        const T Td = (T)4 * t3phi;
-        const T To = R.Phi + tphi2 + (T)(4.0 / 3.0) * t3phi;
+        const T t2dphi = R.t2 * R.dphi, tdphi = R.t * R.dphi, t2d2phi = R.t2 * R.d2phi;
+        const T Td = (T)-2 * t2dphi;
+        const T To = R.Phi + tphi2 - (T)(2.0 / 3.0) * t2dphi;
         const T P = Td * ri3;
         const T ri5 = ri3 * ri2;
         const T Qc = -(T)6 * To * ri5;
-        const T dTd = (T)4 * R.t2 * R.phi * ((T)3 - (T)2 * R.t2);
-        const T dTo = -(T)(8.0 / 3.0) * R.t2 * R.t2 * R.phi;
+        const T dTd = (T)-4 * tdphi - (T)2 * t2d2phi;
+        const T dTo = (T)(2.0 / 3.0) * (tdphi - t2d2phi);
         const T Pr = dTd * isig * ri2 * ri2 - (T)3 * Td * ri5;
         const T Qr = -(T)6 * (dTo * isig * ri3 * ri3 - (T)5 * To * ri5 * ri2);
         const T dGs = d[0] * Gs[0] + d[1] * Gs[1] + d[2] * Gs[2];
@@ -300,7 +346,7 @@ __device__ inline void pair_bwd(const T d[3], T r2, T isig, T isig2, T kexp, con
     } else {
         const T Oo = R.Phi + tphi2;
         const T f = Oo * ri3;
-        const T dOo = -(T)4 * R.t2 * R.phi;
+        const T dOo = (T)2 * R.t * R.dphi;
         const T fr = dOo * isig * ri2 * ri2 - (T)3 * Oo * ri3 * ri2;
         // grad_rho_t = f (Gs x d)
         v[0] = f * (Gs[1] * d[2] - Gs[2] * d[1]);
@@ -531,8 +577,8 @@ __device__ inline void wave_sum(T *v)
     }
 }
 
-template <int KERN, typename FP, bool BWD>
-__global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
+template <int KERN, typename FP, bool BWD, int WIN>
+__global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P, WinArg<WIN, FP> WC)
 {
     using C = Cfg<KERN, FP, BWD>;
     using T = FP;
@@ -728,9 +774,9 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P)
         const T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         const bool ok = (r2 > (T)0) && (r2 < rc2);
         if constexpr (BWD)
-            pair_bwd<KERN, T>(d, r2, isig, isig2, kexp, ps, pt, v);
+            pair_bwd<KERN, WIN, T>(d, r2, isig, isig2, kexp, WC, ps, pt, v);
         else
-            pair_fwd<KERN, T>(d, r2, isig, isig2, kexp, ps, v);
+            pair_fwd<KERN, WIN, T>(d, r2, isig, isig2, kexp, WC, ps, v);
         for (int c = 0; c < C::NC; ++c) v[c] = ok ? v[c] : (T)0;
     };
 
@@ -933,29 +979,38 @@ size_t ws_need(int64_t N, int kernel, int backward)
     return (size_t)(sizeof(double) * ncomp * (N > 0 ? N : 1) + 256);
 }
 
-template <int KERN, typename FP, bool BWD>
-void launch_one(const ResParams &P, hipStream_t s)
+template <int KERN, typename FP, bool BWD, int WIN>
+void launch_one(const ResParams &P, const dmk_pswf *w, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_residual<KERN, FP, BWD>), dim3((unsigned)P.ntiles), dim3(Cfg<KERN, FP, BWD>::NW * WAVE), 0,
-                       s, P);
+    WinArg<WIN, FP> wc{};
+    if constexpr (WIN == WIN_PSWF) {
+        // the series of the precision's path, zero past the terms it keeps
+        const int nt = sizeof(FP) == 4 ? w->nterms32 : w->nterms64;
+        for (int q = 0; q < 4; ++q)
+            for (int k = 0; k < WinMax<FP>::n; ++k) wc.c[q][k] = k < nt ? (FP)w->cheb[q][k] : (FP)0;
+    } else {
+        (void)w;
+    }
+    hipLaunchKernelGGL((k_residual<KERN, FP, BWD, WIN>), dim3((unsigned)P.ntiles),
+                       dim3(Cfg<KERN, FP, BWD>::NW * WAVE), 0, s, P, wc);
 }
 
-template <bool BWD>
-int dispatch(int kernel, int prec, const ResParams &P, hipStream_t s)
+template <bool BWD, int WIN>
+int dispatch(int kernel, int prec, const ResParams &P, const dmk_pswf *w, hipStream_t s)
 {
     if (prec == DMK_FP64) {
         switch (kernel) {
-        case 0: launch_one<0, double, BWD>(P, s); break;
-        case 1: launch_one<1, double, BWD>(P, s); break;
-        case 2: launch_one<2, double, BWD>(P, s); break;
-        default: launch_one<3, double, BWD>(P, s); break;
+        case 0: launch_one<0, double, BWD, WIN>(P, w, s); break;
+        case 1: launch_one<1, double, BWD, WIN>(P, w, s); break;
+        case 2: launch_one<2, double, BWD, WIN>(P, w, s); break;
+        default: launch_one<3, double, BWD, WIN>(P, w, s); break;
         }
     } else {
         switch (kernel) {
-        case 0: launch_one<0, float, BWD>(P, s); break;
-        case 1: launch_one<1, float, BWD>(P, s); break;
-        case 2: launch_one<2, float, BWD>(P, s); break;
-        default: launch_one<3, float, BWD>(P, s); break;
+        case 0: launch_one<0, float, BWD, WIN>(P, w, s); break;
+        case 1: launch_one<1, float, BWD, WIN>(P, w, s); break;
+        case 2: launch_one<2, float, BWD, WIN>(P, w, s); break;
+        default: launch_one<3, float, BWD, WIN>(P, w, s); break;
         }
     }
     return hipGetLastError() == hipSuccess ? DMK_OK : DMK_EHIP;
@@ -999,12 +1054,15 @@ extern "C" int dmk_residual_set_kernel_events(hipEvent_t start, hipEvent_t stop)
 }
 
 namespace {
-// launch the pair kernel between the optional timing events
+// launch the pair kernel between the optional timing events; w selects the
+// PSWF window (null: Gaussian)
 template <bool BWD>
-int launch_timed(int kernel, int prec, const ResParams &P, hipStream_t s)
+int launch_timed(int kernel, int prec, const ResParams &P, const dmk_pswf *w, hipStream_t s)
 {
     if (g_kernel_ev_start && hipEventRecord(g_kernel_ev_start, s) != hipSuccess) return DMK_EHIP;
-    const int st = P.ntiles > 0 ? dispatch<BWD>(kernel, prec, P, s) : DMK_OK;
+    int st = DMK_OK;
+    if (P.ntiles > 0)
+        st = w ? dispatch<BWD, WIN_PSWF>(kernel, prec, P, w, s) : dispatch<BWD, WIN_GAUSS>(kernel, prec, P, w, s);
     if (st == DMK_OK && g_kernel_ev_stop && hipEventRecord(g_kernel_ev_stop, s) != hipSuccess) return DMK_EHIP;
     return st;
 }
@@ -1019,9 +1077,12 @@ extern "C" size_t dmk_residual_ws_bytes(const dmk_grid *grid, const dmk_bins *bi
     return ws_need(bins->N, kernel, backward);
 }
 
-extern "C" int dmk_residual_eval(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma,
-                                 double rc, const double *rho, double *u, void *ws, size_t ws_bytes,
-                                 hipStream_t stream)
+namespace {
+
+// shared by the Gaussian and PSWF entry points (w null: Gaussian split of
+// width sigma with cutoff rc; else the PSWF split, sigma = rc = nu)
+int eval_impl(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma, double rc,
+              const dmk_pswf *w, const double *rho, double *u, void *ws, size_t ws_bytes, hipStream_t stream)
 {
     int rc_ = check_call(grid, bins, kernel, prec, sigma, rc);
     if (rc_ != DMK_OK) return rc_;
@@ -1035,12 +1096,12 @@ extern "C" int dmk_residual_eval(const dmk_grid *grid, const dmk_bins *bins, int
     if (hipGetLastError() != hipSuccess) return DMK_EHIP;
     ResParams P = make_params(grid, bins, sigma, rc, pl);
     P.out0 = u;
-    return launch_timed<false>(kernel, prec, P, stream);
+    return launch_timed<false>(kernel, prec, P, w, stream);
 }
 
-extern "C" int dmk_residual_backward(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec,
-                                     double sigma, double rc, const double *rho, const double *gu, double *grad_rho,
-                                     double *grad_x, void *ws, size_t ws_bytes, hipStream_t stream)
+int backward_impl(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma, double rc,
+                  const dmk_pswf *w, const double *rho, const double *gu, double *grad_rho, double *grad_x,
+                  void *ws, size_t ws_bytes, hipStream_t stream)
 {
     int rc_ = check_call(grid, bins, kernel, prec, sigma, rc);
     if (rc_ != DMK_OK) return rc_;
@@ -1051,8 +1112,54 @@ extern "C" int dmk_residual_backward(const dmk_grid *grid, const dmk_bins *bins,
     double *pl = (double *)ws;
     hipLaunchKernelGGL(k_gather_payload, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, rho, gu,
                        bins->perm, N, m_in_of(kernel), m_out_of(kernel), pl);
+    if (hipGetLastError() != hipSuccess) return DMK_EHIP;
     ResParams P = make_params(grid, bins, sigma, rc, pl);
     P.out0 = grad_rho;
     P.out1 = grad_x;
-    return launch_timed<true>(kernel, prec, P, stream);
+    return launch_timed<true>(kernel, prec, P, w, stream);
+}
+
+int check_window(const dmk_pswf *w)
+{
+    if (!w) return DMK_EINVAL;
+    if (!(w->c > 0.0) || !(w->c <= DMK_PSWF_CMAX) || w->nterms64 < 1 || w->nterms64 > DMK_PSWF_MAXTERMS ||
+        w->nterms32 < 1 || w->nterms32 > DMK_PSWF_MAXTERMS32)
+        return DMK_EUNSUPPORTED;
+    return DMK_OK;
+}
+
+}  // namespace
+
+extern "C" int dmk_residual_eval(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma,
+                                 double rc, const double *rho, double *u, void *ws, size_t ws_bytes,
+                                 hipStream_t stream)
+{
+    return eval_impl(grid, bins, kernel, prec, sigma, rc, nullptr, rho, u, ws, ws_bytes, stream);
+}
+
+extern "C" int dmk_residual_backward(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec,
+                                     double sigma, double rc, const double *rho, const double *gu, double *grad_rho,
+                                     double *grad_x, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    return backward_impl(grid, bins, kernel, prec, sigma, rc, nullptr, rho, gu, grad_rho, grad_x, ws, ws_bytes,
+                         stream);
+}
+
+extern "C" int dmk_residual_eval_pswf(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec,
+                                      const dmk_pswf *w, double nu, const double *rho, double *u, void *ws,
+                                      size_t ws_bytes, hipStream_t stream)
+{
+    const int st = check_window(w);
+    if (st != DMK_OK) return st;
+    return eval_impl(grid, bins, kernel, prec, nu, nu, w, rho, u, ws, ws_bytes, stream);
+}
+
+extern "C" int dmk_residual_backward_pswf(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec,
+                                          const dmk_pswf *w, double nu, const double *rho, const double *gu,
+                                          double *grad_rho, double *grad_x, void *ws, size_t ws_bytes,
+                                          hipStream_t stream)
+{
+    const int st = check_window(w);
+    if (st != DMK_OK) return st;
+    return backward_impl(grid, bins, kernel, prec, nu, nu, w, rho, gu, grad_rho, grad_x, ws, ws_bytes, stream);
 }

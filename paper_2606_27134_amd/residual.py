@@ -106,22 +106,47 @@ def workspace(bins: Bins, kernel, prec, backward: bool) -> torch.Tensor:
     return torch.empty(max(nb, 8) // 8 + 32, dtype=torch.float64, device=bins._arena.device)
 
 
-def residual_eval(bins: Bins, kernel, prec, sigma: float, rc: float, rho: torch.Tensor, out=None, ws=None):
+_PSWF = {}
+
+
+def pswf_window(c: float):
+    """Host description of the PSWF window of bandwidth c (computed by the
+    library, cached per c)."""
+    c = float(c)
+    if c not in _PSWF:
+        w = L.dmk_pswf()
+        code = L.dmk_pswf_window(c, w)
+        if code != L.DMK_OK:
+            raise L.DmkError(code, "dmk_pswf_window")
+        _PSWF[c] = w
+    return _PSWF[c]
+
+
+def residual_eval(bins: Bins, kernel, prec, sigma: float, rc: float, rho: torch.Tensor, out=None, ws=None,
+                  pswf_c: float = None):
+    """Residual sum u[N, m_out].  Gaussian split of width sigma with cutoff rc,
+    or, with pswf_c, the PSWF split of bandwidth pswf_c and support rc
+    (sigma is then unused)."""
     k, p = _kid(kernel), _pid(prec)
     _require_dev_f64(rho, "rho", (bins.N, L.M_IN[k]))
     u = out if out is not None else torch.empty((bins.N, L.M_OUT[k]), dtype=torch.float64, device=rho.device)
     _require_dev_f64(u, "u", (bins.N, L.M_OUT[k]))
     if ws is None:
         ws = workspace(bins, k, p, False)
-    code = L.dmk_residual_eval(bins.grid, bins.c, k, p, sigma, rc, rho.data_ptr(), u.data_ptr(), ws.data_ptr(),
-                               ws.numel() * 8, _stream())
+    if pswf_c is None:
+        code = L.dmk_residual_eval(bins.grid, bins.c, k, p, sigma, rc, rho.data_ptr(), u.data_ptr(),
+                                   ws.data_ptr(), ws.numel() * 8, _stream())
+    else:
+        code = L.dmk_residual_eval_pswf(bins.grid, bins.c, k, p, pswf_window(pswf_c), rc, rho.data_ptr(),
+                                        u.data_ptr(), ws.data_ptr(), ws.numel() * 8, _stream())
     if code != L.DMK_OK:
         raise L.DmkError(code, "dmk_residual_eval")
     return u
 
 
 def residual_backward(bins: Bins, kernel, prec, sigma: float, rc: float, rho: torch.Tensor, gu: torch.Tensor,
-                      out=None, ws=None):
+                      out=None, ws=None, pswf_c: float = None):
+    """Vector-Jacobian product of :func:`residual_eval` (same split arguments)."""
     k, p = _kid(kernel), _pid(prec)
     _require_dev_f64(rho, "rho", (bins.N, L.M_IN[k]))
     _require_dev_f64(gu, "gu", (bins.N, L.M_OUT[k]))
@@ -132,8 +157,13 @@ def residual_backward(bins: Bins, kernel, prec, sigma: float, rc: float, rho: to
         grho, gx = out
     if ws is None:
         ws = workspace(bins, k, p, True)
-    code = L.dmk_residual_backward(bins.grid, bins.c, k, p, sigma, rc, rho.data_ptr(), gu.data_ptr(),
-                                   grho.data_ptr(), gx.data_ptr(), ws.data_ptr(), ws.numel() * 8, _stream())
+    if pswf_c is None:
+        code = L.dmk_residual_backward(bins.grid, bins.c, k, p, sigma, rc, rho.data_ptr(), gu.data_ptr(),
+                                       grho.data_ptr(), gx.data_ptr(), ws.data_ptr(), ws.numel() * 8, _stream())
+    else:
+        code = L.dmk_residual_backward_pswf(bins.grid, bins.c, k, p, pswf_window(pswf_c), rc, rho.data_ptr(),
+                                            gu.data_ptr(), grho.data_ptr(), gx.data_ptr(), ws.data_ptr(),
+                                            ws.numel() * 8, _stream())
     if code != L.DMK_OK:
         raise L.DmkError(code, "dmk_residual_backward")
     return grho, gx
@@ -149,6 +179,7 @@ class ResidualSpec:
     prec: str
     sigma: float
     rc: float
+    pswf_c: float = None   # PSWF split of bandwidth pswf_c and support rc instead of the Gaussian
 
 
 class DmkResidual(torch.autograd.Function):
@@ -168,7 +199,7 @@ class DmkResidual(torch.autograd.Function):
             bins = tree_bin(spec.L, spec.D, spec.n, x_)
         elif bins.N != x_.shape[0]:
             raise ValueError("bins were built for %d points, x has %d" % (bins.N, x_.shape[0]))
-        u = residual_eval(bins, spec.kernel, spec.prec, spec.sigma, spec.rc, rho_)
+        u = residual_eval(bins, spec.kernel, spec.prec, spec.sigma, spec.rc, rho_, pswf_c=spec.pswf_c)
         ctx.spec = spec
         ctx.bins = bins
         ctx.save_for_backward(rho_)
@@ -178,7 +209,8 @@ class DmkResidual(torch.autograd.Function):
     def backward(ctx, gu):
         (rho_,) = ctx.saved_tensors
         s = ctx.spec
-        grho, gx = residual_backward(ctx.bins, s.kernel, s.prec, s.sigma, s.rc, rho_, gu.contiguous())
+        grho, gx = residual_backward(ctx.bins, s.kernel, s.prec, s.sigma, s.rc, rho_, gu.contiguous(),
+                                     pswf_c=s.pswf_c)
         return gx, grho, None, None
 
 

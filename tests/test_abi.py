@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2606_27134_amd import _lib as L
@@ -102,3 +103,34 @@ def test_kernel_events_argument_check():
     assert L.dmk_residual_set_kernel_events(1 << 40, 0) == L.DMK_EINVAL
     assert L.dmk_residual_set_kernel_events(0, 1 << 40) == L.DMK_EINVAL
     assert L.dmk_residual_set_kernel_events(0, 0) == L.DMK_OK
+
+
+def test_pswf_window_host_matches_oracle_window():
+    # the library's host-side PSWF (its own eigen-solve and Chebyshev fit)
+    # against the oracle's PSWF window, at many points of the support
+    from numpy.polynomial import chebyshev as C
+    from oracle.pswf import PswfWindow
+    for c in (7.0, 14.5, 29.0, 40.0):
+        w = L.dmk_pswf()
+        assert L.dmk_pswf_window(c, w) == L.DMK_OK
+        assert 1 <= w.nterms32 <= 24 and 1 <= w.nterms64 <= L.PSWF_MAXTERMS
+        O = PswfWindow(c)
+        t = np.linspace(1e-3, 1 - 1e-3, 997)
+        u = 2 * t * t - 1
+        cf = [np.array([w.cheb[q][k] for k in range(w.nterms64)]) for q in range(4)]
+        np.testing.assert_allclose(C.chebval(u, cf[0]), O.phi_at(t), rtol=0, atol=2e-14)
+        np.testing.assert_allclose(1 - t * C.chebval(u, cf[1]), O.Phi_at(t), rtol=0, atol=2e-14)
+        np.testing.assert_allclose(t * C.chebval(u, cf[2]), O.dphi_at(t), rtol=0, atol=2e-14 * c)
+        np.testing.assert_allclose(C.chebval(u, cf[3]), O.d2phi_at(t), rtol=0, atol=2e-14 * c * c)
+
+
+def test_pswf_window_argument_errors():
+    w = L.dmk_pswf()
+    assert L.dmk_pswf_window(0.0, w) == L.DMK_EUNSUPPORTED
+    assert L.dmk_pswf_window(41.0, w) == L.DMK_EUNSUPPORTED
+    assert L.dmk_pswf_window(float("nan"), w) == L.DMK_EUNSUPPORTED
+    g = L.make_grid((1, 1, 1), 3, (8, 8, 8))
+    b = L.dmk_bins()
+    P = 1 << 40
+    bad = L.dmk_pswf()  # c = 0: not a window
+    assert L.dmk_residual_eval_pswf(g, b, 0, 0, bad, 0.1, P, P, P, 1 << 30, 0) == L.DMK_EUNSUPPORTED
