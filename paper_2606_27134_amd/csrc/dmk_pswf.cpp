@@ -171,7 +171,8 @@ extern "C" int dmk_pswf_window(double c, dmk_pswf *w)
         }
     // terms kept: the tail below the precision of each path
     for (int pass = 0; pass < 2; ++pass) {
-        const double tol = pass == 0 ? 1e-16 : 2e-9;
+        // (the FP64 threshold sits just above the rounding floor of the fit)
+        const double tol = pass == 0 ? 5e-14 : 2e-9;
         int n = 1;
         for (int q = 0; q < 4; ++q) {
             double sc = 0.0;

@@ -153,21 +153,18 @@ struct KNorm {
 
 // Window of the split: WIN_GAUSS (sigma = width) or WIN_PSWF (sigma = support
 // radius nu), the latter as Chebyshev series in u = 2 t^2 - 1 of phi,
-// (1 - Phi)/t, phi'/t and phi'' with MAXT<T> terms (zero-padded by the host).
-constexpr int WIN_GAUSS = 0, WIN_PSWF = 1;
-template <typename T>
-struct WinMax {
-    static constexpr int n = sizeof(T) == 4 ? DMK_PSWF_MAXTERMS32 : DMK_PSWF_MAXTERMS;
-};
-template <typename T>
+// (1 - Phi)/t, phi'/t and phi'' with WIN - 1 terms (WIN > 1; zero-padded by
+// the host past the terms the window needs).
+constexpr int WIN_GAUSS = 0;
+template <int NT, typename T>
 struct WinCoef {
-    T c[4][WinMax<T>::n];
+    T c[4][NT];
 };
 struct NoWin {
     int unused;
 };
 template <int WIN, typename T>
-using WinArg = typename std::conditional<WIN == WIN_PSWF, WinCoef<T>, NoWin>::type;
+using WinArg = typename std::conditional<(WIN > 1), WinCoef<(WIN > 1 ? WIN - 1 : 1), T>, NoWin>::type;
 
 template <typename T>
 struct Rad {
@@ -184,9 +181,9 @@ __device__ inline Rad<T> radial(T r2, T isig, T isig2, T kexp, const W &wc)
     R.r = r2 * R.ri;
     R.t = R.r * isig;
     R.t2 = r2 * isig2;
-    if constexpr (WIN == WIN_PSWF) {
+    if constexpr (WIN > 1) {
         // Chebyshev polynomials T_k(u) by their recurrence, one sum per function
-        constexpr int NT = WinMax<T>::n;
+        constexpr int NT = WIN - 1;
         const T u = (T)2 * R.t2 - (T)1;
         T g[4];
         for (int q = 0; q < 4; ++q) g[q] = wc.c[q][0] + wc.c[q][1] * u;
@@ -983,11 +980,11 @@ template <int KERN, typename FP, bool BWD, int WIN>
 void launch_one(const ResParams &P, const dmk_pswf *w, hipStream_t s)
 {
     WinArg<WIN, FP> wc{};
-    if constexpr (WIN == WIN_PSWF) {
+    if constexpr (WIN > 1) {
         // the series of the precision's path, zero past the terms it keeps
         const int nt = sizeof(FP) == 4 ? w->nterms32 : w->nterms64;
         for (int q = 0; q < 4; ++q)
-            for (int k = 0; k < WinMax<FP>::n; ++k) wc.c[q][k] = k < nt ? (FP)w->cheb[q][k] : (FP)0;
+            for (int k = 0; k < WIN - 1; ++k) wc.c[q][k] = k < nt ? (FP)w->cheb[q][k] : (FP)0;
     } else {
         (void)w;
     }
@@ -1061,8 +1058,20 @@ int launch_timed(int kernel, int prec, const ResParams &P, const dmk_pswf *w, hi
 {
     if (g_kernel_ev_start && hipEventRecord(g_kernel_ev_start, s) != hipSuccess) return DMK_EHIP;
     int st = DMK_OK;
-    if (P.ntiles > 0)
-        st = w ? dispatch<BWD, WIN_PSWF>(kernel, prec, P, w, s) : dispatch<BWD, WIN_GAUSS>(kernel, prec, P, w, s);
+    if (P.ntiles > 0) {
+        if (!w) {
+            st = dispatch<BWD, WIN_GAUSS>(kernel, prec, P, w, s);
+        } else {
+            // PSWF: Chebyshev series of 16 / 24 terms (FP32) or 24 / 32 (FP64),
+            // the shortest that holds the window's terms; WIN = terms + 1
+            const bool f32 = prec == DMK_FP32C;
+            const int nt = f32 ? w->nterms32 : w->nterms64;
+            if (f32)
+                st = nt <= 16 ? dispatch<BWD, 17>(kernel, prec, P, w, s) : dispatch<BWD, 25>(kernel, prec, P, w, s);
+            else
+                st = nt <= 24 ? dispatch<BWD, 25>(kernel, prec, P, w, s) : dispatch<BWD, 33>(kernel, prec, P, w, s);
+        }
+    }
     if (st == DMK_OK && g_kernel_ev_stop && hipEventRecord(g_kernel_ev_stop, s) != hipSuccess) return DMK_EHIP;
     return st;
 }
