@@ -115,3 +115,24 @@ def test_autograd_matches_direct_calls(prec):
     gr2, gx2 = R.residual_backward(b, w.kernel, prec, w.sigma, w.rc, dev(w.rho), G)
     assert host(gx).tobytes() == host(gx2).tobytes()
     assert host(gr).tobytes() == host(gr2).tobytes()
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "stresslet"])
+def test_gradcheck_tiny_pswf(kernel):
+    # the PSWF split (support nu = rc, bandwidth c) through the same autograd Function
+    rng = np.random.default_rng(4)
+    while True:
+        x = rng.random((10, 3))
+        d = x[:, None, :] - x[None, :, :]
+        d -= np.round(d)
+        r = np.sqrt((d ** 2).sum(-1))
+        np.fill_diagonal(r, 1.0)
+        if np.abs(r - 0.45).min() > 0.03 and r.min() > 0.05:
+            break
+    spec = R.ResidualSpec(L=(1, 1, 1), D=3, n=(2, 2, 2), kernel=kernel, prec="fp64", sigma=0.0, rc=0.45,
+                          pswf_c=14.5)
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda", requires_grad=True)
+    rt = torch.tensor(rng.normal(size=(10, W.M_IN[kernel])), dtype=torch.float64, device="cuda",
+                      requires_grad=True)
+    f = lambda a, b: R.dmk_residual(a, b, spec)
+    assert torch.autograd.gradcheck(f, (xt, rt), eps=1e-6, atol=1e-7, rtol=1e-6)
