@@ -929,17 +929,72 @@ __global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P, WinArg
     }
 }
 
-// sorted SoA payload: pl[c][j] = rho[perm[j]][c] (c < m_in), then gu
-__global__ void k_gather_payload(const double *__restrict__ rho, const double *__restrict__ gu,
-                                 const int32_t *__restrict__ perm, int64_t N, int min_, int mout,
+// sorted SoA payload: pl[c][j] = rho[perm[j]][c] (c < m_in), then gu.
+// The gather reads one record of M doubles per point at a random position
+// (perm); every load of a thread is issued before its stores.  Forward: the
+// strengths rho[N][M] themselves.  Adjoint: strengths and cotangent are first
+// interleaved into records of MI + MO doubles in the original order (a
+// coalesced pass), so the random reads touch one record instead of two rows.
+template <int M>
+__global__ void k_gather_payload(const double *__restrict__ rec, const int32_t *__restrict__ perm, int64_t N,
                                  double *__restrict__ pl)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
     const int64_t i = perm[j];
-    for (int c = 0; c < min_; ++c) pl[c * N + j] = rho[i * min_ + c];
-    if (gu)
-        for (int c = 0; c < mout; ++c) pl[(min_ + c) * N + j] = gu[i * mout + c];
+    double v[M];
+    if constexpr (M % 2 == 0) {
+        const double2 *r2 = (const double2 *)(rec + i * M);
+#pragma unroll
+        for (int c = 0; c < M / 2; ++c) {
+            const double2 t = r2[c];
+            v[2 * c] = t.x;
+            v[2 * c + 1] = t.y;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) v[c] = rec[i * M + c];
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) pl[c * N + j] = v[c];
+}
+
+template <int MI, int MO>
+__global__ void k_interleave(const double *__restrict__ rho, const double *__restrict__ gu, int64_t N,
+                             double *__restrict__ rec)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+#pragma unroll
+    for (int c = 0; c < MI; ++c) rec[i * (MI + MO) + c] = rho[i * MI + c];
+#pragma unroll
+    for (int c = 0; c < MO; ++c) rec[i * (MI + MO) + MI + c] = gu[i * MO + c];
+}
+
+template <int MI, int MO>
+void launch_gather(const double *rho, const double *gu, const int32_t *perm, int64_t N, double *pl, double *rec,
+                   hipStream_t s)
+{
+    const dim3 grid((unsigned)((N + 255) / 256));
+    if constexpr (MO == 0) {
+        hipLaunchKernelGGL((k_gather_payload<MI>), grid, dim3(256), 0, s, rho, perm, N, pl);
+    } else {
+        hipLaunchKernelGGL((k_interleave<MI, MO>), grid, dim3(256), 0, s, rho, gu, N, rec);
+        hipLaunchKernelGGL((k_gather_payload<MI + MO>), grid, dim3(256), 0, s, (const double *)rec, perm, N, pl);
+    }
+}
+
+// sorted SoA payload of the call: strengths, then the cotangent (adjoint);
+// rec = scratch of (m_in + m_out) N doubles for the adjoint's records
+void gather_payload(int kernel, bool bwd, const double *rho, const double *gu, const int32_t *perm, int64_t N,
+                    double *pl, double *rec, hipStream_t s)
+{
+    switch (kernel) {
+    case 0: bwd ? launch_gather<1, 1>(rho, gu, perm, N, pl, rec, s) : launch_gather<1, 0>(rho, gu, perm, N, pl, rec, s); break;
+    case 1: bwd ? launch_gather<3, 3>(rho, gu, perm, N, pl, rec, s) : launch_gather<3, 0>(rho, gu, perm, N, pl, rec, s); break;
+    case 2: bwd ? launch_gather<9, 3>(rho, gu, perm, N, pl, rec, s) : launch_gather<9, 0>(rho, gu, perm, N, pl, rec, s); break;
+    default: bwd ? launch_gather<3, 3>(rho, gu, perm, N, pl, rec, s) : launch_gather<3, 0>(rho, gu, perm, N, pl, rec, s); break;
+    }
 }
 
 }  // namespace dmk
@@ -970,10 +1025,12 @@ int check_call(const dmk_grid *g, const dmk_bins *b, int kernel, int prec, doubl
     return DMK_OK;
 }
 
+// workspace: the sorted payload, and for the adjoint the interleaved records
 size_t ws_need(int64_t N, int kernel, int backward)
 {
     const int64_t ncomp = m_in_of(kernel) + (backward ? m_out_of(kernel) : 0);
-    return (size_t)(sizeof(double) * ncomp * (N > 0 ? N : 1) + 256);
+    const size_t one = (size_t)(sizeof(double) * ncomp * (N > 0 ? N : 1));
+    return (backward ? 2 * one : one) + 512;
 }
 
 template <int KERN, typename FP, bool BWD, int WIN>
@@ -1100,8 +1157,7 @@ int eval_impl(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, 
     if (!rho || !u || !ws) return DMK_EINVAL;
     if (ws_bytes < ws_need(N, kernel, 0)) return DMK_ESIZE;
     double *pl = (double *)ws;
-    hipLaunchKernelGGL(k_gather_payload, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, rho,
-                       (const double *)nullptr, bins->perm, N, m_in_of(kernel), m_out_of(kernel), pl);
+    gather_payload(kernel, false, rho, nullptr, bins->perm, N, pl, nullptr, stream);
     if (hipGetLastError() != hipSuccess) return DMK_EHIP;
     ResParams P = make_params(grid, bins, sigma, rc, pl);
     P.out0 = u;
@@ -1119,8 +1175,10 @@ int backward_impl(const dmk_grid *grid, const dmk_bins *bins, int kernel, int pr
     if (!rho || !gu || !grad_rho || !grad_x || !ws) return DMK_EINVAL;
     if (ws_bytes < ws_need(N, kernel, 1)) return DMK_ESIZE;
     double *pl = (double *)ws;
-    hipLaunchKernelGGL(k_gather_payload, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, rho, gu,
-                       bins->perm, N, m_in_of(kernel), m_out_of(kernel), pl);
+    // records after the payload, 256-byte aligned
+    const size_t one = sizeof(double) * (size_t)(m_in_of(kernel) + m_out_of(kernel)) * (size_t)N;
+    double *rec = (double *)(((uintptr_t)ws + one + 255) & ~(uintptr_t)255);
+    gather_payload(kernel, true, rho, gu, bins->perm, N, pl, rec, stream);
     if (hipGetLastError() != hipSuccess) return DMK_EHIP;
     ResParams P = make_params(grid, bins, sigma, rc, pl);
     P.out0 = grad_rho;
