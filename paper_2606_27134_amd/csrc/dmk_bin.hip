@@ -88,30 +88,69 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const int32_t *__restric
     hist[(int64_t)tid * nblk + blockIdx.x] = h[tid];
 }
 
-// exclusive scan of a[0..n) in place, one workgroup of 1024 threads
-__global__ __launch_bounds__(1024) void k_scan_excl(int32_t *__restrict__ a, int64_t n)
+// exclusive scan of a[0..n) in place, one workgroup of 1024 threads.  A
+// chunk of 16 Ki values goes through LDS: coalesced loads, each thread then
+// scans 16 consecutive values serially, the per-thread totals are scanned
+// with wave shuffles and 16 wave totals, and the chunk is written back
+// coalesced.  The LDS index is padded by one word in 32 so that the
+// per-thread reads (stride 16 words) spread over the banks.
+constexpr int SCAN_T = 1024;
+constexpr int SCAN_I = 16;
+constexpr int SCAN_CH = SCAN_T * SCAN_I;
+
+__device__ inline int scan_pad(int i) { return i + (i >> 5); }
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_excl(int32_t *__restrict__ a, int64_t n)
 {
-    __shared__ int s[1024];
-    __shared__ int carry_s;
+    __shared__ int buf[SCAN_CH + SCAN_CH / 32];
+    __shared__ int wsum[SCAN_T / WAVE];
     const int tid = threadIdx.x;
-    if (tid == 0) carry_s = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < n; base += 1024) {
-        int v = (base + tid < n) ? a[base + tid] : 0;
-        s[tid] = v;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            int w = (tid >= off) ? s[tid - off] : 0;
-            __syncthreads();
-            s[tid] += w;
-            __syncthreads();
+    const int lane = tid & (WAVE - 1);
+    const int w = tid / WAVE;
+    int carry = 0;
+    for (int64_t base = 0; base < n; base += SCAN_CH) {
+        const int64_t rem = n - base;
+        const int m = rem < SCAN_CH ? (int)rem : SCAN_CH;
+        for (int r = 0; r < SCAN_I; ++r) {
+            const int i = r * SCAN_T + tid;
+            buf[scan_pad(i)] = i < m ? a[base + i] : 0;
         }
-        int incl = s[tid];
-        int carry = carry_s;
-        if (base + tid < n) a[base + tid] = carry + incl - v;
         __syncthreads();
-        if (tid == 1023) carry_s = carry + incl;
+        int v[SCAN_I];
+        int tsum = 0;
+#pragma unroll
+        for (int i = 0; i < SCAN_I; ++i) {
+            v[i] = buf[scan_pad(tid * SCAN_I + i)];
+            tsum += v[i];
+        }
+        int x = tsum;  // inclusive scan of the thread totals within the wave
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const int y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == WAVE - 1) wsum[w] = x;
         __syncthreads();
+        int wpre = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < SCAN_T / WAVE; ++q) {
+            const int t = wsum[q];
+            wpre += q < w ? t : 0;
+            tot += t;
+        }
+        int run = carry + wpre + x - tsum;
+#pragma unroll
+        for (int i = 0; i < SCAN_I; ++i) {
+            buf[scan_pad(tid * SCAN_I + i)] = run;
+            run += v[i];
+        }
+        carry += tot;
+        __syncthreads();
+        for (int r = 0; r < SCAN_I; ++r) {
+            const int i = r * SCAN_T + tid;
+            if (i < m) a[base + i] = buf[scan_pad(i)];
+        }
+        __syncthreads();  // buf and wsum are rewritten by the next chunk
     }
 }
 
@@ -230,7 +269,7 @@ __global__ void k_axis_tables(BinGeom g, int32_t *__restrict__ nbr, int8_t *__re
 }
 
 // ---------------------------------------------------------------------------
-// 6. target tiles.  One thread walks one leaf column (b0, b1) in z.
+// 6. target tiles, one leaf column (b0, b1) at a time.
 struct TileGeom {
     int n[3];
     const int32_t *bs;
@@ -271,12 +310,37 @@ __device__ inline int cost_key(int64_t cost)
     return 64 - bucket;
 }
 
+// One wavefront per leaf column (b0, b1).  The lanes first stage, for the
+// column's z range, the target count of each box and the slab count (sources
+// in the 9 stencil columns at that z) in LDS; lane 0 then walks the column in
+// z, growing a tile while its targets, its staged sources and its z extent
+// fit.  Columns taller than TW_ZST boxes read the rest from the box starts.
+constexpr int TW_ZST = 2048;
+
+struct ColView {
+    const TileGeom *g;
+    const int *ccol;
+    const int *snt;
+    const int *ssl;
+    int col;
+    __device__ int nt(int z) const { return z < TW_ZST ? snt[z] : box_count(*g, col, z); }
+    // slab count at virtual z in [-1, n2]
+    __device__ int sl(int zv) const
+    {
+        const int zp = phys_z(*g, zv);
+        if (zp < 0) return 0;
+        return zp < TW_ZST ? ssl[zp] : slab_count(*g, ccol, zp);
+    }
+};
+
 template <bool WRITE>
-__global__ void k_tiles(TileGeom g, int32_t *__restrict__ counts, int4 *__restrict__ tiles,
-                        int32_t *__restrict__ tkey)
+__global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int32_t *__restrict__ counts, int4 *__restrict__ tiles,
+                                                int32_t *__restrict__ tkey)
 {
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= g.n[0] * g.n[1]) return;
+    __shared__ int snt[TW_ZST];
+    __shared__ int ssl[TW_ZST];
+    const int col = blockIdx.x;
+    const int lane = threadIdx.x;
     const int b0 = col / g.n[1], b1 = col % g.n[1];
     int ccol[9];
     for (int k = 0; k < 9; ++k) {
@@ -285,16 +349,26 @@ __global__ void k_tiles(TileGeom g, int32_t *__restrict__ counts, int4 *__restri
         ccol[k] = (nb0 < 0 || nb1 < 0) ? -1 : nb0 * g.n[1] + nb1;
     }
     const int n2 = g.n[2];
+    const int zst = n2 < TW_ZST ? n2 : TW_ZST;
+    for (int z = lane; z < zst; z += WAVE) {
+        snt[z] = box_count(g, col, z);
+        int sc = 0;
+        for (int k = 0; k < 9; ++k) sc += box_count(g, ccol[k], z);
+        ssl[z] = sc;
+    }
+    __syncthreads();
+    if (lane != 0) return;
+    const ColView cv{&g, ccol, snt, ssl, col};
     int cnt = 0;
     int out = WRITE ? counts[col] : 0;
     int z = 0;
     while (z < n2) {
-        const int nt = box_count(g, col, z);
+        const int nt = cv.nt(z);
         if (nt == 0) {
             ++z;
             continue;
         }
-        const int q1 = slab_count(g, ccol, z - 1) + slab_count(g, ccol, z) + slab_count(g, ccol, z + 1);
+        const int q1 = cv.sl(z - 1) + cv.sl(z) + cv.sl(z + 1);
         const int first = g.bs[(int64_t)col * n2 + z];
         if (nt > TILE_T || q1 > TILE_CAP) {
             for (int c = 0; c < nt; c += TILE_T) {
@@ -311,12 +385,11 @@ __global__ void k_tiles(TileGeom g, int32_t *__restrict__ counts, int4 *__restri
         int z1 = z, tacc = nt, q = q1;
         int64_t cost = (int64_t)nt * q1;
         while (z1 + 1 < n2 && (z1 + 1 - z + 1) <= TILE_ZMAX) {
-            const int nn = box_count(g, col, z1 + 1);
-            const int s2 = slab_count(g, ccol, z1 + 2);
+            const int nn = cv.nt(z1 + 1);
+            const int s2 = cv.sl(z1 + 2);
             const int qn = q + s2;
             if (tacc + nn > TILE_T || qn > TILE_CAP) break;
-            if (WRITE && nn > 0)
-                cost += (int64_t)nn * (slab_count(g, ccol, z1) + slab_count(g, ccol, z1 + 1) + s2);
+            if (WRITE && nn > 0) cost += (int64_t)nn * (cv.sl(z1) + cv.sl(z1 + 1) + s2);
             ++z1;
             tacc += nn;
             q = qn;
@@ -497,7 +570,7 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
             int32_t *vout = to_final ? bins->perm : altv;
             hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_THREADS), 0, stream, kin, N, 8 * p, hist,
                                (int)nblk);
-            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, stream, hist, (int64_t)256 * nblk);
+            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(SCAN_T), 0, stream, hist, (int64_t)256 * nblk);
             hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(RS_THREADS), 0, stream, kin, vin, N, 8 * p,
                                hist, (int)nblk, kout, vout);
             kin = kout;
@@ -522,12 +595,12 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     int32_t *tkey2 = tkey + bins->max_tiles;
     int32_t *torder = tkey2 + bins->max_tiles;
     int32_t *thist = torder + bins->max_tiles;
-    hipLaunchKernelGGL(k_tiles<false>, dim3(nblocks(ncol, 64)), dim3(64), 0, stream, tg, colcnt, tiles_u, tkey);
+    hipLaunchKernelGGL(k_tiles<false>, dim3((unsigned)ncol), dim3(WAVE), 0, stream, tg, colcnt, tiles_u, tkey);
     // keep the raw count of the last column, scan, then total
     DMK_HIP_CHECK(hipMemcpyAsync(bins->status + 2, colcnt + ncol - 1, sizeof(int32_t), hipMemcpyDeviceToDevice,
                                  stream));
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, stream, colcnt, ncol);
-    hipLaunchKernelGGL(k_tiles<true>, dim3(nblocks(ncol, 64)), dim3(64), 0, stream, tg, colcnt, tiles_u, tkey);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(SCAN_T), 0, stream, colcnt, ncol);
+    hipLaunchKernelGGL(k_tiles<true>, dim3((unsigned)ncol), dim3(WAVE), 0, stream, tg, colcnt, tiles_u, tkey);
     hipLaunchKernelGGL(k_tile_total, dim3(1), dim3(1), 0, stream, colcnt, (int)ncol, bins->status + 2,
                        bins->status);
     DMK_HIP_CHECK(hipGetLastError());
@@ -541,7 +614,7 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     if (nt > 0) {
         const int64_t tb = (nt + RS_TILE - 1) / RS_TILE;
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tb), dim3(RS_THREADS), 0, stream, tkey, nt, 0, thist, (int)tb);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, stream, thist, (int64_t)256 * tb);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(SCAN_T), 0, stream, thist, (int64_t)256 * tb);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tb), dim3(RS_THREADS), 0, stream, tkey,
                            (const int32_t *)nullptr, nt, 0, thist, (int)tb, tkey2, torder);
         hipLaunchKernelGGL(k_gather_tiles, dim3(nblocks(nt, 256)), dim3(256), 0, stream, tiles_u, torder, nt,

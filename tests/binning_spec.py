@@ -68,3 +68,73 @@ def axis_tables_spec(D, n):
             rows.append(r)
             imgs.append(s)
     return np.asarray(rows, dtype=np.int32), np.asarray(imgs, dtype=np.int8)
+
+
+def tiles_spec(box_start, D, n, T=64, CAP=512, ZMAX=46):
+    """Target tiles as the library forms them, heavy-first.
+
+    Per leaf column (b0, b1), walking z upwards: a box with more than T
+    targets, or whose three neighbour slabs hold more than CAP sources, gets
+    tiles of its own (col, z, -(z+1), first) of at most T targets each;
+    otherwise a tile grows over z0..z1 while its targets stay <= T, the slabs
+    z0-1 .. z1+1 (sources in the 9 stencil columns) stay <= CAP and
+    z1 - z0 + 1 <= ZMAX.  A slab is counted once per stencil column it is
+    reached through, and a slab beyond a free z face is empty.  The tiles,
+    listed column by column, are then stably sorted by the key
+    64 - bit_length(cost + 1), cost = sum over the tile's targets of the
+    sources in their 3 slabs.
+    """
+    n0, n1, n2 = (int(v) for v in n)
+    nbr, _ = axis_tables_spec(D, n)
+    bs = np.asarray(box_start, dtype=np.int64)
+    cnt = (bs[1:] - bs[:-1]).reshape(n0 * n1, n2)
+    tiles, keys = [], []
+    for b0 in range(n0):
+        for b1 in range(n1):
+            col = b0 * n1 + b1
+            ccol = []
+            for k in range(9):
+                nb0 = nbr[b0][k // 3]
+                nb1 = nbr[n0 + b1][k % 3]
+                if nb0 >= 0 and nb1 >= 0:
+                    ccol.append(nb0 * n1 + nb1)
+            slab = cnt[ccol].sum(axis=0) if ccol else np.zeros(n2, dtype=np.int64)
+
+            def sl(zv):
+                if 0 <= zv < n2:
+                    return int(slab[zv])
+                if D > 2:
+                    return int(slab[zv % n2])
+                return 0
+
+            z = 0
+            while z < n2:
+                nt = int(cnt[col, z])
+                if nt == 0:
+                    z += 1
+                    continue
+                q1 = sl(z - 1) + sl(z) + sl(z + 1)
+                first = int(bs[col * n2 + z])
+                if nt > T or q1 > CAP:
+                    for c in range(0, nt, T):
+                        m = min(T, nt - c)
+                        tiles.append((col, z, -(z + 1), first + c))
+                        keys.append(64 - (m * q1 + 1).bit_length())
+                    z += 1
+                    continue
+                z1, tacc, q, cost = z, nt, q1, nt * q1
+                while z1 + 1 < n2 and z1 + 2 - z <= ZMAX:
+                    nn = int(cnt[col, z1 + 1])
+                    s2 = sl(z1 + 2)
+                    if tacc + nn > T or q + s2 > CAP:
+                        break
+                    cost += nn * (sl(z1) + sl(z1 + 1) + s2)
+                    z1 += 1
+                    tacc += nn
+                    q += s2
+                tiles.append((col, z, z1, first))
+                keys.append(64 - (cost + 1).bit_length())
+                z = z1 + 1
+    tiles = np.asarray(tiles, dtype=np.int32).reshape(-1, 4)
+    order = np.argsort(np.asarray(keys, dtype=np.int64), kind="stable")
+    return tiles[order]

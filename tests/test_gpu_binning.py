@@ -4,7 +4,7 @@ axis tables; structural checks of the target tiles."""
 import numpy as np
 import pytest
 
-from binning_spec import axis_tables_spec, bin_spec
+from binning_spec import axis_tables_spec, bin_spec, tiles_spec
 from gpu_util import HAVE_GPU, dev, host, needs_gpu
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
@@ -45,6 +45,16 @@ CASES = [
     ((0.1, 0.3, 0.2), 3, (1, 1, 1), "outside"),
 ]
 
+# larger cases: the radix histograms span several chunks of the device scan
+# (N = 200,000 -> 25,088 counters); the 10^6-point tiling; columns taller than the 2048 boxes the
+# tile walk stages in LDS, periodic and free in z
+BIG = [
+    ((1.0, 1.0, 1.0), 3, (32, 32, 32), 200_000),
+    ((1.0, 1.0, 8.0), 3, (2, 3, 2100), 30_000),
+    ((1.0, 1.0, 8.0), 2, (2, 2, 2500), 30_000),
+    ((1.0, 1.0, 1.0), 3, (64, 64, 64), 1_000_000),  # the Laplace 10^6-point workload's tiling
+]
+
 
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_binning_bit_exact(case):
@@ -65,10 +75,23 @@ def test_binning_bit_exact(case):
     rn, ri = axis_tables_spec(D, n)
     np.testing.assert_array_equal(host(nbr), rn)
     np.testing.assert_array_equal(host(img), ri)
-    _check_tiles(b, n, ref)
+    _check_tiles(b, n, ref, D)
 
 
-def _check_tiles(b, n, ref):
+@pytest.mark.parametrize("case", range(len(BIG)))
+def test_binning_bit_exact_large(case):
+    Lv, D, n, N = BIG[case]
+    x = _points(300 + case, N, Lv, D, "uniform")
+    print("binning large case", case, Lv, D, n, N, flush=True)
+    ref = bin_spec(x, Lv, D, n)
+    b = R.tree_bin(Lv, D, n, dev(x))
+    np.testing.assert_array_equal(host(b.perm()), ref["perm"])
+    np.testing.assert_array_equal(host(b.box_start()), ref["box_start"])
+    assert host(b.ys()).tobytes() == ref["ys"].tobytes()
+    _check_tiles(b, n, ref, D)
+
+
+def _check_tiles(b, n, ref, D):
     tiles = host(b.tiles())
     bs = ref["box_start"]
     covered = np.zeros(b.N, dtype=np.int64)
@@ -87,6 +110,7 @@ def _check_tiles(b, n, ref):
             assert 0 < cnt <= 64
         covered[t0:t0 + cnt] += 1
     assert (covered == 1).all(), "every target in exactly one tile"
+    np.testing.assert_array_equal(tiles.reshape(-1, 4), tiles_spec(bs, D, n))
 
 
 def test_binning_rejects_bad_points():
@@ -111,7 +135,7 @@ def test_binning_dense_and_empty():
     np.testing.assert_array_equal(host(b.perm()), ref["perm"])
     np.testing.assert_array_equal(host(b.box_start()), ref["box_start"])
     assert b.ntiles == (3000 + 63) // 64
-    _check_tiles(b, (6, 6, 6), ref)
+    _check_tiles(b, (6, 6, 6), ref, 3)
 
 
 def test_binning_deterministic():
