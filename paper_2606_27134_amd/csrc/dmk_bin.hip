@@ -88,70 +88,131 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const int32_t *__restric
     hist[(int64_t)tid * nblk + blockIdx.x] = h[tid];
 }
 
-// exclusive scan of a[0..n) in place, one workgroup of 1024 threads.  A
-// chunk of 16 Ki values goes through LDS: coalesced loads, each thread then
-// scans 16 consecutive values serially, the per-thread totals are scanned
-// with wave shuffles and 16 wave totals, and the chunk is written back
-// coalesced.  The LDS index is padded by one word in 32 so that the
-// per-thread reads (stride 16 words) spread over the banks.
-constexpr int SCAN_T = 1024;
+// Exclusive scan of a[0..n) in place.  A chunk of NT x 16 values goes
+// through LDS: coalesced loads, each thread scans 16 consecutive values
+// serially, the per-thread totals are scanned with wave shuffles and the
+// wave totals, and the chunk is written back coalesced.  The LDS index is
+// padded by one word in 32 so that the per-thread reads (stride 16 words)
+// spread over the banks.  Short arrays take one workgroup that walks the
+// chunks; longer ones are split into 4096-value blocks: block sums, a scan of
+// those, then every block scans its values from its offset.
 constexpr int SCAN_I = 16;
-constexpr int SCAN_CH = SCAN_T * SCAN_I;
+constexpr int SCAN_T = 1024;           // single-workgroup scan
+constexpr int SCAN_BT = 256;           // per-block scan
+constexpr int SCAN_B = SCAN_BT * SCAN_I;
 
 __device__ inline int scan_pad(int i) { return i + (i >> 5); }
 
-__global__ __launch_bounds__(SCAN_T) void k_scan_excl(int32_t *__restrict__ a, int64_t n)
+// scans a[base, base + m) (m <= NT * SCAN_I) adding `carry`; returns the
+// chunk total.  buf holds NT * SCAN_I padded words, wsum NT / WAVE words.
+template <int NT>
+__device__ int scan_chunk(int32_t *__restrict__ a, int64_t base, int m, int carry, int *buf, int *wsum)
 {
-    __shared__ int buf[SCAN_CH + SCAN_CH / 32];
-    __shared__ int wsum[SCAN_T / WAVE];
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int w = tid / WAVE;
-    int carry = 0;
-    for (int64_t base = 0; base < n; base += SCAN_CH) {
-        const int64_t rem = n - base;
-        const int m = rem < SCAN_CH ? (int)rem : SCAN_CH;
-        for (int r = 0; r < SCAN_I; ++r) {
-            const int i = r * SCAN_T + tid;
-            buf[scan_pad(i)] = i < m ? a[base + i] : 0;
-        }
-        __syncthreads();
-        int v[SCAN_I];
-        int tsum = 0;
-#pragma unroll
-        for (int i = 0; i < SCAN_I; ++i) {
-            v[i] = buf[scan_pad(tid * SCAN_I + i)];
-            tsum += v[i];
-        }
-        int x = tsum;  // inclusive scan of the thread totals within the wave
-#pragma unroll
-        for (int off = 1; off < WAVE; off <<= 1) {
-            const int y = __shfl_up(x, off);
-            if (lane >= off) x += y;
-        }
-        if (lane == WAVE - 1) wsum[w] = x;
-        __syncthreads();
-        int wpre = 0, tot = 0;
-#pragma unroll
-        for (int q = 0; q < SCAN_T / WAVE; ++q) {
-            const int t = wsum[q];
-            wpre += q < w ? t : 0;
-            tot += t;
-        }
-        int run = carry + wpre + x - tsum;
-#pragma unroll
-        for (int i = 0; i < SCAN_I; ++i) {
-            buf[scan_pad(tid * SCAN_I + i)] = run;
-            run += v[i];
-        }
-        carry += tot;
-        __syncthreads();
-        for (int r = 0; r < SCAN_I; ++r) {
-            const int i = r * SCAN_T + tid;
-            if (i < m) a[base + i] = buf[scan_pad(i)];
-        }
-        __syncthreads();  // buf and wsum are rewritten by the next chunk
+    for (int r = 0; r < SCAN_I; ++r) {
+        const int i = r * NT + tid;
+        buf[scan_pad(i)] = i < m ? a[base + i] : 0;
     }
+    __syncthreads();
+    int v[SCAN_I];
+    int tsum = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_I; ++i) {
+        v[i] = buf[scan_pad(tid * SCAN_I + i)];
+        tsum += v[i];
+    }
+    int x = tsum;  // inclusive scan of the thread totals within the wave
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == WAVE - 1) wsum[w] = x;
+    __syncthreads();
+    int wpre = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < NT / WAVE; ++q) {
+        const int t = wsum[q];
+        wpre += q < w ? t : 0;
+        tot += t;
+    }
+    int run = carry + wpre + x - tsum;
+#pragma unroll
+    for (int i = 0; i < SCAN_I; ++i) {
+        buf[scan_pad(tid * SCAN_I + i)] = run;
+        run += v[i];
+    }
+    __syncthreads();
+    for (int r = 0; r < SCAN_I; ++r) {
+        const int i = r * NT + tid;
+        if (i < m) a[base + i] = buf[scan_pad(i)];
+    }
+    __syncthreads();  // buf and wsum are rewritten by the next chunk
+    return tot;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_excl(int32_t *__restrict__ a, int64_t n)
+{
+    __shared__ int buf[SCAN_T * SCAN_I + SCAN_T * SCAN_I / 32];
+    __shared__ int wsum[SCAN_T / WAVE];
+    int carry = 0;
+    for (int64_t base = 0; base < n; base += SCAN_T * SCAN_I) {
+        const int64_t rem = n - base;
+        const int m = rem < SCAN_T * SCAN_I ? (int)rem : SCAN_T * SCAN_I;
+        carry += scan_chunk<SCAN_T>(a, base, m, carry, buf, wsum);
+    }
+}
+
+// part[blk] = sum of block blk's values
+__global__ __launch_bounds__(SCAN_BT) void k_scan_reduce(const int32_t *__restrict__ a, int64_t n,
+                                                         int32_t *__restrict__ part)
+{
+    __shared__ int wsum[SCAN_BT / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B;
+    int t = 0;
+    for (int r = 0; r < SCAN_I; ++r) {
+        const int64_t i = base + r * SCAN_BT + threadIdx.x;
+        t += i < n ? a[i] : 0;
+    }
+    for (int off = WAVE / 2; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if ((threadIdx.x & (WAVE - 1)) == 0) wsum[threadIdx.x / WAVE] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int q = 0; q < SCAN_BT / WAVE; ++q) s += wsum[q];
+        part[blockIdx.x] = s;
+    }
+}
+
+// block blk scans its values from offset part[blk] (already scanned)
+__global__ __launch_bounds__(SCAN_BT) void k_scan_apply(int32_t *__restrict__ a, int64_t n,
+                                                        const int32_t *__restrict__ part)
+{
+    __shared__ int buf[SCAN_B + SCAN_B / 32];
+    __shared__ int wsum[SCAN_BT / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B;
+    const int64_t rem = n - base;
+    const int m = rem < SCAN_B ? (int)rem : SCAN_B;
+    scan_chunk<SCAN_BT>(a, base, m, part[blockIdx.x], buf, wsum);
+}
+
+// scratch ints that scan_excl needs for n values
+inline int64_t scan_part_ints(int64_t n) { return (n + SCAN_B - 1) / SCAN_B + 1; }
+
+// exclusive scan of a[0, n) on the stream; part holds scan_part_ints(n) ints
+void scan_excl(int32_t *a, int64_t n, int32_t *part, hipStream_t s)
+{
+    if (n <= 0) return;
+    if (n <= 4 * SCAN_B) {
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(SCAN_T), 0, s, a, n);
+        return;
+    }
+    const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BT), 0, s, (const int32_t *)a, n, part);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(SCAN_T), 0, s, part, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BT), 0, s, a, n, (const int32_t *)part);
 }
 
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__restrict__ kin,
@@ -455,8 +516,9 @@ Layout layout_for(const dmk_grid *g, int64_t N)
     const int64_t nblk = (N + RS_TILE - 1) / RS_TILE;
     l.max_tiles = max_tiles_for(N, nbox);
     const int64_t tblk = (l.max_tiles + RS_TILE - 1) / RS_TILE;
-    const int64_t phase1 = 2 * N + 256 * (nblk > 0 ? nblk : 1) + 64;
-    const int64_t phase2 = (ncol + 64) + 7 * l.max_tiles + 256 * (tblk > 0 ? tblk : 1) + 64;
+    const int64_t nh = 256 * (nblk > 0 ? nblk : 1), nth = 256 * (tblk > 0 ? tblk : 1);
+    const int64_t phase1 = 2 * N + nh + scan_part_ints(nh) + 64;
+    const int64_t phase2 = (ncol + 64) + 7 * l.max_tiles + nth + scan_part_ints(nth > ncol ? nth : ncol) + 64;
     l.tmp_ints = phase1 > phase2 ? phase1 : phase2;
     size_t off = 0;
     l.key = off;
@@ -570,7 +632,7 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
             int32_t *vout = to_final ? bins->perm : altv;
             hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_THREADS), 0, stream, kin, N, 8 * p, hist,
                                (int)nblk);
-            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(SCAN_T), 0, stream, hist, (int64_t)256 * nblk);
+            scan_excl(hist, (int64_t)256 * nblk, hist + 256 * nblk, stream);
             hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(RS_THREADS), 0, stream, kin, vin, N, 8 * p,
                                hist, (int)nblk, kout, vout);
             kin = kout;
@@ -599,7 +661,7 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     // keep the raw count of the last column, scan, then total
     DMK_HIP_CHECK(hipMemcpyAsync(bins->status + 2, colcnt + ncol - 1, sizeof(int32_t), hipMemcpyDeviceToDevice,
                                  stream));
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(SCAN_T), 0, stream, colcnt, ncol);
+    scan_excl(colcnt, ncol, thist + 256 * ((bins->max_tiles + RS_TILE - 1) / RS_TILE), stream);
     hipLaunchKernelGGL(k_tiles<true>, dim3((unsigned)ncol), dim3(WAVE), 0, stream, tg, colcnt, tiles_u, tkey);
     hipLaunchKernelGGL(k_tile_total, dim3(1), dim3(1), 0, stream, colcnt, (int)ncol, bins->status + 2,
                        bins->status);
@@ -614,7 +676,7 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     if (nt > 0) {
         const int64_t tb = (nt + RS_TILE - 1) / RS_TILE;
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tb), dim3(RS_THREADS), 0, stream, tkey, nt, 0, thist, (int)tb);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(SCAN_T), 0, stream, thist, (int64_t)256 * tb);
+        scan_excl(thist, (int64_t)256 * tb, thist + 256 * tb, stream);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tb), dim3(RS_THREADS), 0, stream, tkey,
                            (const int32_t *)nullptr, nt, 0, thist, (int)tb, tkey2, torder);
         hipLaunchKernelGGL(k_gather_tiles, dim3(nblocks(nt, 256)), dim3(256), 0, stream, tiles_u, torder, nt,

@@ -53,6 +53,7 @@ BIG = [
     ((1.0, 1.0, 8.0), 3, (2, 3, 2100), 30_000),
     ((1.0, 1.0, 8.0), 2, (2, 2, 2500), 30_000),
     ((1.0, 1.0, 1.0), 3, (64, 64, 64), 1_000_000),  # the Laplace 10^6-point workload's tiling
+    ((32.0, 1.0, 1.0), 1, (256, 80, 2), 100_000),   # 20,480 columns: the column scan in blocks
 ]
 
 
