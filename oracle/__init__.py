@@ -17,6 +17,11 @@ Functions follow the paper's notation:
 * :func:`direct_free` -- D = 0 direct sum of the original kernels (App. B).
 * :func:`full_split_3p` -- mode F for D = 3 (eq. (ewald_far_3P) plus the
   self-interaction correction of Sec. 2.4).
+* :func:`far_3p` -- the far-field part of eq. (ewald_far_3P) alone, from given
+  sources to given targets, over the cube of wave numbers of eqs.
+  (wavenumbers-3p-trunc), (kintmax); :func:`far_3p_grid` applies it to the
+  root-level Chebyshev grids of the top cubes (Sec. 4, evaluation of the
+  far-field contribution, eqs. (structurefac), (eval_tensor)).
 
 Every function takes ``window=None`` (the Gaussian split of width sigma) or a
 :class:`oracle.pswf.PswfWindow` (the PSWF split of Sec. 2.2, eq.
@@ -69,6 +74,8 @@ def _load():
         lib.oracle_kernel_free_tensor.argtypes = [C, P, P]
         lib.oracle_set_window.argtypes = [C, C, P, C, P, P, P]
         lib.oracle_set_window.restype = C
+        lib.oracle_far_3p.argtypes = [C, P, D, P, I64, P, P, I64, P, P]
+        lib.oracle_far_3p.restype = C
         for f in (lib.oracle_residual, lib.oracle_residual_vjp, lib.oracle_direct_free,
                   lib.oracle_full_split_3p, lib.oracle_kernel_tensor, lib.oracle_kernel_free_tensor):
             f.restype = C
@@ -206,3 +213,57 @@ def kernel_free_tensor(kernel, d):
     K = np.zeros((3, 9))
     _load().oracle_kernel_free_tensor(k, _ptr(d), _ptr(K))
     return K[:M_OUT[k], :M_IN[k]]
+
+
+def far_3p(kernel, L, sigma, K, xs, rho, xt, window=None):
+    """u[nt, m_out] = far-field part (eq. (ewald_far_3P)) at targets xt from
+    sources xs with strengths rho, wave numbers 2 pi n_i / L_i with
+    |n_i| <= K_i, n != 0."""
+    _set_window(window)
+    k = _kid(kernel)
+    xs = _f64(xs, (-1, 3))
+    xt = _f64(xt, (-1, 3))
+    rho = _f64(rho, (xs.shape[0], M_IN[k]))
+    Lv = _f64(L, (3,))
+    Kv = np.ascontiguousarray(np.asarray(K, dtype=np.int32).reshape(3))
+    u = np.zeros((xt.shape[0], M_OUT[k]), dtype=np.float64)
+    rc_ = _load().oracle_far_3p(k, _ptr(Lv), float(sigma), _ptr(Kv), xs.shape[0], _ptr(xs), _ptr(rho),
+                                xt.shape[0], _ptr(xt), _ptr(u))
+    if rc_ != 0:
+        raise ValueError("oracle_far_3p: bad arguments")
+    return u
+
+
+def cheb_points(p):
+    """First-kind Chebyshev points cos((2j - 1) pi / (2p)), j = 1..p, on [-1, 1]
+    (the proxy grid of every box, Sec. 3.1, upward pass)."""
+    j = np.arange(1, p + 1, dtype=np.float64)
+    return np.cos((2 * j - 1) * np.pi / (2 * p))
+
+
+def top_grid(L, M, p):
+    """Per-axis coordinates of the root-level Chebyshev grids: the cell
+    [0,L0)x[0,L1)x[0,L2) tiled exactly by M0 x M1 x M2 cubes of side h0;
+    grid index g = b p + (j - 1) on each axis, coordinate (b + 1/2) h0 +
+    (h0/2) eta_j."""
+    L = np.asarray(L, dtype=np.float64)
+    M = np.asarray(M, dtype=np.int64)
+    h0 = L / M
+    if not np.allclose(h0, h0[0], rtol=0, atol=1e-14 * h0[0]):
+        raise ValueError("the top cubes must tile the cell exactly")
+    eta = cheb_points(p)
+    return [((np.arange(M[i])[:, None] + 0.5) * h0[i] + 0.5 * h0[i] * eta[None, :]).ravel() for i in range(3)]
+
+
+def far_3p_grid(kernel, L, M, p, K, sigma, rho_grid, window=None):
+    """Far field on the root-level Chebyshev grids from proxy strengths on the
+    same grids: rho_grid[m_in][G0][G1][G2] -> u[m_out][G0][G1][G2], G_i = M_i p,
+    by the direct sums of :func:`far_3p` with every grid point a source and a
+    target."""
+    k = _kid(kernel)
+    X = top_grid(L, M, p)
+    G = [len(a) for a in X]
+    pts = np.stack(np.meshgrid(*X, indexing="ij"), axis=-1).reshape(-1, 3)
+    rho = np.asarray(rho_grid, dtype=np.float64).reshape(M_IN[k], -1).T
+    u = far_3p(kernel, L, sigma, K, pts, rho, pts, window=window)
+    return u.T.reshape(M_OUT[k], *G)

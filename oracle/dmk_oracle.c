@@ -27,6 +27,11 @@
  *                        mollified kernel over k != 0 (eq. (ewald_far_3P),
  *                        structure factor eq. (structurefacgen)) + the
  *                        self-interaction correction (Sec. 2.4, App. B).
+ *  oracle_far_3p         The far-field part alone (eq. (ewald_far_3P)) from
+ *                        given sources to given targets, over the cube of
+ *                        wave numbers |kbar_i| <= K_i, kbar != 0 (eqs.
+ *                        (wavenumbers-3p-trunc), (kintmax)); used with the
+ *                        root-level Chebyshev grids as sources and targets.
  *
  * Kernel ids: 0 Laplace (harmonic), 1 Stokeslet, 2 stresslet, 3 rotlet.
  * Strength sizes m_in = 1, 3, 9, 3; potential sizes m_out = 1, 3, 3, 3.
@@ -546,6 +551,68 @@ int oracle_full_split_3p(int kern, const double L[3], double sigma, int64_t N, c
     }
     free(ur);
     free(uf);
+    return 0;
+}
+
+/*
+ * Far-field part of the D = 3 split (eq. (ewald_far_3P)) truncated to the
+ * cube of wave numbers 2 pi (n0/L0, n1/L1, n2/L2), |n_i| <= K_i, n != 0
+ * (eq. (wavenumbers-3p-trunc)): for every target x_t
+ *   u_j(x_t) = sum_k Re[ sum_q Khat_jq(k) chi_q(k) e^{i k.x_t} ],
+ *   chi_q(k) = (1/|Omega|) sum_s rho_{s,q} e^{-i k.x_s}   (eq. (structurefacgen)).
+ */
+int oracle_far_3p(int kern, const double L[3], double sigma, const int32_t K[3], int64_t ns, const double *xs,
+                  const double *rho, int64_t nt, const double *xt, double *u)
+{
+    if (kern < 0 || kern > 3 || !(sigma > 0.0) || ns < 0 || nt < 0) return 1;
+    for (int i = 0; i < 3; i++)
+        if (!(L[i] > 0.0) || K[i] < 0 || K[i] > 4096) return 1;
+    const int mi = m_in_of(kern), mo = m_out_of(kern);
+    const long double V = (long double)L[0] * L[1] * L[2];
+    const int64_t w0 = 2 * K[0] + 1, w1 = 2 * K[1] + 1, w2 = 2 * K[2] + 1;
+    const int64_t nm = w0 * w1 * w2;
+    /* per mode: wave vector and w_j = sum_q Khat_jq chi_q */
+    long double(*kv)[3] = malloc(sizeof(long double[3]) * (size_t)nm);
+    long double complex(*wm)[3] = malloc(sizeof(long double complex[3]) * (size_t)nm);
+    if (!kv || !wm) {
+        free(kv);
+        free(wm);
+        return 2;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t m = 0; m < nm; m++) {
+        const long n0 = (long)(m / (w1 * w2)) - K[0];
+        const long n1 = (long)((m / w2) % w1) - K[1];
+        const long n2 = (long)(m % w2) - K[2];
+        kv[m][0] = 2.0L * PI_L * n0 / L[0];
+        kv[m][1] = 2.0L * PI_L * n1 / L[1];
+        kv[m][2] = 2.0L * PI_L * n2 / L[2];
+        for (int j = 0; j < 3; j++) wm[m][j] = 0;
+        if (n0 == 0 && n1 == 0 && n2 == 0) continue; /* k = 0 omitted */
+        long double complex Kh[3][9];
+        khat_tensor(kern, kv[m], sigma, Kh);
+        long double complex chi[9];
+        for (int q = 0; q < mi; q++) chi[q] = 0;
+        for (int64_t a = 0; a < ns; a++) {
+            long double ph = kv[m][0] * xs[3 * a] + kv[m][1] * xs[3 * a + 1] + kv[m][2] * xs[3 * a + 2];
+            long double complex e = cosl(ph) - I * sinl(ph);
+            for (int q = 0; q < mi; q++) chi[q] += e * (long double)rho[mi * a + q];
+        }
+        for (int j = 0; j < mo; j++)
+            for (int q = 0; q < mi; q++) wm[m][j] += Kh[j][q] * chi[q] / V;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < nt; b++) {
+        long double acc[3] = {0, 0, 0};
+        for (int64_t m = 0; m < nm; m++) {
+            long double ph = kv[m][0] * xt[3 * b] + kv[m][1] * xt[3 * b + 1] + kv[m][2] * xt[3 * b + 2];
+            long double complex e = cosl(ph) + I * sinl(ph);
+            for (int j = 0; j < mo; j++) acc[j] += creall(wm[m][j] * e);
+        }
+        for (int j = 0; j < mo; j++) u[mo * b + j] = (double)acc[j];
+    }
+    free(kv);
+    free(wm);
     return 0;
 }
 
