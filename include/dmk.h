@@ -205,6 +205,56 @@ const char *dmk_strerror(int status);
 /* Library version string. */
 const char *dmk_version(void);
 
+/*
+ * Root-level far field of the triply periodic split (D = 3; Sec. 4,
+ * evaluation of the far-field contribution, eqs. (structurefac),
+ * (eval_tensor), wave numbers of eqs. (wavenumbers-3p-trunc), (kintmax)).
+ *
+ * The cell [0,L0)x[0,L1)x[0,L2) is tiled exactly by M0 x M1 x M2 top-level
+ * cubes of side h0 = L_i / M_i (equal on the three axes).  Each cube carries a
+ * p x p x p grid of first-kind Chebyshev points, (h0/2) cos((2j-1) pi/(2p)),
+ * j = 1..p, about its centre.  Along axis i the grid coordinates of all cubes
+ * form one list of G_i = M_i p entries, index g = b p + (j - 1) (cube b),
+ * coordinate (b + 1/2) h0 + (h0/2) cos((2j-1) pi/(2p)).
+ *
+ * Given proxy strengths rho on those grid points, dmk_far3p_eval computes
+ * on the same points
+ *
+ *   u_j(x) = sum_{k != 0} Re[ e^{i k.x} sum_q Khat_jq(k; sigma0) chi_q(k) ],
+ *   chi_q(k) = (1/(L0 L1 L2)) sum_y e^{-i k.y} rho_q(y),
+ *   k = 2 pi (n0/L0, n1/L1, n2/L2), |n_i| <= K_i,
+ *
+ * with Khat the Fourier transform of the mollified kernel (harmonic,
+ * Stokeslet, stresslet, rotlet; App. A) for the Gaussian window of width
+ * sigma0 (win = NULL, phihat(q) = exp(-q^2/4)) or the PSWF window of support
+ * sigma0 (win from dmk_pswf_window).  The stresslet's extra k = 0
+ * compensation term is not included.
+ *
+ * Layout (dev, FP64): rho_grid[m_in][G0][G1][G2], u_grid[m_out][G0][G1][G2]
+ * (last index fastest).  `ws` is a device workspace of >= dmk_far3p_ws_bytes
+ * bytes.  Asynchronous on `stream`; u_grid is fully overwritten.  Errors:
+ * DMK_EINVAL (null pointer, p outside [1, DMK_FAR_PMAX], M_i outside
+ * [1, DMK_FAR_MMAX], K_i outside [0, DMK_FAR_KMAX], cubes that do not tile the
+ * cell), DMK_ECUTOFF (sigma0 <= 0), DMK_EUNSUPPORTED (bad window, or
+ * |k|max sigma0 > 4096 with the PSWF window), DMK_ESIZE (workspace too small).
+ */
+#define DMK_FAR_PMAX 64
+#define DMK_FAR_MMAX 4096
+#define DMK_FAR_KMAX 1024
+
+typedef struct {
+    double L[3];
+    int32_t M[3];
+    int32_t p;
+    int32_t K[3];
+} dmk_far_grid;
+
+/* Workspace bytes for dmk_far3p_eval, or 0 for invalid arguments. */
+size_t dmk_far3p_ws_bytes(const dmk_far_grid *fg, int kernel);
+
+int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0, const dmk_pswf *win, const double *rho_grid,
+                   double *u_grid, void *ws, size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

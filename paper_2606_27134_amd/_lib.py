@@ -42,6 +42,16 @@ class dmk_pswf(ctypes.Structure):
                 ("cheb", (ctypes.c_double * PSWF_MAXTERMS) * 4)]
 
 
+class dmk_far_grid(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double * 3), ("M", ctypes.c_int32 * 3), ("p", ctypes.c_int32),
+                ("K", ctypes.c_int32 * 3)]
+
+
+FAR_PMAX = 64
+FAR_MMAX = 4096
+FAR_KMAX = 1024
+
+
 class DmkError(RuntimeError):
     def __init__(self, code, where):
         self.code = code
@@ -88,6 +98,11 @@ def load():
     lib.dmk_residual_backward_pswf.restype = ctypes.c_int
     lib.dmk_residual_set_kernel_events.argtypes = [P, P]
     lib.dmk_residual_set_kernel_events.restype = ctypes.c_int
+    F = ctypes.POINTER(dmk_far_grid)
+    lib.dmk_far3p_ws_bytes.argtypes = [F, ctypes.c_int]
+    lib.dmk_far3p_ws_bytes.restype = ctypes.c_size_t
+    lib.dmk_far3p_eval.argtypes = [F, ctypes.c_int, ctypes.c_double, P, P, P, P, ctypes.c_size_t, P]
+    lib.dmk_far3p_eval.restype = ctypes.c_int
     lib.dmk_strerror.argtypes = [ctypes.c_int]
     lib.dmk_strerror.restype = ctypes.c_char_p
     lib.dmk_version.argtypes = []
@@ -171,6 +186,28 @@ def dmk_residual_backward_pswf(grid, bins, kernel, prec, w, nu, rho_ptr, gu_ptr,
 
 def dmk_residual_set_kernel_events(start_ptr: int, stop_ptr: int) -> int:
     return int(load().dmk_residual_set_kernel_events(ctypes.c_void_p(start_ptr), ctypes.c_void_p(stop_ptr)))
+
+
+def make_far_grid(L, M, p, K) -> dmk_far_grid:
+    g = dmk_far_grid()
+    for i in range(3):
+        g.L[i] = float(L[i])
+        g.M[i] = int(M[i])
+        g.K[i] = int(K[i])
+    g.p = int(p)
+    return g
+
+
+def dmk_far3p_ws_bytes(fg: dmk_far_grid, kernel: int) -> int:
+    return int(load().dmk_far3p_ws_bytes(ctypes.byref(fg), int(kernel)))
+
+
+def dmk_far3p_eval(fg, kernel, sigma0, w, rho_ptr, u_ptr, ws_ptr, ws_bytes, stream) -> int:
+    """w: a dmk_pswf (PSWF window of support sigma0) or None (Gaussian of width sigma0)."""
+    return int(load().dmk_far3p_eval(ctypes.byref(fg), int(kernel), float(sigma0),
+                                     ctypes.byref(w) if w is not None else None, ctypes.c_void_p(rho_ptr),
+                                     ctypes.c_void_p(u_ptr), ctypes.c_void_p(ws_ptr), int(ws_bytes),
+                                     ctypes.c_void_p(stream)))
 
 
 def dmk_version() -> str:

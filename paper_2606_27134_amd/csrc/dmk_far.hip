@@ -1,0 +1,391 @@
+// dmk_far.hip -- root-level far field of the triply periodic split on gfx950.
+//
+// At the top level the cell is tiled exactly by M0 x M1 x M2 cubes of side h0,
+// each carrying a p^3 grid of first-kind Chebyshev points (Sec. 4,
+// evaluation of the far-field contribution).  With proxy strengths rho on the
+// grids, the far field on the same grids is
+//
+//   chi_q(k) = (1/|Omega|) sum_x e^{-i k.x} rho_q(x)          eq. (structurefac)
+//   u_j(x)   = sum_{k != 0} Re[ e^{i k.x} sum_q Khat_jq(k) chi_q(k) ]   eq. (eval_tensor)
+//
+// over the wave numbers k = 2 pi (n0/L0, n1/L1, n2/L2), |n_i| <= K_i.  Along
+// axis i the grid points of all cubes form one coordinate list X_i[g],
+// g = b p + j (G_i = M_i p entries), and e^{i k.x} = prod_i E_i[g_i][n_i] with
+// E_i[g][n] = exp(2 pi i n X_i[g] / L_i).  Both sums therefore factor into
+// three one-axis contractions each (sum factorization); every contraction is
+// one launch of a complex "mode product"
+//
+//   Y[a][o][c] = s * sum_i coef(i, o) X[a][i][c]
+//
+// with coef a view of one of the E_i tables.  Summing over the cubes of an
+// axis directly costs O(M_i^2) instead of the O(M_i log M_i) of a DFT over the
+// cube index; at the cube counts of elongated cells (tens) the direct form is
+// a few tens of microseconds on the GPU.
+//
+// The mollified kernels in Fourier space (App. A convention) are
+//   harmonic   Hhat = phihat(|k| sigma) / k^2                 eq. (Hhatsplit_wfunc)
+//   biharmonic Bhat = gammaB(|k| sigma) / k^4, gammaB(q) = phihat(q) - q phihat'(q)/2
+//   Stokeslet  (k^2 delta_jl - k_j k_l) Bhat                  eq. (moll_stokeslet)
+//   stresslet  i [(k_m d_jl + k_j d_lm + k_l d_mj) k^2 - 2 k_j k_l k_m] Bhat
+//   rotlet     -(i/2) eps_jlm k_m Hhat
+// with phihat(q) = exp(-q^2/4) for the Gaussian window and, for the PSWF
+// window of support sigma, phihat(q) = 2 int_0^1 phi(t) cos(q t) dt by
+// composite Gauss-Legendre quadrature of the window's Chebyshev series.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include "dmk_internal.h"
+
+namespace dmk {
+namespace {
+
+constexpr int GL_N = 16;  // Gauss-Legendre nodes per quadrature panel
+
+struct FarGeom {
+    int G[3], W[3], K[3], M[3], p;
+    double L[3];
+    int64_t eoff[3];  // offset of E_i in the table array (double2 entries)
+};
+
+struct FarWin {
+    int pswf;      // 0 Gaussian, 1 PSWF series
+    int nterms;
+    double sigma;
+    double cheb[DMK_PSWF_MAXTERMS];  // phi(t) = sum_m cheb[m] T_m(2 t^2 - 1), t in [0, 1]
+    double gx[GL_N], gw[GL_N];       // Gauss-Legendre nodes / weights on [0, 1]
+};
+
+// E_i[g][n] = exp(2 pi i n X_i[g] / L_i), X_i[g] / L_i = (b + 1/2 + cos((2j+1) pi/(2p))/2) / M_i
+__global__ void k_far_tables(FarGeom g, double2 *__restrict__ E)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int ax = 0;
+    int64_t r = t;
+    while (ax < 3 && r >= (int64_t)g.G[ax] * g.W[ax]) {
+        r -= (int64_t)g.G[ax] * g.W[ax];
+        ++ax;
+    }
+    if (ax >= 3) return;
+    const int gi = (int)(r / g.W[ax]);
+    const int n = (int)(r % g.W[ax]) - g.K[ax];
+    const int b = gi / g.p, j = gi % g.p;
+    const double xr = ((double)b + 0.5 + 0.5 * cospi((double)(2 * j + 1) / (double)(2 * g.p))) / (double)g.M[ax];
+    double s, c;
+    sincospi(2.0 * (double)n * xr, &s, &c);
+    E[g.eoff[ax] + r] = make_double2(c, s);
+}
+
+// Y[a][o][c] = s * sum_i coef(i, o) X[a][i][c], coef(i, o) = E[i*si + o*so]
+// (conjugated when CONJ); RIN: X real; ROUT: only Re(Y) is stored (real Y)
+template <bool RIN, bool ROUT, bool CONJ>
+__global__ void k_mode(const void *__restrict__ Xv, const double2 *__restrict__ E, int64_t A, int I, int O, int C,
+                       int64_t si, int64_t so, double s, void *__restrict__ Yv)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= A * O * C) return;
+    const int c = (int)(t % C);
+    const int o = (int)((t / C) % O);
+    const int64_t a = t / ((int64_t)C * O);
+    double re = 0.0, im = 0.0;
+    const int64_t xb = a * I * C + c;
+    for (int i = 0; i < I; ++i) {
+        const double2 e = E[i * si + o * so];
+        const double ei = CONJ ? -e.y : e.y;
+        if constexpr (RIN) {
+            const double x = ((const double *)Xv)[xb + (int64_t)i * C];
+            re = fma(e.x, x, re);
+            im = fma(ei, x, im);
+        } else {
+            const double2 x = ((const double2 *)Xv)[xb + (int64_t)i * C];
+            re = fma(e.x, x.x, fma(-ei, x.y, re));
+            im = fma(e.x, x.y, fma(ei, x.x, im));
+        }
+    }
+    const int64_t yi = (a * O + o) * C + c;
+    if constexpr (ROUT)
+        ((double *)Yv)[yi] = s * re;
+    else
+        ((double2 *)Yv)[yi] = make_double2(s * re, s * im);
+}
+
+// phi(t) of the PSWF window from its Chebyshev series in u = 2 t^2 - 1 (Clenshaw)
+__device__ inline double win_phi(const FarWin &w, double t)
+{
+    const double u = 2.0 * t * t - 1.0;
+    double b1 = 0.0, b2 = 0.0;
+    for (int m = w.nterms - 1; m >= 1; --m) {
+        const double b0 = fma(2.0 * u, b1, w.cheb[m] - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    return fma(u, b1, w.cheb[0] - b2);
+}
+
+// phihat(q) and phihat'(q)
+__device__ inline void win_hat(const FarWin &w, double q, double &ph, double &dph)
+{
+    if (!w.pswf) {
+        ph = exp(-0.25 * q * q);
+        dph = -0.5 * q * ph;
+        return;
+    }
+    // 2 int_0^1 phi(t) cos(q t) dt and -2 int_0^1 t phi(t) sin(q t) dt on
+    // panels over which q t varies by at most 4; at least two panels, as phi is
+    // a polynomial of degree up to ~60 in t
+    const int np = 2 + (int)(q * 0.25);
+    const double hw = 1.0 / np;
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < np; ++k)
+        for (int i = 0; i < GL_N; ++i) {
+            const double t = (k + w.gx[i]) * hw;
+            const double f = w.gw[i] * win_phi(w, t);
+            double sn, cs;
+            sincos(q * t, &sn, &cs);
+            a = fma(f, cs, a);
+            b = fma(f * t, sn, b);
+        }
+    ph = 2.0 * hw * a;
+    dph = -2.0 * hw * b;
+}
+
+// W[j][m] = sum_q Khat_jq(k_m) chi[q][m] for every mode m (0 at k = 0)
+template <int KERN>
+__global__ void k_far_weights(FarGeom g, FarWin w, const double2 *__restrict__ chi, double2 *__restrict__ Wt)
+{
+    constexpr int MI = KERN == 0 ? 1 : (KERN == 2 ? 9 : 3);
+    constexpr int MO = KERN == 0 ? 1 : 3;
+    const int64_t nm = (int64_t)g.W[0] * g.W[1] * g.W[2];
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nm) return;
+    const int n0 = (int)(m / ((int64_t)g.W[1] * g.W[2])) - g.K[0];
+    const int n1 = (int)((m / g.W[2]) % g.W[1]) - g.K[1];
+    const int n2 = (int)(m % g.W[2]) - g.K[2];
+    double2 out[MO];
+    for (int j = 0; j < MO; ++j) out[j] = make_double2(0.0, 0.0);
+    if (n0 != 0 || n1 != 0 || n2 != 0) {
+        const double k[3] = {2.0 * M_PI * n0 / g.L[0], 2.0 * M_PI * n1 / g.L[1], 2.0 * M_PI * n2 / g.L[2]};
+        const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        const double q = sqrt(k2) * w.sigma;
+        double ph, dph;
+        win_hat(w, q, ph, dph);
+        const double Hh = ph / k2;
+        const double Bh = (ph - 0.5 * q * dph) / (k2 * k2);
+        double2 x[MI];
+        for (int c = 0; c < MI; ++c) x[c] = chi[c * nm + m];
+        if constexpr (KERN == 0) {
+            out[0] = make_double2(Hh * x[0].x, Hh * x[0].y);
+        } else if constexpr (KERN == 1) {
+            for (int j = 0; j < 3; ++j) {
+                double re = 0.0, im = 0.0;
+                for (int l = 0; l < 3; ++l) {
+                    const double K = ((j == l ? k2 : 0.0) - k[j] * k[l]) * Bh;
+                    re += K * x[l].x;
+                    im += K * x[l].y;
+                }
+                out[j] = make_double2(re, im);
+            }
+        } else if constexpr (KERN == 2) {
+            // i * T: multiplying by i maps (re, im) to (-im, re)
+            for (int j = 0; j < 3; ++j) {
+                double re = 0.0, im = 0.0;
+                for (int l = 0; l < 3; ++l)
+                    for (int mm = 0; mm < 3; ++mm) {
+                        const double T = ((j == l ? k[mm] : 0.0) + (l == mm ? k[j] : 0.0) + (mm == j ? k[l] : 0.0)) * k2 -
+                                         2.0 * k[j] * k[l] * k[mm];
+                        const double K = T * Bh;
+                        re += K * x[3 * l + mm].x;
+                        im += K * x[3 * l + mm].y;
+                    }
+                out[j] = make_double2(-im, re);
+            }
+        } else {
+            // sum_l -(i/2) eps_jlm k_m Hhat chi_l = (i/2) Hhat (k x chi)_j
+            const double h = 0.5 * Hh;
+            const double cr[3] = {k[1] * x[2].x - k[2] * x[1].x, k[2] * x[0].x - k[0] * x[2].x,
+                                  k[0] * x[1].x - k[1] * x[0].x};
+            const double ci[3] = {k[1] * x[2].y - k[2] * x[1].y, k[2] * x[0].y - k[0] * x[2].y,
+                                  k[0] * x[1].y - k[1] * x[0].y};
+            // i h (cr + i ci) = (-h ci, h cr)
+            for (int j = 0; j < 3; ++j) out[j] = make_double2(-h * ci[j], h * cr[j]);
+        }
+    }
+    for (int j = 0; j < MO; ++j) Wt[j * nm + m] = out[j];
+}
+
+int m_in_k(int k) { return k == 0 ? 1 : (k == 2 ? 9 : 3); }
+int m_out_k(int k) { return k == 0 ? 1 : 3; }
+
+struct FarLayout {
+    int64_t E, T1, T2, CHI, WT, V1, V2, total;  // byte offsets
+};
+
+FarLayout far_layout(const FarGeom &g, int kernel)
+{
+    const int64_t Q = m_in_k(kernel), J = m_out_k(kernel);
+    const int64_t G0 = g.G[0], G1 = g.G[1], W0 = g.W[0], W1 = g.W[1], W2 = g.W[2];
+    auto al = [](int64_t v) { return (v + 255) & ~(int64_t)255; };
+    FarLayout l{};
+    int64_t off = 0;
+    const int64_t z = (int64_t)sizeof(double2);
+    l.E = off;
+    off = al(off + z * ((int64_t)g.G[0] * W0 + (int64_t)g.G[1] * W1 + (int64_t)g.G[2] * W2));
+    l.T1 = off;
+    off = al(off + z * Q * G0 * G1 * W2);
+    l.T2 = off;
+    off = al(off + z * Q * G0 * W1 * W2);
+    l.CHI = off;
+    off = al(off + z * Q * W0 * W1 * W2);
+    l.WT = off;
+    off = al(off + z * J * W0 * W1 * W2);
+    l.V1 = off;
+    off = al(off + z * J * G0 * W1 * W2);
+    l.V2 = off;
+    off = al(off + z * J * G0 * G1 * W2);
+    l.total = off;
+    return l;
+}
+
+int far_geom(const dmk_far_grid *fg, FarGeom &g)
+{
+    if (!fg) return DMK_EINVAL;
+    if (fg->p < 1 || fg->p > DMK_FAR_PMAX) return DMK_EINVAL;
+    double h0 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        if (!(fg->L[i] > 0.0) || !isfinite(fg->L[i])) return DMK_EINVAL;
+        if (fg->M[i] < 1 || fg->M[i] > DMK_FAR_MMAX) return DMK_EINVAL;
+        if (fg->K[i] < 0 || fg->K[i] > DMK_FAR_KMAX) return DMK_EINVAL;
+        const double h = fg->L[i] / fg->M[i];
+        if (i == 0) h0 = h;
+        if (fabs(h - h0) > 1e-12 * h0) return DMK_EINVAL;  // the top cubes must tile the cell
+    }
+    memset(&g, 0, sizeof(g));
+    g.p = fg->p;
+    int64_t off = 0;
+    for (int i = 0; i < 3; ++i) {
+        g.L[i] = fg->L[i];
+        g.M[i] = fg->M[i];
+        g.K[i] = fg->K[i];
+        g.G[i] = fg->M[i] * fg->p;
+        g.W[i] = 2 * fg->K[i] + 1;
+        g.eoff[i] = off;
+        off += (int64_t)g.G[i] * g.W[i];
+    }
+    return DMK_OK;
+}
+
+// Gauss-Legendre nodes and weights on [0, 1] (Newton on P_n)
+void gauss_legendre01(double *x, double *w)
+{
+    const int n = GL_N;
+    for (int k = 0; k < n; ++k) {
+        double z = cos(M_PI * (k + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int m = 2; m <= n; ++m) {
+                const double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / m;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int m = 2; m <= n; ++m) {
+            const double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / m;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[k] = 0.5 * (1.0 - z);
+        w[k] = 1.0 / ((1.0 - z * z) * dp * dp);  // 2 / ((1 - z^2) P'^2) halved for [0, 1]
+    }
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <bool RIN, bool ROUT, bool CONJ>
+void mode(const void *X, const double2 *E, int64_t A, int I, int O, int C, int64_t si, int64_t so, double s, void *Y,
+          hipStream_t st)
+{
+    const int64_t n = A * O * C;
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_mode<RIN, ROUT, CONJ>), dim3(nblk(n, 256)), dim3(256), 0, st, X, E, A, I, O, C, si, so, s,
+                       Y);
+}
+
+}  // namespace
+}  // namespace dmk
+
+using namespace dmk;
+
+extern "C" size_t dmk_far3p_ws_bytes(const dmk_far_grid *fg, int kernel)
+{
+    FarGeom g;
+    if (far_geom(fg, g) != DMK_OK || kernel < 0 || kernel > 3) return 0;
+    return (size_t)far_layout(g, kernel).total;
+}
+
+extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0, const dmk_pswf *win,
+                              const double *rho_grid, double *u_grid, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    FarGeom g;
+    int st = far_geom(fg, g);
+    if (st != DMK_OK) return st;
+    if (kernel < 0 || kernel > 3) return DMK_EINVAL;
+    if (!(sigma0 > 0.0) || !isfinite(sigma0)) return DMK_ECUTOFF;
+    if (!rho_grid || !u_grid || !ws) return DMK_EINVAL;
+    FarWin w;
+    memset(&w, 0, sizeof(w));
+    w.sigma = sigma0;
+    if (win) {
+        if (!(win->c > 0.0) || !(win->c <= DMK_PSWF_CMAX) || win->nterms64 < 1 ||
+            win->nterms64 > DMK_PSWF_MAXTERMS)
+            return DMK_EUNSUPPORTED;
+        w.pswf = 1;
+        w.nterms = win->nterms64;
+        for (int m = 0; m < DMK_PSWF_MAXTERMS; ++m) w.cheb[m] = win->cheb[0][m];
+        gauss_legendre01(w.gx, w.gw);
+        // the quadrature grows with |k| sigma: bound it
+        double kk = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            const double ki = 2.0 * M_PI * g.K[i] / g.L[i];
+            kk += ki * ki;
+        }
+        if (sqrt(kk) * sigma0 > 4096.0) return DMK_EUNSUPPORTED;
+    }
+    const FarLayout l = far_layout(g, kernel);
+    if (ws_bytes < (size_t)l.total) return DMK_ESIZE;
+    char *b = (char *)ws;
+    double2 *E = (double2 *)(b + l.E);
+    double2 *T1 = (double2 *)(b + l.T1), *T2 = (double2 *)(b + l.T2), *CHI = (double2 *)(b + l.CHI);
+    double2 *WT = (double2 *)(b + l.WT), *V1 = (double2 *)(b + l.V1), *V2 = (double2 *)(b + l.V2);
+    const int64_t Q = m_in_k(kernel), J = m_out_k(kernel);
+    const int G0 = g.G[0], G1 = g.G[1], G2 = g.G[2], W0 = g.W[0], W1 = g.W[1], W2 = g.W[2];
+    const double2 *E0 = E + g.eoff[0], *E1 = E + g.eoff[1], *E2 = E + g.eoff[2];
+    const double invV = 1.0 / (g.L[0] * g.L[1] * g.L[2]);
+
+    const int64_t ne = (int64_t)G0 * W0 + (int64_t)G1 * W1 + (int64_t)G2 * W2;
+    hipLaunchKernelGGL(k_far_tables, dim3(nblk(ne, 256)), dim3(256), 0, stream, g, E);
+    // structure factor (eq. (structurefac)): contract g2, g1, g0 with conj(E)
+    mode<true, false, true>(rho_grid, E2, Q * G0 * G1, G2, W2, 1, W2, 1, 1.0, T1, stream);
+    mode<false, false, true>(T1, E1, Q * G0, G1, W1, W2, W1, 1, 1.0, T2, stream);
+    mode<false, false, true>(T2, E0, Q, G0, W0, (int)((int64_t)W1 * W2), W0, 1, invV, CHI, stream);
+    // mode weights
+    const int64_t nm = (int64_t)W0 * W1 * W2;
+    switch (kernel) {
+    case 0: hipLaunchKernelGGL(k_far_weights<0>, dim3(nblk(nm, 64)), dim3(64), 0, stream, g, w, CHI, WT); break;
+    case 1: hipLaunchKernelGGL(k_far_weights<1>, dim3(nblk(nm, 64)), dim3(64), 0, stream, g, w, CHI, WT); break;
+    case 2: hipLaunchKernelGGL(k_far_weights<2>, dim3(nblk(nm, 64)), dim3(64), 0, stream, g, w, CHI, WT); break;
+    default: hipLaunchKernelGGL(k_far_weights<3>, dim3(nblk(nm, 64)), dim3(64), 0, stream, g, w, CHI, WT); break;
+    }
+    // evaluation on the grids (eq. (eval_tensor)): contract n0, n1, n2 with E
+    mode<false, false, false>(WT, E0, J, W0, G0, (int)((int64_t)W1 * W2), 1, W0, 1.0, V1, stream);
+    mode<false, false, false>(V1, E1, J * G0, W1, G1, W2, 1, W1, 1.0, V2, stream);
+    mode<false, true, false>(V2, E2, J * G0 * G1, W2, G2, 1, 1, W2, 1.0, u_grid, stream);
+    DMK_HIP_CHECK(hipGetLastError());
+    return DMK_OK;
+}

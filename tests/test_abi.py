@@ -134,3 +134,25 @@ def test_pswf_window_argument_errors():
     P = 1 << 40
     bad = L.dmk_pswf()  # c = 0: not a window
     assert L.dmk_residual_eval_pswf(g, b, 0, 0, bad, 0.1, P, P, P, 1 << 30, 0) == L.DMK_EUNSUPPORTED
+
+
+def test_far3p_host_argument_checks():
+    fg = L.make_far_grid((1, 1, 1), (1, 1, 1), 8, (2, 2, 2))
+    nb = L.dmk_far3p_ws_bytes(fg, 1)
+    assert nb >= 16 * (3 * 8 * 5) and nb % 256 == 0
+    fake = 1 << 40  # never dereferenced: every check below fails before a launch
+    assert L.dmk_far3p_eval(fg, 1, 1.0, None, fake, fake, fake, nb - 1, 0) == L.DMK_ESIZE
+    assert L.dmk_far3p_eval(fg, 1, 0.0, None, fake, fake, fake, nb, 0) == L.DMK_ECUTOFF
+    assert L.dmk_far3p_eval(fg, 4, 1.0, None, fake, fake, fake, nb, 0) == L.DMK_EINVAL
+    assert L.dmk_far3p_eval(fg, 1, 1.0, None, 0, fake, fake, nb, 0) == L.DMK_EINVAL
+    bad = L.dmk_pswf()  # c = 0: not a window
+    assert L.dmk_far3p_eval(fg, 1, 1.0, bad, fake, fake, fake, nb, 0) == L.DMK_EUNSUPPORTED
+    for args in [((1, 1, 1), (1, 1, 2), 8, (2, 2, 2)),      # cubes do not tile the cell
+                 ((1, 1, 1), (1, 1, 1), 0, (2, 2, 2)),      # p < 1
+                 ((1, 1, 1), (1, 1, 1), L.FAR_PMAX + 1, (2, 2, 2)),
+                 ((1, 1, 1), (1, 1, 1), 8, (2, -1, 2)),
+                 ((1, 1, 1), (1, 1, 1), 8, (2, L.FAR_KMAX + 1, 2)),
+                 ((0, 1, 1), (1, 1, 1), 8, (2, 2, 2))]:
+        g = L.make_far_grid(*args)
+        assert L.dmk_far3p_ws_bytes(g, 0) == 0
+        assert L.dmk_far3p_eval(g, 0, 1.0, None, fake, fake, fake, 1 << 30, 0) == L.DMK_EINVAL

@@ -1,0 +1,102 @@
+"""dmk_far3p_eval (root-level far field, D = 3) against the oracle's direct
+sums of eqs. (structurefacgen) and (ewald_far_3P) with the top-level
+Chebyshev grid points as sources and targets.  FP64 bar: relative l2 <= 1e-12
+(and every element within 1e-12 of the largest)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.pswf import PswfWindow
+from gpu_util import HAVE_GPU, assert_parity, dev, host, needs_gpu
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+if HAVE_GPU:
+    from paper_2606_27134_amd import far as F
+
+KERNELS = ["laplace", "stokeslet", "stresslet", "rotlet"]
+_WIN = {}
+
+
+def _w(c):
+    if c is None:
+        return None
+    if c not in _WIN:
+        _WIN[c] = PswfWindow(c)
+    return _WIN[c]
+
+
+# (L, M, p, K, sigma0 for the Gaussian): small grids over one or several cubes
+GEOMS = [
+    ((1.0, 1.0, 1.0), (1, 1, 1), 6, (2, 2, 2), 0.3),
+    ((2.0, 1.0, 3.0), (2, 1, 3), 5, (3, 1, 4), 0.4),
+    ((1.0, 1.0, 1.0), (1, 1, 1), 12, (1, 1, 1), 0.5),
+]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("geom", range(len(GEOMS)))
+@pytest.mark.parametrize("win", ["gauss", "pswf"])
+def test_far_small_grids(kernel, geom, win):
+    Lv, M, p, K, sg = GEOMS[geom]
+    print("far small", kernel, geom, win, flush=True)
+    k = oracle.KERNELS[kernel]
+    G = [m * p for m in M]
+    rng = np.random.default_rng(500 + 10 * geom + k)
+    rho = rng.normal(size=(oracle.M_IN[k], *G))
+    if win == "gauss":
+        c, sigma0 = None, sg
+    else:
+        c, sigma0 = 14.5, Lv[0] / M[0]
+    ref = oracle.far_3p_grid(kernel, Lv, M, p, K, sigma0, rho, window=_w(c))
+    got = host(F.far3p_eval(Lv, M, p, K, kernel, sigma0, dev(rho), pswf_c=c))
+    assert_parity(got, ref, 1e-12, "far %s %d %s" % (kernel, geom, win))
+
+
+def test_far_cube_laplace_1e12_full():
+    # Laplace table row 1e-12: c = 29, p = 38, N_per = 9; sigma0 = the cube side
+    Lv, M, p = (1.0, 1.0, 1.0), (1, 1, 1), 38
+    K = F.table_modes(29.0, Lv, 1.0)
+    assert K == (4, 4, 4)
+    rng = np.random.default_rng(77)
+    rho = rng.normal(size=(1, p, p, p))
+    ref = oracle.far_3p_grid("laplace", Lv, M, p, K, 1.0, rho, window=_w(29.0))
+    got = host(F.far3p_eval(Lv, M, p, K, "laplace", 1.0, dev(rho), pswf_c=29.0))
+    assert_parity(got, ref, 1e-12, "far laplace p38")
+
+
+def _sampled(kernel, Lv, M, p, K, c, nnz, ntgt, seed):
+    k = oracle.KERNELS[kernel]
+    G = [m * p for m in M]
+    rng = np.random.default_rng(seed)
+    rho = np.zeros((oracle.M_IN[k], *G))
+    flat = rng.choice(G[0] * G[1] * G[2], size=nnz, replace=False)
+    idx = np.unravel_index(flat, G)
+    rho[(slice(None),) + idx] = rng.normal(size=(oracle.M_IN[k], nnz))
+    got = host(F.far3p_eval(Lv, M, p, K, kernel, Lv[0] / M[0], dev(rho), pswf_c=c))
+    X = oracle.top_grid(Lv, M, p)
+    xs = np.stack([X[i][idx[i]] for i in range(3)], axis=1)
+    tsel = rng.choice(G[0] * G[1] * G[2], size=ntgt, replace=False)
+    tidx = np.unravel_index(tsel, G)
+    xt = np.stack([X[i][tidx[i]] for i in range(3)], axis=1)
+    ref = oracle.far_3p(kernel, Lv, Lv[0] / M[0], K, xs, rho[(slice(None),) + idx].T, xt, window=_w(c))
+    return got[(slice(None),) + tidx].T, ref
+
+
+def test_far_cube_stokeslet_1e12_sampled():
+    # Stokeslet table row 1e-12: c = 32.46, p = 44, N_per = 11
+    Lv, M, p = (1.0, 1.0, 1.0), (1, 1, 1), 44
+    K = F.table_modes(32.46, Lv, 1.0)
+    assert K == (5, 5, 5)
+    got, ref = _sampled("stokeslet", Lv, M, p, K, 32.46, 4000, 256, 78)
+    assert_parity(got, ref, 1e-12, "far stokeslet p44")
+
+
+@pytest.mark.parametrize("kernel,c,p", [("stresslet", 33.51, 44), ("rotlet", 32.46, 44), ("laplace", 29.0, 38)])
+def test_far_elongated_cell_sampled(kernel, c, p):
+    # the cuboid (32, 1, 1) of 32 top cubes: 32 times the modes along x
+    Lv, M = (32.0, 1.0, 1.0), (32, 1, 1)
+    K = F.table_modes(c, Lv, 1.0)
+    print("far elongated", kernel, K, flush=True)
+    got, ref = _sampled(kernel, Lv, M, p, K, c, 1500, 128, 79)
+    assert_parity(got, ref, 1e-12, "far elongated %s" % kernel)
