@@ -111,6 +111,63 @@ def cpu_baseline(w, budget_s=15.0):
                        "P_in(sample)=%d" % (n, w.name, w.N, dt, pin)), (t, u, gr, gx, G)
 
 
+def _time_ms(fn, reps, warm=3):
+    import torch
+    for _ in range(warm):
+        fn()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        fn()
+    ev[1].record()
+    torch.cuda.synchronize()
+    return ev[0].elapsed_time(ev[1]) / reps
+
+
+def far_leaf_leg(args):
+    """Root-level far field (dmk_far3p_eval) and leaf-grid anterpolation /
+    evaluation (dmk_cheb_anterp / dmk_cheb_eval), FP64, at the Laplace
+    parameters for 1e-12 (c = 29, p = 38, N_per from the table).  Algorithmic
+    flops: the sum-factorized contractions (complex multiply-add 8, real by
+    complex 4, real part only 4) and, for the leaf grids, 4 per point and
+    node (anterpolation) and 2 (evaluation)."""
+    import torch
+    from paper_2606_27134_amd import _lib as L
+    from paper_2606_27134_amd import far as F
+    from paper_2606_27134_amd import residual as R
+    out = {}
+    rng = np.random.default_rng(2026)
+    for name, Lv, M in (("cube", (1.0, 1.0, 1.0), (1, 1, 1)), ("cuboid_32x1x1", (32.0, 1.0, 1.0), (32, 1, 1))):
+        p, c = 38, 29.0
+        K = F.table_modes(c, Lv, 1.0)
+        G = [m * p for m in M]
+        Wn = [2 * k + 1 for k in K]
+        rho = torch.as_tensor(rng.normal(size=(1, *G))).cuda()
+        u = torch.empty_like(rho)
+        nb = L.dmk_far3p_ws_bytes(L.make_far_grid(Lv, M, p, K), 0)
+        ws = torch.empty(nb // 8 + 32, dtype=torch.float64, device="cuda")
+        ms = _time_ms(lambda: F.far3p_eval(Lv, M, p, K, "laplace", 1.0, rho, pswf_c=c, out=u, ws=ws), 20)
+        fl = (4.0 * G[0] * G[1] * G[2] * Wn[2] + 8.0 * G[0] * G[1] * Wn[1] * Wn[2] + 8.0 * G[0] * Wn[0] * Wn[1] * Wn[2]
+              + 8.0 * Wn[0] * G[0] * Wn[1] * Wn[2] + 8.0 * G[0] * Wn[1] * G[1] * Wn[2] + 4.0 * G[0] * G[1] * Wn[2] * G[2])
+        out["far3p_" + name] = {"L": list(Lv), "cubes": list(M), "p": p, "c": c, "K": list(K), "ms": ms,
+                                "gflops": fl / (ms * 1e-3) / 1e9, "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / 78.6}
+    # leaf grids: 100k uniform points on an 8^3 tiling, p = 20 (the 1e-6 order)
+    N, n, p = 100_000, (8, 8, 8), 20
+    x = torch.as_tensor(rng.random((N, 3))).cuda()
+    q = torch.as_tensor(rng.normal(size=(N, 1))).cuda()
+    b = R.tree_bin((1.0, 1.0, 1.0), 3, n, x)
+    ws = F.cheb_workspace(b, p)
+    rg = F.cheb_anterp(b, p, q, ws=ws)
+    uu = torch.empty_like(q)
+    ta = _time_ms(lambda: F.cheb_anterp(b, p, q, out=rg, ws=ws), 10)
+    te = _time_ms(lambda: F.cheb_eval(b, p, rg, out=uu, ws=ws), 10)
+    out["leaf_grid"] = {"N": N, "tiling": list(n), "p": p,
+                        "anterp_ms": ta, "anterp_gflops": 4.0 * N * p ** 3 / (ta * 1e-3) / 1e9,
+                        "eval_ms": te, "eval_gflops": 2.0 * N * p ** 3 / (te * 1e-3) / 1e9}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +179,8 @@ def main():
     ap.add_argument("--precs", default="fp32c,fp64")
     ap.add_argument("--pswf-c", type=float, default=None,
                     help="bandwidth of the PSWF-split leg (default: the paper's 1e-6 value for the kernel; 0 skips)")
+    ap.add_argument("--no-far", action="store_true",
+                    help="skip the root-level far field and leaf-grid leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -286,6 +345,8 @@ def main():
 
     if pswf is not None:
         line["pswf"] = pswf
+    if not args.no_far:
+        line["far_leaf"] = far_leaf_leg(args)
 
     if not args.no_cpu_baseline:
         cb, (t, u_o, gr_o, gx_o, _) = cpu_baseline(w)

@@ -255,6 +255,47 @@ size_t dmk_far3p_ws_bytes(const dmk_far_grid *fg, int kernel);
 int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0, const dmk_pswf *win, const double *rho_grid,
                    double *u_grid, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Leaf-box Chebyshev grids (Sec. 3.1: every box carries a p x p x p grid of
+ * first-kind Chebyshev points; upward pass: proxy charges by anterpolation;
+ * leaf level: the smooth potential's expansion evaluated at the targets).
+ *
+ * The boxes are the leaf boxes of `grid` as binned in `bins` (dmk_tree_bin).
+ * Grid values of all boxes form one tensor [m][n0 p][n1 p][n2 p] (index
+ * g_i = b_i p + (j - 1) for node j of box b_i; dev, FP64), the layout of
+ * dmk_far3p_eval when the leaf boxes are the top cubes.  In a box of side
+ * h_i the node j sits at (b_i + 1/2) h_i + (h_i/2) cos((2j-1) pi/(2p)); l_j is
+ * the tensor-product Lagrange basis on the nodes, in the box-local coordinate
+ * of the point's wrapped position (the binning's box).  m in {1, 3, 9};
+ * p in [1, DMK_FAR_PMAX].  `ws` is a device workspace of >= dmk_cheb_ws_bytes
+ * bytes.  Asynchronous on `stream`.  Errors: DMK_EINVAL (bad p, m, pointer,
+ * or bins not of this grid), DMK_ESIZE (workspace too small or tensor too
+ * large).
+ *
+ * dmk_cheb_anterp: rho_grid[q](g) = sum over the points a of the box of g of
+ *   rho[a][q] l_j(x_a)  (rho[N][m] in the original order; rho_grid fully
+ *   overwritten).
+ * dmk_cheb_eval: u[a][q] = sum_j u_grid[q](box of a, j) l_j(x_a), stored to
+ *   u[N][m] (original order), or added to it when accumulate != 0.
+ */
+size_t dmk_cheb_ws_bytes(const dmk_bins *bins, int p);
+int dmk_cheb_anterp(const dmk_grid *grid, const dmk_bins *bins, int p, int m, const double *rho, double *rho_grid,
+                    void *ws, size_t ws_bytes, hipStream_t stream);
+int dmk_cheb_eval(const dmk_grid *grid, const dmk_bins *bins, int p, int m, const double *u_grid, int accumulate,
+                  double *u, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Self-interaction correction of the split (Sec. 2.4, eq. (S_self)): the far
+ * field contains the k-space image of each point's own mollified kernel; for
+ * the harmonic kernel and the Stokeslet it is removed by
+ *   u[i][j] += -phi(0) rho[i][j] / (2 pi sigma0)
+ * (phi the window: Gaussian of width sigma0 when win = NULL, else the PSWF
+ * window of support sigma0).  The stresslet and rotlet have none (no-op).
+ * u[N][m_out], rho[N][m_in] dev FP64, original order.  Asynchronous.
+ */
+int dmk_self_term(int kernel, double sigma0, const dmk_pswf *win, int64_t N, const double *rho, double *u,
+                  hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -103,6 +103,14 @@ def load():
     lib.dmk_far3p_ws_bytes.restype = ctypes.c_size_t
     lib.dmk_far3p_eval.argtypes = [F, ctypes.c_int, ctypes.c_double, P, P, P, P, ctypes.c_size_t, P]
     lib.dmk_far3p_eval.restype = ctypes.c_int
+    lib.dmk_cheb_ws_bytes.argtypes = [B, ctypes.c_int]
+    lib.dmk_cheb_ws_bytes.restype = ctypes.c_size_t
+    lib.dmk_cheb_anterp.argtypes = [G, B, ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_size_t, P]
+    lib.dmk_cheb_anterp.restype = ctypes.c_int
+    lib.dmk_cheb_eval.argtypes = [G, B, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_size_t, P]
+    lib.dmk_cheb_eval.restype = ctypes.c_int
+    lib.dmk_self_term.argtypes = [ctypes.c_int, ctypes.c_double, P, ctypes.c_int64, P, P, P]
+    lib.dmk_self_term.restype = ctypes.c_int
     lib.dmk_strerror.argtypes = [ctypes.c_int]
     lib.dmk_strerror.restype = ctypes.c_char_p
     lib.dmk_version.argtypes = []
@@ -208,6 +216,27 @@ def dmk_far3p_eval(fg, kernel, sigma0, w, rho_ptr, u_ptr, ws_ptr, ws_bytes, stre
                                      ctypes.byref(w) if w is not None else None, ctypes.c_void_p(rho_ptr),
                                      ctypes.c_void_p(u_ptr), ctypes.c_void_p(ws_ptr), int(ws_bytes),
                                      ctypes.c_void_p(stream)))
+
+
+def dmk_cheb_ws_bytes(bins: dmk_bins, p: int) -> int:
+    return int(load().dmk_cheb_ws_bytes(ctypes.byref(bins), int(p)))
+
+
+def dmk_cheb_anterp(grid, bins, p, m, rho_ptr, rg_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return int(load().dmk_cheb_anterp(ctypes.byref(grid), ctypes.byref(bins), int(p), int(m),
+                                      ctypes.c_void_p(rho_ptr), ctypes.c_void_p(rg_ptr), ctypes.c_void_p(ws_ptr),
+                                      int(ws_bytes), ctypes.c_void_p(stream)))
+
+
+def dmk_cheb_eval(grid, bins, p, m, ug_ptr, accumulate, u_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return int(load().dmk_cheb_eval(ctypes.byref(grid), ctypes.byref(bins), int(p), int(m), ctypes.c_void_p(ug_ptr),
+                                    int(bool(accumulate)), ctypes.c_void_p(u_ptr), ctypes.c_void_p(ws_ptr),
+                                    int(ws_bytes), ctypes.c_void_p(stream)))
+
+
+def dmk_self_term(kernel, sigma0, w, N, rho_ptr, u_ptr, stream) -> int:
+    return int(load().dmk_self_term(int(kernel), float(sigma0), ctypes.byref(w) if w is not None else None, int(N),
+                                    ctypes.c_void_p(rho_ptr), ctypes.c_void_p(u_ptr), ctypes.c_void_p(stream)))
 
 
 def dmk_version() -> str:

@@ -1,0 +1,287 @@
+// dmk_cheb.hip -- leaf-box Chebyshev grids on gfx950.
+//
+// Every box of the tiling carries a p x p x p grid of first-kind Chebyshev
+// points (Sec. 3.1, upward pass).  This file provides
+//   * anterpolation (upward pass): proxy strengths on the grid of each box,
+//     rho~_q(j) = sum_{a in box} rho_{a,q} l_j(x_a);
+//   * leaf evaluation (downward pass, last step): u_q(x) = sum_j U_q(j) l_j(x)
+//     for the targets x of each box;
+//   * the self-interaction correction of the split (Sec. 2.4): the far field
+//     includes the k-space image of a point's own mollified kernel, removed by
+//     u -= phi(0) rho / (2 pi sigma0) for the harmonic kernel and the
+//     Stokeslet.
+// l_j is the tensor-product Lagrange basis of the box's grid in box-local
+// coordinates t = 2 (y n / L - b) - 1, evaluated with the barycentric formula
+// for first-kind Chebyshev points (weights (-1)^k sin((2k+1) pi / (2p))).
+// Grid values of all boxes form one tensor [m][n0 p][n1 p][n2 p] (index
+// g_i = b_i p + j_i), the layout of the root-level far field.
+//
+// Points are taken in the binning's sorted order (box ranges from box_start),
+// so a box's points are contiguous; results go to the original order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include "dmk_internal.h"
+
+namespace dmk {
+namespace {
+
+struct ChebGeom {
+    double inv[3];  // n_i / L_i, as in the binning
+    int n[3];
+    int p;
+    int64_t N;
+    int64_t G[3];   // n_i p
+};
+
+constexpr int CB_T = 256;
+
+// lag[s][ax][j] = l_j(t_ax(s)) for the sorted points s
+__global__ __launch_bounds__(CB_T) void k_cheb_lagrange(ChebGeom g, const double *__restrict__ ys,
+                                                        const int32_t *__restrict__ skey, double *__restrict__ lag)
+{
+    __shared__ double eta[DMK_FAR_PMAX], wb[DMK_FAR_PMAX];
+    const int p = g.p;
+    for (int k = threadIdx.x; k < p; k += CB_T) {
+        const double a = (double)(2 * k + 1) / (double)(2 * p);
+        eta[k] = cospi(a);
+        wb[k] = (k & 1) ? -sinpi(a) : sinpi(a);
+    }
+    __syncthreads();
+    const int64_t e = (int64_t)blockIdx.x * CB_T + threadIdx.x;
+    if (e >= 3 * g.N) return;
+    const int64_t s = e / 3;
+    const int ax = (int)(e % 3);
+    const int key = skey[s];
+    const int b = ax == 0 ? key / (g.n[1] * g.n[2]) : (ax == 1 ? (key / g.n[2]) % g.n[1] : key % g.n[2]);
+    const double t = 2.0 * (ys[(int64_t)ax * g.N + s] * g.inv[ax] - (double)b) - 1.0;
+    double *out = lag + (s * 3 + ax) * p;
+    int hit = -1;
+    double S = 0.0;
+    for (int k = 0; k < p; ++k) {
+        const double d = t - eta[k];
+        if (d == 0.0) hit = k;
+        S += wb[k] / (d == 0.0 ? 1.0 : d);
+    }
+    if (hit >= 0) {
+        for (int k = 0; k < p; ++k) out[k] = k == hit ? 1.0 : 0.0;
+        return;
+    }
+    const double iS = 1.0 / S;
+    for (int k = 0; k < p; ++k) out[k] = wb[k] / (t - eta[k]) * iS;
+}
+
+// rho_grid[q][g0][g1][g2] = sum over the points s of box (g0/p, g1/p, g2/p)
+// of rho[perm[s]][q] l_{g0%p} l_{g1%p} l_{g2%p}
+template <int M>
+__global__ __launch_bounds__(CB_T) void k_cheb_anterp(ChebGeom g, const int32_t *__restrict__ bs,
+                                                      const int32_t *__restrict__ perm,
+                                                      const double *__restrict__ lag, const double *__restrict__ rho,
+                                                      double *__restrict__ rg)
+{
+    const int64_t tot = g.G[0] * g.G[1] * g.G[2];
+    const int64_t e = (int64_t)blockIdx.x * CB_T + threadIdx.x;
+    if (e >= tot) return;
+    const int p = g.p;
+    const int64_t g0 = e / (g.G[1] * g.G[2]), g1 = (e / g.G[2]) % g.G[1], g2 = e % g.G[2];
+    const int64_t box = ((g0 / p) * g.n[1] + g1 / p) * g.n[2] + g2 / p;
+    const int j0 = (int)(g0 % p), j1 = (int)(g1 % p), j2 = (int)(g2 % p);
+    double acc[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) acc[q] = 0.0;
+    const int s1 = bs[box + 1];
+    for (int s = bs[box]; s < s1; ++s) {
+        const double *l = lag + (int64_t)s * 3 * p;
+        const double w = l[j0] * l[p + j1] * l[2 * p + j2];
+        const int64_t i = perm[s];
+#pragma unroll
+        for (int q = 0; q < M; ++q) acc[q] = fma(w, rho[i * M + q], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < M; ++q) rg[q * tot + e] = acc[q];
+}
+
+// u[perm[s]][q] (+)= sum_j U[q][grid of the box of s](j) l_j(s)
+template <int M, bool ACC>
+__global__ __launch_bounds__(CB_T) void k_cheb_eval(ChebGeom g, const int32_t *__restrict__ skey,
+                                                    const int32_t *__restrict__ perm, const double *__restrict__ lag,
+                                                    const double *__restrict__ U, double *__restrict__ u)
+{
+    const int64_t s = (int64_t)blockIdx.x * CB_T + threadIdx.x;
+    if (s >= g.N) return;
+    const int p = g.p;
+    const int key = skey[s];
+    const int64_t b0 = key / (g.n[1] * g.n[2]), b1 = (key / g.n[2]) % g.n[1], b2 = key % g.n[2];
+    const int64_t tot = g.G[0] * g.G[1] * g.G[2];
+    const double *l = lag + s * 3 * p;
+    double acc[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) acc[q] = 0.0;
+    for (int j0 = 0; j0 < p; ++j0) {
+        double a1[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) a1[q] = 0.0;
+        for (int j1 = 0; j1 < p; ++j1) {
+            const int64_t row = ((b0 * p + j0) * g.G[1] + (b1 * p + j1)) * g.G[2] + b2 * p;
+            double a2[M];
+#pragma unroll
+            for (int q = 0; q < M; ++q) a2[q] = 0.0;
+            for (int j2 = 0; j2 < p; ++j2) {
+                const double w = l[2 * p + j2];
+#pragma unroll
+                for (int q = 0; q < M; ++q) a2[q] = fma(w, U[q * tot + row + j2], a2[q]);
+            }
+            const double w1 = l[p + j1];
+#pragma unroll
+            for (int q = 0; q < M; ++q) a1[q] = fma(w1, a2[q], a1[q]);
+        }
+        const double w0 = l[j0];
+#pragma unroll
+        for (int q = 0; q < M; ++q) acc[q] = fma(w0, a1[q], acc[q]);
+    }
+    const int64_t i = perm[s];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        if constexpr (ACC)
+            u[i * M + q] += acc[q];
+        else
+            u[i * M + q] = acc[q];
+    }
+}
+
+// u[i][j] += -phi(0) / (2 pi sigma0) rho[i][j] (harmonic kernel: 1 component,
+// Stokeslet: 3); phi(0) = 1/sqrt(pi) for the Gaussian, or the PSWF series at
+// t = 0, i.e. u = -1: sum_m (-1)^m c_m
+struct SelfWin {
+    double cheb[DMK_PSWF_MAXTERMS];
+};
+
+__global__ void k_self_term_w(int ncomp, int64_t N, int pswf, int nterms, SelfWin w, double sigma0,
+                              const double *__restrict__ rho, double *__restrict__ u)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= N * ncomp) return;
+    double phi0;
+    if (pswf) {
+        phi0 = 0.0;
+        for (int m = nterms - 1; m >= 0; --m) phi0 += (m & 1) ? -w.cheb[m] : w.cheb[m];
+    } else {
+        phi0 = 1.0 / sqrt(M_PI);
+    }
+    u[e] += -phi0 / (2.0 * M_PI * sigma0) * rho[e];
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+int cheb_geom(const dmk_grid *grid, const dmk_bins *bins, int p, int m, ChebGeom &g)
+{
+    if (!grid || !bins) return DMK_EINVAL;
+    if (grid->D < 0 || grid->D > 3) return DMK_EINVAL;
+    if (p < 1 || p > DMK_FAR_PMAX) return DMK_EINVAL;
+    if (m != 1 && m != 3 && m != 9) return DMK_EINVAL;
+    const int64_t nbox = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+    if (bins->nbox != nbox || bins->N < 0) return DMK_EINVAL;
+    memset(&g, 0, sizeof(g));
+    for (int i = 0; i < 3; ++i) {
+        if (grid->n[i] < 1 || !(grid->L[i] > 0.0)) return DMK_EINVAL;
+        g.n[i] = grid->n[i];
+        g.inv[i] = (double)grid->n[i] / grid->L[i];  // the binning's factor
+        g.G[i] = (int64_t)grid->n[i] * p;
+    }
+    if ((double)g.G[0] * (double)g.G[1] * (double)g.G[2] * m > 9.0e15) return DMK_ESIZE;
+    g.p = p;
+    g.N = bins->N;
+    return DMK_OK;
+}
+
+size_t lag_bytes(int64_t N, int p) { return (size_t)(sizeof(double) * 3 * p * (N > 0 ? N : 1) + 256); }
+
+}  // namespace
+}  // namespace dmk
+
+using namespace dmk;
+
+extern "C" size_t dmk_cheb_ws_bytes(const dmk_bins *bins, int p)
+{
+    if (!bins || bins->N < 0 || p < 1 || p > DMK_FAR_PMAX) return 0;
+    return lag_bytes(bins->N, p);
+}
+
+extern "C" int dmk_cheb_anterp(const dmk_grid *grid, const dmk_bins *bins, int p, int m, const double *rho,
+                               double *rho_grid, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    ChebGeom g;
+    const int st = cheb_geom(grid, bins, p, m, g);
+    if (st != DMK_OK) return st;
+    if (!rho_grid || !ws || (g.N > 0 && !rho)) return DMK_EINVAL;
+    if (ws_bytes < lag_bytes(g.N, p)) return DMK_ESIZE;
+    double *lag = (double *)ws;
+    if (g.N > 0)
+        hipLaunchKernelGGL(k_cheb_lagrange, dim3(nblk(3 * g.N, CB_T)), dim3(CB_T), 0, stream, g, bins->ys,
+                           bins->skey, lag);
+    const int64_t tot = g.G[0] * g.G[1] * g.G[2];
+    const dim3 grd(nblk(tot, CB_T));
+    switch (m) {
+    case 1: hipLaunchKernelGGL(k_cheb_anterp<1>, grd, dim3(CB_T), 0, stream, g, bins->box_start, bins->perm, lag, rho, rho_grid); break;
+    case 3: hipLaunchKernelGGL(k_cheb_anterp<3>, grd, dim3(CB_T), 0, stream, g, bins->box_start, bins->perm, lag, rho, rho_grid); break;
+    default: hipLaunchKernelGGL(k_cheb_anterp<9>, grd, dim3(CB_T), 0, stream, g, bins->box_start, bins->perm, lag, rho, rho_grid); break;
+    }
+    DMK_HIP_CHECK(hipGetLastError());
+    return DMK_OK;
+}
+
+extern "C" int dmk_cheb_eval(const dmk_grid *grid, const dmk_bins *bins, int p, int m, const double *u_grid,
+                             int accumulate, double *u, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    ChebGeom g;
+    const int st = cheb_geom(grid, bins, p, m, g);
+    if (st != DMK_OK) return st;
+    if (!u_grid || !ws || (g.N > 0 && !u)) return DMK_EINVAL;
+    if (ws_bytes < lag_bytes(g.N, p)) return DMK_ESIZE;
+    if (g.N == 0) return DMK_OK;
+    double *lag = (double *)ws;
+    hipLaunchKernelGGL(k_cheb_lagrange, dim3(nblk(3 * g.N, CB_T)), dim3(CB_T), 0, stream, g, bins->ys, bins->skey,
+                       lag);
+    const dim3 grd(nblk(g.N, CB_T));
+    const int32_t *sk = bins->skey, *pm = bins->perm;
+    if (accumulate) {
+        switch (m) {
+        case 1: hipLaunchKernelGGL((k_cheb_eval<1, true>), grd, dim3(CB_T), 0, stream, g, sk, pm, lag, u_grid, u); break;
+        case 3: hipLaunchKernelGGL((k_cheb_eval<3, true>), grd, dim3(CB_T), 0, stream, g, sk, pm, lag, u_grid, u); break;
+        default: hipLaunchKernelGGL((k_cheb_eval<9, true>), grd, dim3(CB_T), 0, stream, g, sk, pm, lag, u_grid, u); break;
+        }
+    } else {
+        switch (m) {
+        case 1: hipLaunchKernelGGL((k_cheb_eval<1, false>), grd, dim3(CB_T), 0, stream, g, sk, pm, lag, u_grid, u); break;
+        case 3: hipLaunchKernelGGL((k_cheb_eval<3, false>), grd, dim3(CB_T), 0, stream, g, sk, pm, lag, u_grid, u); break;
+        default: hipLaunchKernelGGL((k_cheb_eval<9, false>), grd, dim3(CB_T), 0, stream, g, sk, pm, lag, u_grid, u); break;
+        }
+    }
+    DMK_HIP_CHECK(hipGetLastError());
+    return DMK_OK;
+}
+
+extern "C" int dmk_self_term(int kernel, double sigma0, const dmk_pswf *win, int64_t N, const double *rho, double *u,
+                             hipStream_t stream)
+{
+    if (kernel < 0 || kernel > 3 || N < 0) return DMK_EINVAL;
+    if (!(sigma0 > 0.0) || !isfinite(sigma0)) return DMK_ECUTOFF;
+    SelfWin w;
+    memset(&w, 0, sizeof(w));
+    int nterms = 0;
+    if (win) {
+        if (!(win->c > 0.0) || !(win->c <= DMK_PSWF_CMAX) || win->nterms64 < 1 ||
+            win->nterms64 > DMK_PSWF_MAXTERMS)
+            return DMK_EUNSUPPORTED;
+        nterms = win->nterms64;
+        for (int m = 0; m < DMK_PSWF_MAXTERMS; ++m) w.cheb[m] = win->cheb[0][m];
+    }
+    if (kernel == 2 || kernel == 3 || N == 0) return DMK_OK;  // no self term for stresslet and rotlet
+    if (!rho || !u) return DMK_EINVAL;
+    const int nc = kernel == 0 ? 1 : 3;
+    hipLaunchKernelGGL(k_self_term_w, dim3(nblk(N * nc, 256)), dim3(256), 0, stream, nc, N, win ? 1 : 0, nterms, w,
+                       sigma0, rho, u);
+    DMK_HIP_CHECK(hipGetLastError());
+    return DMK_OK;
+}

@@ -46,3 +46,88 @@ def far3p_eval(Lv, M, p, K, kernel, sigma0: float, rho_grid: torch.Tensor, pswf_
     if code != L.DMK_OK:
         raise L.DmkError(code, "dmk_far3p_eval")
     return u
+
+
+def cheb_workspace(bins, p: int) -> torch.Tensor:
+    nb = L.dmk_cheb_ws_bytes(bins.c, p)
+    if nb == 0:
+        raise L.DmkError(L.DMK_EINVAL, "dmk_cheb_ws_bytes")
+    return torch.empty(nb // 8 + 32, dtype=torch.float64, device=bins._arena.device)
+
+
+def cheb_anterp(bins, p: int, rho: torch.Tensor, out=None, ws=None) -> torch.Tensor:
+    """Proxy strengths rho_grid[m, n0 p, n1 p, n2 p] of the binned points with
+    strengths rho[N, m] on the leaf boxes' Chebyshev grids."""
+    m = rho.shape[1] if rho.dim() == 2 else -1
+    _require_dev_f64(rho, "rho", (bins.N, m))
+    G = tuple(int(bins.grid.n[i]) * int(p) for i in range(3))
+    rg = out if out is not None else torch.empty((m,) + G, dtype=torch.float64, device=rho.device)
+    _require_dev_f64(rg, "rho_grid", (m,) + G)
+    if ws is None:
+        ws = cheb_workspace(bins, p)
+    code = L.dmk_cheb_anterp(bins.grid, bins.c, p, m, rho.data_ptr(), rg.data_ptr(), ws.data_ptr(),
+                             ws.numel() * 8, _stream())
+    if code != L.DMK_OK:
+        raise L.DmkError(code, "dmk_cheb_anterp")
+    return rg
+
+
+def cheb_eval(bins, p: int, u_grid: torch.Tensor, out=None, accumulate: bool = False, ws=None) -> torch.Tensor:
+    """u[N, m] at the binned points from grid values u_grid[m, n0 p, n1 p, n2 p]
+    (added to ``out`` when accumulate)."""
+    m = u_grid.shape[0]
+    G = tuple(int(bins.grid.n[i]) * int(p) for i in range(3))
+    _require_dev_f64(u_grid, "u_grid", (m,) + G)
+    if out is None:
+        if accumulate:
+            raise ValueError("accumulate needs out")
+        out = torch.empty((bins.N, m), dtype=torch.float64, device=u_grid.device)
+    _require_dev_f64(out, "u", (bins.N, m))
+    if ws is None:
+        ws = cheb_workspace(bins, p)
+    code = L.dmk_cheb_eval(bins.grid, bins.c, p, m, u_grid.data_ptr(), accumulate, out.data_ptr(), ws.data_ptr(),
+                           ws.numel() * 8, _stream())
+    if code != L.DMK_OK:
+        raise L.DmkError(code, "dmk_cheb_eval")
+    return out
+
+
+def self_term(kernel, sigma0: float, rho: torch.Tensor, u: torch.Tensor, pswf_c: float = None) -> torch.Tensor:
+    """u += self-interaction correction of the split (in place)."""
+    k = _kid(kernel)
+    _require_dev_f64(rho, "rho", (rho.shape[0], L.M_IN[k]))
+    _require_dev_f64(u, "u", (rho.shape[0], L.M_OUT[k]))
+    w = pswf_window(pswf_c) if pswf_c is not None else None
+    code = L.dmk_self_term(k, sigma0, w, rho.shape[0], rho.data_ptr(), u.data_ptr(), _stream())
+    if code != L.DMK_OK:
+        raise L.DmkError(code, "dmk_self_term")
+    return u
+
+
+def single_level_3p(x: torch.Tensor, rho: torch.Tensor, kernel, Lv, c: float, p: int, K=None,
+                    prec="fp64") -> torch.Tensor:
+    """Triply periodic sum with the PSWF split at the root level only: the
+    top cubes (side h0 = min L_i, tiling the cell exactly) are the leaf boxes.
+    u = residual (support nu) + far field (proxy strengths on the cubes'
+    grids -> far field on the grids -> evaluation at the points) + self term.
+    K defaults to the mode ranges of the parameter tables (table_modes).
+
+    The support is nu = h0 (1 - 2^-30), a hair inside the cube side: a
+    point's own periodic images lie at distance exactly h0 along the axes of
+    side h0, and the PSWF residual kernels jump by O(phi(1)) (of the order of
+    the tolerance) at the edge of their support, so such ties are kept
+    clearly outside it instead of being left to the rounding of the image
+    shift."""
+    from .residual import residual_eval, tree_bin
+    h0 = min(float(v) for v in Lv)
+    nu = h0 * (1.0 - 2.0 ** -30)
+    M = tuple(int(round(float(v) / h0)) for v in Lv)
+    if K is None:
+        K = table_modes(c, Lv, h0)
+    bins = tree_bin(Lv, 3, M, x)
+    u = residual_eval(bins, kernel, prec, nu, nu, rho, pswf_c=c)
+    ws = cheb_workspace(bins, p)
+    rg = cheb_anterp(bins, p, rho, ws=ws)
+    ug = far3p_eval(Lv, M, p, K, kernel, nu, rg, pswf_c=c)
+    cheb_eval(bins, p, ug, out=u, accumulate=True, ws=ws)
+    return self_term(kernel, nu, rho, u, pswf_c=c)

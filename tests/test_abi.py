@@ -156,3 +156,25 @@ def test_far3p_host_argument_checks():
         g = L.make_far_grid(*args)
         assert L.dmk_far3p_ws_bytes(g, 0) == 0
         assert L.dmk_far3p_eval(g, 0, 1.0, None, fake, fake, fake, 1 << 30, 0) == L.DMK_EINVAL
+
+
+def test_cheb_and_self_term_host_argument_checks():
+    g = L.make_grid((1, 1, 1), 3, (2, 2, 2))
+    b = L.dmk_bins()
+    nb = L.dmk_bins_bytes(g, 100)
+    fake = 1 << 40  # never dereferenced: every check below fails before a launch
+    assert L.dmk_bins_carve(g, 100, fake, nb, b) == L.DMK_OK
+    ws = L.dmk_cheb_ws_bytes(b, 8)
+    assert ws >= 100 * 3 * 8 * 8
+    assert L.dmk_cheb_ws_bytes(b, 0) == 0 and L.dmk_cheb_ws_bytes(b, L.FAR_PMAX + 1) == 0
+    assert L.dmk_cheb_anterp(g, b, 8, 1, fake, fake, fake, ws - 1, 0) == L.DMK_ESIZE
+    assert L.dmk_cheb_anterp(g, b, 8, 2, fake, fake, fake, ws, 0) == L.DMK_EINVAL
+    assert L.dmk_cheb_eval(g, b, 8, 3, fake, 0, fake, fake, ws - 1, 0) == L.DMK_ESIZE
+    assert L.dmk_cheb_eval(g, b, 0, 3, fake, 0, fake, fake, ws, 0) == L.DMK_EINVAL
+    other = L.make_grid((1, 1, 1), 3, (3, 2, 2))  # bins of another tiling
+    assert L.dmk_cheb_eval(other, b, 8, 1, fake, 0, fake, fake, ws, 0) == L.DMK_EINVAL
+    assert L.dmk_self_term(4, 1.0, None, 10, fake, fake, 0) == L.DMK_EINVAL
+    assert L.dmk_self_term(0, 0.0, None, 10, fake, fake, 0) == L.DMK_ECUTOFF
+    assert L.dmk_self_term(0, 1.0, L.dmk_pswf(), 10, fake, fake, 0) == L.DMK_EUNSUPPORTED
+    assert L.dmk_self_term(0, 1.0, None, 10, 0, fake, 0) == L.DMK_EINVAL
+    assert L.dmk_self_term(2, 1.0, None, 10, 0, 0, 0) == L.DMK_OK  # stresslet: nothing to add
