@@ -37,7 +37,11 @@ struct ChebGeom {
 
 constexpr int CB_T = 256;
 
-// lag[s][ax][j] = l_j(t_ax(s)) for the sorted points s
+// l_j(t_ax(s)) for the sorted points s, stored node-fastest lag[s][ax][j]
+// (anterpolation: the lanes of a wavefront are consecutive nodes of one point)
+// or point-fastest lag[ax][j][s] (PT; evaluation: the lanes are consecutive
+// points)
+template <bool PT>
 __global__ __launch_bounds__(CB_T) void k_cheb_lagrange(ChebGeom g, const double *__restrict__ ys,
                                                         const int32_t *__restrict__ skey, double *__restrict__ lag)
 {
@@ -56,7 +60,8 @@ __global__ __launch_bounds__(CB_T) void k_cheb_lagrange(ChebGeom g, const double
     const int key = skey[s];
     const int b = ax == 0 ? key / (g.n[1] * g.n[2]) : (ax == 1 ? (key / g.n[2]) % g.n[1] : key % g.n[2]);
     const double t = 2.0 * (ys[(int64_t)ax * g.N + s] * g.inv[ax] - (double)b) - 1.0;
-    double *out = lag + (s * 3 + ax) * p;
+    double *out = PT ? lag + (int64_t)ax * p * g.N + s : lag + (s * 3 + ax) * p;
+    const int64_t st = PT ? g.N : 1;
     int hit = -1;
     double S = 0.0;
     for (int k = 0; k < p; ++k) {
@@ -65,11 +70,11 @@ __global__ __launch_bounds__(CB_T) void k_cheb_lagrange(ChebGeom g, const double
         S += wb[k] / (d == 0.0 ? 1.0 : d);
     }
     if (hit >= 0) {
-        for (int k = 0; k < p; ++k) out[k] = k == hit ? 1.0 : 0.0;
+        for (int k = 0; k < p; ++k) out[k * st] = k == hit ? 1.0 : 0.0;
         return;
     }
     const double iS = 1.0 / S;
-    for (int k = 0; k < p; ++k) out[k] = wb[k] / (t - eta[k]) * iS;
+    for (int k = 0; k < p; ++k) out[k * st] = wb[k] / (t - eta[k]) * iS;
 }
 
 // rho_grid[q][g0][g1][g2] = sum over the points s of box (g0/p, g1/p, g2/p)
@@ -91,6 +96,7 @@ __global__ __launch_bounds__(CB_T) void k_cheb_anterp(ChebGeom g, const int32_t 
 #pragma unroll
     for (int q = 0; q < M; ++q) acc[q] = 0.0;
     const int s1 = bs[box + 1];
+#pragma unroll 4
     for (int s = bs[box]; s < s1; ++s) {
         const double *l = lag + (int64_t)s * 3 * p;
         const double w = l[j0] * l[p + j1] * l[2 * p + j2];
@@ -114,7 +120,8 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval(ChebGeom g, const int32_t *_
     const int key = skey[s];
     const int64_t b0 = key / (g.n[1] * g.n[2]), b1 = (key / g.n[2]) % g.n[1], b2 = key % g.n[2];
     const int64_t tot = g.G[0] * g.G[1] * g.G[2];
-    const double *l = lag + s * 3 * p;
+    const int64_t N = g.N;
+    const double *l0 = lag + s, *l1 = lag + (int64_t)p * N + s, *l2 = lag + 2 * (int64_t)p * N + s;
     double acc[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) acc[q] = 0.0;
@@ -127,16 +134,17 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval(ChebGeom g, const int32_t *_
             double a2[M];
 #pragma unroll
             for (int q = 0; q < M; ++q) a2[q] = 0.0;
+#pragma unroll 4
             for (int j2 = 0; j2 < p; ++j2) {
-                const double w = l[2 * p + j2];
+                const double w = l2[j2 * N];
 #pragma unroll
                 for (int q = 0; q < M; ++q) a2[q] = fma(w, U[q * tot + row + j2], a2[q]);
             }
-            const double w1 = l[p + j1];
+            const double w1 = l1[j1 * N];
 #pragma unroll
             for (int q = 0; q < M; ++q) a1[q] = fma(w1, a2[q], a1[q]);
         }
-        const double w0 = l[j0];
+        const double w0 = l0[j0 * N];
 #pragma unroll
         for (int q = 0; q < M; ++q) acc[q] = fma(w0, a1[q], acc[q]);
     }
@@ -218,7 +226,7 @@ extern "C" int dmk_cheb_anterp(const dmk_grid *grid, const dmk_bins *bins, int p
     if (ws_bytes < lag_bytes(g.N, p)) return DMK_ESIZE;
     double *lag = (double *)ws;
     if (g.N > 0)
-        hipLaunchKernelGGL(k_cheb_lagrange, dim3(nblk(3 * g.N, CB_T)), dim3(CB_T), 0, stream, g, bins->ys,
+        hipLaunchKernelGGL(k_cheb_lagrange<false>, dim3(nblk(3 * g.N, CB_T)), dim3(CB_T), 0, stream, g, bins->ys,
                            bins->skey, lag);
     const int64_t tot = g.G[0] * g.G[1] * g.G[2];
     const dim3 grd(nblk(tot, CB_T));
@@ -241,8 +249,8 @@ extern "C" int dmk_cheb_eval(const dmk_grid *grid, const dmk_bins *bins, int p, 
     if (ws_bytes < lag_bytes(g.N, p)) return DMK_ESIZE;
     if (g.N == 0) return DMK_OK;
     double *lag = (double *)ws;
-    hipLaunchKernelGGL(k_cheb_lagrange, dim3(nblk(3 * g.N, CB_T)), dim3(CB_T), 0, stream, g, bins->ys, bins->skey,
-                       lag);
+    hipLaunchKernelGGL(k_cheb_lagrange<true>, dim3(nblk(3 * g.N, CB_T)), dim3(CB_T), 0, stream, g, bins->ys,
+                       bins->skey, lag);
     const dim3 grd(nblk(g.N, CB_T));
     const int32_t *sk = bins->skey, *pm = bins->perm;
     if (accumulate) {

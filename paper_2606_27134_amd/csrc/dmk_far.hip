@@ -89,6 +89,7 @@ __global__ void k_mode(const void *__restrict__ Xv, const double2 *__restrict__ 
     const int64_t a = t / ((int64_t)C * O);
     double re = 0.0, im = 0.0;
     const int64_t xb = a * I * C + c;
+#pragma unroll 4
     for (int i = 0; i < I; ++i) {
         const double2 e = E[i * si + o * so];
         const double ei = CONJ ? -e.y : e.y;
@@ -122,8 +123,10 @@ __device__ inline double win_phi(const FarWin &w, double t)
     return fma(u, b1, w.cheb[0] - b2);
 }
 
-// phihat(q) and phihat'(q)
-__device__ inline void win_hat(const FarWin &w, double q, double &ph, double &dph)
+// phihat(q) and phihat'(q); the quadrature nodes are split over the 64
+// lanes of the wavefront and the partial sums combined with shuffles (in a
+// fixed order), so every lane returns the same values
+__device__ inline void win_hat(const FarWin &w, double q, int lane, double &ph, double &dph)
 {
     if (!w.pswf) {
         ph = exp(-0.25 * q * q);
@@ -136,27 +139,36 @@ __device__ inline void win_hat(const FarWin &w, double q, double &ph, double &dp
     const int np = 2 + (int)(q * 0.25);
     const double hw = 1.0 / np;
     double a = 0.0, b = 0.0;
-    for (int k = 0; k < np; ++k)
-        for (int i = 0; i < GL_N; ++i) {
-            const double t = (k + w.gx[i]) * hw;
-            const double f = w.gw[i] * win_phi(w, t);
-            double sn, cs;
-            sincos(q * t, &sn, &cs);
-            a = fma(f, cs, a);
-            b = fma(f * t, sn, b);
-        }
+    for (int i = lane; i < np * GL_N; i += WAVE) {
+        const int k = i / GL_N, nd = i - k * GL_N;
+        const double t = (k + w.gx[nd]) * hw;
+        const double f = w.gw[nd] * win_phi(w, t);
+        double sn, cs;
+        sincos(q * t, &sn, &cs);
+        a = fma(f, cs, a);
+        b = fma(f * t, sn, b);
+    }
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
     ph = 2.0 * hw * a;
     dph = -2.0 * hw * b;
 }
 
 // W[j][m] = sum_q Khat_jq(k_m) chi[q][m] for every mode m (0 at k = 0)
+// (one wavefront per mode)
+constexpr int FW_T = 256;
+
 template <int KERN>
-__global__ void k_far_weights(FarGeom g, FarWin w, const double2 *__restrict__ chi, double2 *__restrict__ Wt)
+__global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, FarWin w, const double2 *__restrict__ chi,
+                                                      double2 *__restrict__ Wt)
 {
     constexpr int MI = KERN == 0 ? 1 : (KERN == 2 ? 9 : 3);
     constexpr int MO = KERN == 0 ? 1 : 3;
     const int64_t nm = (int64_t)g.W[0] * g.W[1] * g.W[2];
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t m = (int64_t)blockIdx.x * (FW_T / WAVE) + threadIdx.x / WAVE;
     if (m >= nm) return;
     const int n0 = (int)(m / ((int64_t)g.W[1] * g.W[2])) - g.K[0];
     const int n1 = (int)((m / g.W[2]) % g.W[1]) - g.K[1];
@@ -168,7 +180,7 @@ __global__ void k_far_weights(FarGeom g, FarWin w, const double2 *__restrict__ c
         const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
         const double q = sqrt(k2) * w.sigma;
         double ph, dph;
-        win_hat(w, q, ph, dph);
+        win_hat(w, q, lane, ph, dph);
         const double Hh = ph / k2;
         const double Bh = (ph - 0.5 * q * dph) / (k2 * k2);
         double2 x[MI];
@@ -210,7 +222,8 @@ __global__ void k_far_weights(FarGeom g, FarWin w, const double2 *__restrict__ c
             for (int j = 0; j < 3; ++j) out[j] = make_double2(-h * ci[j], h * cr[j]);
         }
     }
-    for (int j = 0; j < MO; ++j) Wt[j * nm + m] = out[j];
+    if (lane == 0)
+        for (int j = 0; j < MO; ++j) Wt[j * nm + m] = out[j];
 }
 
 int m_in_k(int k) { return k == 0 ? 1 : (k == 2 ? 9 : 3); }
@@ -377,10 +390,10 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     // mode weights
     const int64_t nm = (int64_t)W0 * W1 * W2;
     switch (kernel) {
-    case 0: hipLaunchKernelGGL(k_far_weights<0>, dim3(nblk(nm, 64)), dim3(64), 0, stream, g, w, CHI, WT); break;
-    case 1: hipLaunchKernelGGL(k_far_weights<1>, dim3(nblk(nm, 64)), dim3(64), 0, stream, g, w, CHI, WT); break;
-    case 2: hipLaunchKernelGGL(k_far_weights<2>, dim3(nblk(nm, 64)), dim3(64), 0, stream, g, w, CHI, WT); break;
-    default: hipLaunchKernelGGL(k_far_weights<3>, dim3(nblk(nm, 64)), dim3(64), 0, stream, g, w, CHI, WT); break;
+    case 0: hipLaunchKernelGGL(k_far_weights<0>, dim3(nblk(nm, FW_T / WAVE)), dim3(FW_T), 0, stream, g, w, CHI, WT); break;
+    case 1: hipLaunchKernelGGL(k_far_weights<1>, dim3(nblk(nm, FW_T / WAVE)), dim3(FW_T), 0, stream, g, w, CHI, WT); break;
+    case 2: hipLaunchKernelGGL(k_far_weights<2>, dim3(nblk(nm, FW_T / WAVE)), dim3(FW_T), 0, stream, g, w, CHI, WT); break;
+    default: hipLaunchKernelGGL(k_far_weights<3>, dim3(nblk(nm, FW_T / WAVE)), dim3(FW_T), 0, stream, g, w, CHI, WT); break;
     }
     // evaluation on the grids (eq. (eval_tensor)): contract n0, n1, n2 with E
     mode<false, false, false>(WT, E0, J, W0, G0, (int)((int64_t)W1 * W2), 1, W0, 1.0, V1, stream);
