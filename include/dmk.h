@@ -1,6 +1,9 @@
 /*
  * dmk.h -- C ABI of libdmkloc: the leaf-level residual (short-range) kernel
- * interaction of the periodized DMK method on one AMD MI355X (gfx950).
+ * interaction of the periodized DMK method on one AMD MI355X (gfx950), with
+ * the binning it runs on and, further down, the root-level far field of the
+ * triply periodic split, the leaf boxes' Chebyshev grids (proxy strengths,
+ * evaluation at targets) and the self-interaction correction.
  *
  * Operation (Sec. 2.3, eq. (u_local); image set P_D of eq. (periodic-images),
  * Sec. 1): for every point x_b of the cell [0,L1)x[0,L2)x[0,L3), whose first

@@ -78,34 +78,66 @@ __global__ __launch_bounds__(CB_T) void k_cheb_lagrange(ChebGeom g, const double
 }
 
 // rho_grid[q][g0][g1][g2] = sum over the points s of box (g0/p, g1/p, g2/p)
-// of rho[perm[s]][q] l_{g0%p} l_{g1%p} l_{g2%p}
+// of rho[perm[s]][q] l_{g0%p} l_{g1%p} l_{g2%p}.  A workgroup takes CB_NODES
+// nodes of one box; the box's points are staged in LDS in chunks of `ch`
+// (l0, l1 and l2 * rho per point), and every thread sums over a chunk for its
+// nodes.  More than one chunk: the first writes, later ones add (the same
+// thread owns a node throughout, so there are no races).
+constexpr int CB_NODES = 2048;
+
 template <int M>
-__global__ __launch_bounds__(CB_T) void k_cheb_anterp(ChebGeom g, const int32_t *__restrict__ bs,
+__global__ __launch_bounds__(CB_T) void k_cheb_anterp(ChebGeom g, int ch, int nsplit, const int32_t *__restrict__ bs,
                                                       const int32_t *__restrict__ perm,
                                                       const double *__restrict__ lag, const double *__restrict__ rho,
                                                       double *__restrict__ rg)
 {
-    const int64_t tot = g.G[0] * g.G[1] * g.G[2];
-    const int64_t e = (int64_t)blockIdx.x * CB_T + threadIdx.x;
-    if (e >= tot) return;
+    extern __shared__ double sm[];
     const int p = g.p;
-    const int64_t g0 = e / (g.G[1] * g.G[2]), g1 = (e / g.G[2]) % g.G[1], g2 = e % g.G[2];
-    const int64_t box = ((g0 / p) * g.n[1] + g1 / p) * g.n[2] + g2 / p;
-    const int j0 = (int)(g0 % p), j1 = (int)(g1 % p), j2 = (int)(g2 % p);
-    double acc[M];
+    const int64_t box = blockIdx.x / nsplit;
+    const int part = blockIdx.x - (int)(box * nsplit);
+    const int64_t b0 = box / ((int64_t)g.n[1] * g.n[2]), b1 = (box / g.n[2]) % g.n[1], b2 = box % g.n[2];
+    const int64_t tot = g.G[0] * g.G[1] * g.G[2];
+    const int nn = p * p * p;
+    const int e0 = part * CB_NODES, e1 = min(nn, e0 + CB_NODES);
+    double *L0 = sm, *L1 = sm + ch * p, *Cq = sm + 2 * ch * p;
+    const int sb = bs[box], se = bs[box + 1];
+    const int npass = max(1, (se - sb + ch - 1) / ch);
+    for (int ps = 0; ps < npass; ++ps) {
+        const int c0 = sb + ps * ch;
+        const int nc = max(0, min(ch, se - c0));
+        __syncthreads();  // the previous chunk is no longer read
+        for (int e = threadIdx.x; e < nc * p; e += CB_T) {
+            const int si = e / p, j = e - si * p;
+            const int64_t s = c0 + si;
+            const double *l = lag + s * 3 * p;
+            L0[si * p + j] = l[j];
+            L1[si * p + j] = l[p + j];
+            const double l2 = l[2 * p + j];
+            const int64_t i = perm[s];
 #pragma unroll
-    for (int q = 0; q < M; ++q) acc[q] = 0.0;
-    const int s1 = bs[box + 1];
-#pragma unroll 4
-    for (int s = bs[box]; s < s1; ++s) {
-        const double *l = lag + (int64_t)s * 3 * p;
-        const double w = l[j0] * l[p + j1] * l[2 * p + j2];
-        const int64_t i = perm[s];
+            for (int q = 0; q < M; ++q) Cq[(q * ch + si) * p + j] = l2 * rho[i * M + q];
+        }
+        __syncthreads();
+        for (int e = e0 + threadIdx.x; e < e1; e += CB_T) {
+            const int j0 = e / (p * p), j1 = (e / p) % p, j2 = e % p;
+            double acc[M];
 #pragma unroll
-        for (int q = 0; q < M; ++q) acc[q] = fma(w, rho[i * M + q], acc[q]);
+            for (int q = 0; q < M; ++q) acc[q] = 0.0;
+            for (int si = 0; si < nc; ++si) {
+                const double w = L0[si * p + j0] * L1[si * p + j1];
+#pragma unroll
+                for (int q = 0; q < M; ++q) acc[q] = fma(w, Cq[(q * ch + si) * p + j2], acc[q]);
+            }
+            const int64_t idx = ((b0 * p + j0) * g.G[1] + (b1 * p + j1)) * g.G[2] + b2 * p + j2;
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                if (ps == 0)
+                    rg[q * tot + idx] = acc[q];
+                else
+                    rg[q * tot + idx] += acc[q];
+            }
+        }
     }
-#pragma unroll
-    for (int q = 0; q < M; ++q) rg[q * tot + e] = acc[q];
 }
 
 // u[perm[s]][q] (+)= sum_j U[q][grid of the box of s](j) l_j(s)
@@ -228,12 +260,17 @@ extern "C" int dmk_cheb_anterp(const dmk_grid *grid, const dmk_bins *bins, int p
     if (g.N > 0)
         hipLaunchKernelGGL(k_cheb_lagrange<false>, dim3(nblk(3 * g.N, CB_T)), dim3(CB_T), 0, stream, g, bins->ys,
                            bins->skey, lag);
-    const int64_t tot = g.G[0] * g.G[1] * g.G[2];
-    const dim3 grd(nblk(tot, CB_T));
+    // points per LDS chunk: (2 + m) p doubles each, within 48 KB
+    const int ch = max(1, min(256, 49152 / ((2 + m) * p * 8)));
+    const int nsplit = (p * p * p + CB_NODES - 1) / CB_NODES;
+    const int64_t nwg = (g.G[0] / p) * (g.G[1] / p) * (g.G[2] / p) * nsplit;
+    if (nwg > 0x7fffffff) return DMK_ESIZE;
+    const dim3 grd((unsigned)nwg);
+    const size_t lds = sizeof(double) * (size_t)(2 + m) * ch * p;
     switch (m) {
-    case 1: hipLaunchKernelGGL(k_cheb_anterp<1>, grd, dim3(CB_T), 0, stream, g, bins->box_start, bins->perm, lag, rho, rho_grid); break;
-    case 3: hipLaunchKernelGGL(k_cheb_anterp<3>, grd, dim3(CB_T), 0, stream, g, bins->box_start, bins->perm, lag, rho, rho_grid); break;
-    default: hipLaunchKernelGGL(k_cheb_anterp<9>, grd, dim3(CB_T), 0, stream, g, bins->box_start, bins->perm, lag, rho, rho_grid); break;
+    case 1: hipLaunchKernelGGL(k_cheb_anterp<1>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bins->box_start, bins->perm, lag, rho, rho_grid); break;
+    case 3: hipLaunchKernelGGL(k_cheb_anterp<3>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bins->box_start, bins->perm, lag, rho, rho_grid); break;
+    default: hipLaunchKernelGGL(k_cheb_anterp<9>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bins->box_start, bins->perm, lag, rho, rho_grid); break;
     }
     DMK_HIP_CHECK(hipGetLastError());
     return DMK_OK;

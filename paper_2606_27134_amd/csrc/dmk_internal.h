@@ -29,7 +29,6 @@ constexpr int TILE_NW = DMK_WAVES_PER_TILE;  // wavefronts per tile workgroup
 #define DMK_TILE_ZMAX 46
 #endif
 constexpr int TILE_ZMAX = DMK_TILE_ZMAX;  // z-boxes per multi-box tile (<= 64 slabs)
-constexpr int TILE_PAD = 64;      // sentinel slots after the staged sources
 
 // tiles[t] = {col, z0, z1 or -(z+1) for a dense tile, first target}
 struct TileDesc {
