@@ -190,6 +190,104 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval(ChebGeom g, const int32_t *_
     }
 }
 
+// The same evaluation as a dense contraction on the FP64 matrix cores, for
+// boxes holding many points.  For a block of 16 points of one box,
+//   V[i][n] = sum_{j2} l2(s_i, j2) U[n][j2],   n = (j0, j1),
+// is a (16 x p) by (p x p^2) product, done with v_mfma_f64_16x16x4 (A: lane l
+// holds A[l % 16][l / 16], B: B[l / 16][l % 16], D: D[4 r + l / 16][l % 16]);
+// each D element is then weighted by l0(s_i, j0) l1(s_i, j1) and the 16
+// lanes that hold a point's row are summed with shuffles.  One workgroup per
+// box; its wavefronts take the box's 16-point blocks in turn.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int KMAX = DMK_FAR_PMAX / 4;
+
+template <int M, bool ACC>
+__global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32_t *__restrict__ bs,
+                                                         const int32_t *__restrict__ perm,
+                                                         const double *__restrict__ lag,
+                                                         const double *__restrict__ U, double *__restrict__ u)
+{
+    const int p = g.p;
+    const int64_t N = g.N;
+    const int64_t box = blockIdx.x;
+    const int64_t b0 = box / ((int64_t)g.n[1] * g.n[2]), b1 = (box / g.n[2]) % g.n[1], b2 = box % g.n[2];
+    const int64_t tot = g.G[0] * g.G[1] * g.G[2];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x / WAVE;
+    const int li = lane & 15, lk = lane >> 4;  // A row / B column, A column / B row
+    const int sb = bs[box], se = bs[box + 1];
+    const int nblock = (se - sb + 15) / 16;
+    const int pp = p * p;
+    const int nkk = (p + 3) / 4;
+    for (int blk = wv; blk < nblock; blk += CB_T / WAVE) {
+        const int s0 = sb + blk * 16;
+        const int nv = min(16, se - s0);
+        // A fragments: l2 of point li at j2 = 4 kk + lk
+        double afr[KMAX];
+#pragma unroll
+        for (int kk = 0; kk < KMAX; ++kk) {
+            const int k = 4 * kk + lk;
+            afr[kk] = (kk < nkk && k < p && li < nv) ? lag[(int64_t)(2 * p + k) * N + s0 + li] : 0.0;
+        }
+        double part[M][4];
+#pragma unroll
+        for (int q = 0; q < M; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[q][r] = 0.0;
+        for (int n0 = 0; n0 < pp; n0 += 16) {
+            const int n = n0 + li;  // this lane's B / D column
+            const bool nok = n < pp;
+            const int j0 = nok ? n / p : 0, j1 = nok ? n - (n / p) * p : 0;
+            const int64_t row = ((b0 * p + j0) * g.G[1] + (b1 * p + j1)) * g.G[2] + b2 * p;
+            dbl4 d[M];
+#pragma unroll
+            for (int q = 0; q < M; ++q) d[q] = (dbl4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < KMAX; ++kk) {
+                if (kk < nkk) {
+                    const int k = 4 * kk + lk;
+#pragma unroll
+                    for (int q = 0; q < M; ++q) {
+                        const double bv = (nok && k < p) ? U[q * tot + row + k] : 0.0;
+                        d[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[kk], bv, d[q], 0, 0, 0);
+                    }
+                }
+            }
+            // weights of the four D rows this lane holds (points 4 r + lk)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 4 * r + lk;
+                const double w = (nok && i < nv) ? lag[(int64_t)j0 * N + s0 + i] * lag[(int64_t)(p + j1) * N + s0 + i]
+                                                 : 0.0;
+#pragma unroll
+                for (int q = 0; q < M; ++q) part[q][r] = fma(w, d[q][r], part[q][r]);
+            }
+        }
+        // sum over the 16 lanes of a row group, in a fixed order
+#pragma unroll
+        for (int q = 0; q < M; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                for (int off = 8; off > 0; off >>= 1) part[q][r] += __shfl_xor(part[q][r], off);
+        if (li == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 4 * r + lk;
+                if (i < nv) {
+                    const int64_t pi = perm[s0 + i];
+#pragma unroll
+                    for (int q = 0; q < M; ++q) {
+                        if constexpr (ACC)
+                            u[pi * M + q] += part[q][r];
+                        else
+                            u[pi * M + q] = part[q][r];
+                    }
+                }
+            }
+        }
+    }
+}
+
 // u[i][j] += -phi(0) / (2 pi sigma0) rho[i][j] (harmonic kernel: 1 component,
 // Stokeslet: 3); phi(0) = 1/sqrt(pi) for the Gaussian, or the PSWF series at
 // t = 0, i.e. u = -1: sum_m (-1)^m c_m
@@ -288,8 +386,28 @@ extern "C" int dmk_cheb_eval(const dmk_grid *grid, const dmk_bins *bins, int p, 
     double *lag = (double *)ws;
     hipLaunchKernelGGL(k_cheb_lagrange<true>, dim3(nblk(3 * g.N, CB_T)), dim3(CB_T), 0, stream, g, bins->ys,
                        bins->skey, lag);
+    const int32_t *sk = bins->skey, *pm = bins->perm, *bsp = bins->box_start;
+    const int64_t nbox = (g.G[0] / p) * (g.G[1] / p) * (g.G[2] / p);
+    if (g.N >= 16 * nbox) {
+        // boxes of 16 or more points on average: matrix-core contraction per box
+        const dim3 grd((unsigned)nbox);
+        if (accumulate) {
+            switch (m) {
+            case 1: hipLaunchKernelGGL((k_cheb_eval_mfma<1, true>), grd, dim3(CB_T), 0, stream, g, bsp, pm, lag, u_grid, u); break;
+            case 3: hipLaunchKernelGGL((k_cheb_eval_mfma<3, true>), grd, dim3(CB_T), 0, stream, g, bsp, pm, lag, u_grid, u); break;
+            default: hipLaunchKernelGGL((k_cheb_eval_mfma<9, true>), grd, dim3(CB_T), 0, stream, g, bsp, pm, lag, u_grid, u); break;
+            }
+        } else {
+            switch (m) {
+            case 1: hipLaunchKernelGGL((k_cheb_eval_mfma<1, false>), grd, dim3(CB_T), 0, stream, g, bsp, pm, lag, u_grid, u); break;
+            case 3: hipLaunchKernelGGL((k_cheb_eval_mfma<3, false>), grd, dim3(CB_T), 0, stream, g, bsp, pm, lag, u_grid, u); break;
+            default: hipLaunchKernelGGL((k_cheb_eval_mfma<9, false>), grd, dim3(CB_T), 0, stream, g, bsp, pm, lag, u_grid, u); break;
+            }
+        }
+        DMK_HIP_CHECK(hipGetLastError());
+        return DMK_OK;
+    }
     const dim3 grd(nblk(g.N, CB_T));
-    const int32_t *sk = bins->skey, *pm = bins->perm;
     if (accumulate) {
         switch (m) {
         case 1: hipLaunchKernelGGL((k_cheb_eval<1, true>), grd, dim3(CB_T), 0, stream, g, sk, pm, lag, u_grid, u); break;
