@@ -58,6 +58,23 @@ def test_anterp_and_eval(case, m):
     assert_parity(host(acc) - base, OC.evaluate(Lv, D, n, p, x, ug), 1e-12, "eval accumulate")
 
 
+def test_degenerate_grids():
+    rng = np.random.default_rng(8)
+    # p = 1: one node per box, the box's total strength / a constant per box
+    Lv, n = (1.0, 1.0, 1.0), (2, 3, 1)
+    x = rng.random((50, 3))
+    rho = rng.normal(size=(50, 3))
+    b = R.tree_bin(Lv, 3, n, dev(x))
+    assert_parity(host(F.cheb_anterp(b, 1, dev(rho))), OC.anterp(Lv, 3, n, 1, x, rho), 1e-12, "anterp p=1")
+    ug = rng.normal(size=(3, 2, 3, 1))
+    assert_parity(host(F.cheb_eval(b, 1, dev(ug))), OC.evaluate(Lv, 3, n, 1, x, ug), 1e-12, "eval p=1")
+    # no points: the grids are all zero, evaluation leaves its output alone
+    b0 = R.tree_bin(Lv, 3, n, dev(np.zeros((0, 3))))
+    rg = F.cheb_anterp(b0, 4, dev(np.zeros((0, 1))), out=dev(np.full((1, 8, 12, 4), 7.0)))
+    assert np.all(host(rg) == 0.0)
+    assert host(F.cheb_eval(b0, 4, dev(np.ones((1, 8, 12, 4))))).shape == (0, 1)
+
+
 def test_eval_at_grid_nodes():
     # points on (or within rounding of) grid nodes: the barycentric form near its poles
     p, Lv, n = 7, (1.0, 1.0, 1.0), (2, 1, 1)

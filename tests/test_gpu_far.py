@@ -100,3 +100,19 @@ def test_far_elongated_cell_sampled(kernel, c, p):
     print("far elongated", kernel, K, flush=True)
     got, ref = _sampled(kernel, Lv, M, p, K, c, 1500, 128, 79)
     assert_parity(got, ref, 1e-12, "far elongated %s" % kernel)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_far_edge_cases(kernel):
+    k = oracle.KERNELS[kernel]
+    rng = np.random.default_rng(81)
+    # K = 0: only k = 0, which is excluded -> exactly zero
+    rho = rng.normal(size=(oracle.M_IN[k], 4, 4, 4))
+    got = host(F.far3p_eval((1.0, 1.0, 1.0), (1, 1, 1), 4, (0, 0, 0), kernel, 0.3, dev(rho)))
+    assert np.all(got == 0.0)
+    # one grid point per cube (p = 1), modes along one axis only
+    Lv, M, p, K = (3.0, 1.0, 2.0), (3, 1, 2), 1, (4, 0, 2)
+    rho = rng.normal(size=(oracle.M_IN[k], 3, 1, 2))
+    ref = oracle.far_3p_grid(kernel, Lv, M, p, K, 0.4, rho)
+    got = host(F.far3p_eval(Lv, M, p, K, kernel, 0.4, dev(rho)))
+    assert_parity(got, ref, 1e-12, "far p=1 %s" % kernel)
