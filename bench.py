@@ -72,9 +72,10 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload, prec, khash):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
+def read_traffic(workload, prec, khash, field=None):
+    """HBM bytes per launch (or, with field, another per-launch counter figure)
+    from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
@@ -84,6 +85,8 @@ def read_traffic(workload, prec, khash):
         return None
     if d.get("kernel_hash") != khash:
         return None
+    if field is not None:
+        return d.get(field, {}).get(prec)
     return d.get(prec)
 
 
@@ -322,8 +325,12 @@ def main():
     khash = kernel_hash()
     tr = read_traffic(w.name, head, khash)
     traffic = None if tr is None else tr.get(dom)
+    vi = read_traffic(w.name, head, khash, field="valu_issue")
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[head], "traffic": traffic,
+            # share of the SIMDs' VALU issue slots the launch used (SQ_INSTS_VALU
+            # x 4 cycles over the launch's cycles), from the same counter runs
+            "valu_issue_frac": None if vi is None else vi.get(dom),
             "kernel": "k_residual<%s,%s,%s>" % (w.kernel, head, dom),
             "flops_per_pair": FLOPS_PER_PAIR[(w.kernel, dom)], "launch_ms": dur_ms}
 
