@@ -140,6 +140,112 @@ __global__ __launch_bounds__(CB_T) void k_cheb_anterp(ChebGeom g, int ch, int ns
     }
 }
 
+// The same anterpolation as a dense contraction on the FP64 matrix cores,
+// for boxes holding many points: per box,
+//   rho~_q[j0][(j1, j2)] = sum_s l0(s, j0) * (l1(s, j1) l2(s, j2) rho_q(s)),
+// a (p x N_b) by (N_b x p^2) product.  Each wavefront owns NT 16 x 16 tiles
+// of (j0, (j1, j2)) in one row of tiles (sharing the A fragment) and adds 4
+// points per v_mfma_f64_16x16x4 from the LDS chunk (lane layout as in
+// k_cheb_eval_mfma); the workgroups of a box share its tiles.
+typedef double dbl4a __attribute__((ext_vector_type(4)));
+
+template <int M>
+struct AnterpTiles {
+    static constexpr int NT = M == 1 ? 4 : (M == 3 ? 2 : 1);  // tiles per wavefront
+};
+
+template <int M>
+__global__ __launch_bounds__(CB_T) void k_cheb_anterp_mfma(ChebGeom g, int ch, int nsplit,
+                                                           const int32_t *__restrict__ bs,
+                                                           const int32_t *__restrict__ perm,
+                                                           const double *__restrict__ lag,
+                                                           const double *__restrict__ rho, double *__restrict__ rg)
+{
+    constexpr int NT = AnterpTiles<M>::NT;
+    extern __shared__ double sm[];
+    const int p = g.p;
+    const int64_t box = blockIdx.x / nsplit;
+    const int part = blockIdx.x - (int)(box * nsplit);
+    const int64_t b0 = box / ((int64_t)g.n[1] * g.n[2]), b1 = (box / g.n[2]) % g.n[1], b2 = box % g.n[2];
+    const int64_t tot = g.G[0] * g.G[1] * g.G[2];
+    const int pp = p * p;
+    const int ntn = (pp + 15) / 16;            // column tiles
+    const int ngn = (ntn + NT - 1) / NT;       // groups of NT column tiles
+    const int ngroup = ((p + 15) / 16) * ngn;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int grp = part * (CB_T / WAVE) + threadIdx.x / WAVE;
+    const bool active = grp < ngroup;  // uniform per wavefront
+    const int tj = active ? grp / ngn : 0, tn0 = active ? (grp - (grp / ngn) * ngn) * NT : 0;
+    const int li = lane & 15, lk = lane >> 4;
+    const int j0a = tj * 16 + li;  // A row of this lane
+    int j1[NT], j2[NT];
+    bool nok[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n = (tn0 + t) * 16 + li;  // B / D column of this lane in tile t
+        nok[t] = n < pp;
+        j1[t] = nok[t] ? n / p : 0;
+        j2[t] = nok[t] ? n - (n / p) * p : 0;
+    }
+    double *L0 = sm, *L1 = sm + ch * p, *Cq = sm + 2 * ch * p;
+    const int sb = bs[box], se = bs[box + 1];
+    const int npass = max(1, (se - sb + ch - 1) / ch);
+    for (int ps = 0; ps < npass; ++ps) {
+        const int c0 = sb + ps * ch;
+        const int nc = max(0, min(ch, se - c0));
+        __syncthreads();  // the previous chunk is no longer read
+        for (int e = threadIdx.x; e < nc * p; e += CB_T) {
+            const int si = e / p, j = e - si * p;
+            const int64_t s = c0 + si;
+            const double *l = lag + s * 3 * p;
+            L0[si * p + j] = l[j];
+            L1[si * p + j] = l[p + j];
+            const double l2 = l[2 * p + j];
+            const int64_t i = perm[s];
+#pragma unroll
+            for (int q = 0; q < M; ++q) Cq[(q * ch + si) * p + j] = l2 * rho[i * M + q];
+        }
+        __syncthreads();
+        if (!active) continue;
+        dbl4a d[NT][M];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int q = 0; q < M; ++q) d[t][q] = (dbl4a){0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < nc; k0 += 4) {
+            const int k = k0 + lk;
+            const bool kok = k < nc;
+            const double a = (kok && j0a < p) ? L0[k * p + j0a] : 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const bool ok = kok && nok[t];
+                const double w1 = ok ? L1[k * p + j1[t]] : 0.0;
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    const double b = ok ? w1 * Cq[(q * ch + k) * p + j2[t]] : 0.0;
+                    d[t][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d[t][q], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j0 = tj * 16 + 4 * r + lk;
+                if (j0 < p && nok[t]) {
+                    const int64_t idx = ((b0 * p + j0) * g.G[1] + (b1 * p + j1[t])) * g.G[2] + b2 * p + j2[t];
+#pragma unroll
+                    for (int q = 0; q < M; ++q) {
+                        if (ps == 0)
+                            rg[q * tot + idx] = d[t][q][r];
+                        else
+                            rg[q * tot + idx] += d[t][q][r];
+                    }
+                }
+            }
+    }
+}
+
 // u[perm[s]][q] (+)= sum_j U[q][grid of the box of s](j) l_j(s)
 template <int M, bool ACC>
 __global__ __launch_bounds__(CB_T) void k_cheb_eval(ChebGeom g, const int32_t *__restrict__ skey,
@@ -360,15 +466,34 @@ extern "C" int dmk_cheb_anterp(const dmk_grid *grid, const dmk_bins *bins, int p
                            bins->skey, lag);
     // points per LDS chunk: (2 + m) p doubles each, within 48 KB
     const int ch = max(1, min(256, 49152 / ((2 + m) * p * 8)));
+    const int64_t nbox = (g.G[0] / p) * (g.G[1] / p) * (g.G[2] / p);
+    const size_t lds = sizeof(double) * (size_t)(2 + m) * ch * p;
+    const int32_t *bsp = bins->box_start, *pm = bins->perm;
+    if (g.N >= 16 * nbox) {
+        // boxes of 16 or more points on average: matrix-core contraction,
+        // one group of 16 x 16 output tiles per wavefront
+        const int nt = m == 1 ? AnterpTiles<1>::NT : (m == 3 ? AnterpTiles<3>::NT : AnterpTiles<9>::NT);
+        const int ngroup = ((p + 15) / 16) * (((p * p + 15) / 16 + nt - 1) / nt);
+        const int nsplit = (ngroup + CB_T / WAVE - 1) / (CB_T / WAVE);
+        const int64_t nwg = nbox * nsplit;
+        if (nwg > 0x7fffffff) return DMK_ESIZE;
+        const dim3 grd((unsigned)nwg);
+        switch (m) {
+        case 1: hipLaunchKernelGGL(k_cheb_anterp_mfma<1>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
+        case 3: hipLaunchKernelGGL(k_cheb_anterp_mfma<3>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
+        default: hipLaunchKernelGGL(k_cheb_anterp_mfma<9>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
+        }
+        DMK_HIP_CHECK(hipGetLastError());
+        return DMK_OK;
+    }
     const int nsplit = (p * p * p + CB_NODES - 1) / CB_NODES;
-    const int64_t nwg = (g.G[0] / p) * (g.G[1] / p) * (g.G[2] / p) * nsplit;
+    const int64_t nwg = nbox * nsplit;
     if (nwg > 0x7fffffff) return DMK_ESIZE;
     const dim3 grd((unsigned)nwg);
-    const size_t lds = sizeof(double) * (size_t)(2 + m) * ch * p;
     switch (m) {
-    case 1: hipLaunchKernelGGL(k_cheb_anterp<1>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bins->box_start, bins->perm, lag, rho, rho_grid); break;
-    case 3: hipLaunchKernelGGL(k_cheb_anterp<3>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bins->box_start, bins->perm, lag, rho, rho_grid); break;
-    default: hipLaunchKernelGGL(k_cheb_anterp<9>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bins->box_start, bins->perm, lag, rho, rho_grid); break;
+    case 1: hipLaunchKernelGGL(k_cheb_anterp<1>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
+    case 3: hipLaunchKernelGGL(k_cheb_anterp<3>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
+    default: hipLaunchKernelGGL(k_cheb_anterp<9>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
     }
     DMK_HIP_CHECK(hipGetLastError());
     return DMK_OK;
