@@ -304,6 +304,14 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval(ChebGeom g, const int32_t *_
 // each D element is then weighted by l0(s_i, j0) l1(s_i, j1) and the 16
 // lanes that hold a point's row are summed with shuffles.  One workgroup per
 // box; its wavefronts take the box's 16-point blocks in turn.
+// LDS stores of a wavefront made visible to all its lanes, in order (no
+// other wavefront touches the same region)
+__device__ inline void wave_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int KMAX = DMK_FAR_PMAX / 4;
 
@@ -313,6 +321,7 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32
                                                          const double *__restrict__ lag,
                                                          const double *__restrict__ U, double *__restrict__ u)
 {
+    extern __shared__ double sm[];
     const int p = g.p;
     const int64_t N = g.N;
     const int64_t box = blockIdx.x;
@@ -325,9 +334,18 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32
     const int nblock = (se - sb + 15) / 16;
     const int pp = p * p;
     const int nkk = (p + 3) / 4;
+    // this wavefront's copy of the block's l0 and l1: W0[j][i], W1[j][i]
+    double *W0 = sm + (size_t)wv * 32 * p, *W1 = W0 + 16 * p;
     for (int blk = wv; blk < nblock; blk += CB_T / WAVE) {
         const int s0 = sb + blk * 16;
         const int nv = min(16, se - s0);
+        wave_barrier();  // the previous block's weights are no longer read
+        for (int e = lane; e < 16 * p; e += WAVE) {
+            const int j = e >> 4, i = e & 15;
+            W0[e] = i < nv ? lag[(int64_t)j * N + s0 + i] : 0.0;
+            W1[e] = i < nv ? lag[(int64_t)(p + j) * N + s0 + i] : 0.0;
+        }
+        wave_barrier();
         // A fragments: l2 of point li at j2 = 4 kk + lk
         double afr[KMAX];
 #pragma unroll
@@ -363,8 +381,7 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = 4 * r + lk;
-                const double w = (nok && i < nv) ? lag[(int64_t)j0 * N + s0 + i] * lag[(int64_t)(p + j1) * N + s0 + i]
-                                                 : 0.0;
+                const double w = nok ? W0[j0 * 16 + i] * W1[j1 * 16 + i] : 0.0;
 #pragma unroll
                 for (int q = 0; q < M; ++q) part[q][r] = fma(w, d[q][r], part[q][r]);
             }
@@ -516,17 +533,18 @@ extern "C" int dmk_cheb_eval(const dmk_grid *grid, const dmk_bins *bins, int p, 
     if (g.N >= 16 * nbox) {
         // boxes of 16 or more points on average: matrix-core contraction per box
         const dim3 grd((unsigned)nbox);
+        const size_t elds = sizeof(double) * (size_t)(CB_T / WAVE) * 32 * p;
         if (accumulate) {
             switch (m) {
-            case 1: hipLaunchKernelGGL((k_cheb_eval_mfma<1, true>), grd, dim3(CB_T), 0, stream, g, bsp, pm, lag, u_grid, u); break;
-            case 3: hipLaunchKernelGGL((k_cheb_eval_mfma<3, true>), grd, dim3(CB_T), 0, stream, g, bsp, pm, lag, u_grid, u); break;
-            default: hipLaunchKernelGGL((k_cheb_eval_mfma<9, true>), grd, dim3(CB_T), 0, stream, g, bsp, pm, lag, u_grid, u); break;
+            case 1: hipLaunchKernelGGL((k_cheb_eval_mfma<1, true>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
+            case 3: hipLaunchKernelGGL((k_cheb_eval_mfma<3, true>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
+            default: hipLaunchKernelGGL((k_cheb_eval_mfma<9, true>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
             }
         } else {
             switch (m) {
-            case 1: hipLaunchKernelGGL((k_cheb_eval_mfma<1, false>), grd, dim3(CB_T), 0, stream, g, bsp, pm, lag, u_grid, u); break;
-            case 3: hipLaunchKernelGGL((k_cheb_eval_mfma<3, false>), grd, dim3(CB_T), 0, stream, g, bsp, pm, lag, u_grid, u); break;
-            default: hipLaunchKernelGGL((k_cheb_eval_mfma<9, false>), grd, dim3(CB_T), 0, stream, g, bsp, pm, lag, u_grid, u); break;
+            case 1: hipLaunchKernelGGL((k_cheb_eval_mfma<1, false>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
+            case 3: hipLaunchKernelGGL((k_cheb_eval_mfma<3, false>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
+            default: hipLaunchKernelGGL((k_cheb_eval_mfma<9, false>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
             }
         }
         DMK_HIP_CHECK(hipGetLastError());
