@@ -110,6 +110,92 @@ __global__ void k_mode(const void *__restrict__ Xv, const double2 *__restrict__ 
         ((double2 *)Yv)[yi] = make_double2(s * re, s * im);
 }
 
+// The same mode product on the FP64 matrix cores, for contractions large
+// enough to fill 16 x 16 tiles (the long axis of an elongated cell): one
+// workgroup per (a, 16 outputs o, 16 outputs c); its MM_W wavefronts take
+// every MM_W-th group of 4 terms i, one v_mfma_f64_16x16x4 per group (A: lane l
+// holds A[l % 16][l / 16], B: B[l / 16][l % 16], D: D[4 r + l / 16][l % 16]),
+// and the partial tiles are summed through LDS in a fixed order.  (8
+// wavefronts per tile measured best for the long axis of a 32-cube cell: 4 and
+// 16 were slower.)  Real and
+// imaginary parts accumulate in two tiles:
+//   Re += Re(coef) Re(x) - Im(coef) Im(x),  Im += Re(coef) Im(x) + Im(coef) Re(x).
+typedef double dbl4m __attribute__((ext_vector_type(4)));
+constexpr int MM_W = 8;  // wavefronts per tile
+
+template <bool RIN, bool ROUT, bool CONJ>
+__global__ __launch_bounds__(MM_W * WAVE) void k_mode_mfma(const void *__restrict__ Xv,
+                                                           const double2 *__restrict__ E, int64_t A, int I, int O,
+                                                           int C, int64_t si, int64_t so, double s,
+                                                           void *__restrict__ Yv)
+{
+    __shared__ double red[MM_W - 1][8][WAVE];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x / WAVE;
+    const int to = (O + 15) / 16, tc = (C + 15) / 16;
+    const int64_t tile = blockIdx.x;
+    const int64_t a = tile / ((int64_t)to * tc);
+    const int rem = (int)(tile - a * to * tc);
+    const int ot = rem / tc, ct = rem - (rem / tc) * tc;
+    const int li = lane & 15, lk = lane >> 4;
+    const int oa = ot * 16 + li, cb = ct * 16 + li;
+    const bool ook = oa < O, cok = cb < C;
+    dbl4m dre = {0.0, 0.0, 0.0, 0.0}, dim = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 4 * wv; k0 < I; k0 += 4 * MM_W) {
+        const int k = k0 + lk;
+        const bool kok = k < I;
+        double er = 0.0, ei = 0.0, xr = 0.0, xi = 0.0;
+        if (kok && ook) {
+            const double2 e = E[(int64_t)k * si + (int64_t)oa * so];
+            er = e.x;
+            ei = CONJ ? -e.y : e.y;
+        }
+        if (kok && cok) {
+            const int64_t xo = (a * I + k) * C + cb;
+            if constexpr (RIN) {
+                xr = ((const double *)Xv)[xo];
+            } else {
+                const double2 x = ((const double2 *)Xv)[xo];
+                xr = x.x;
+                xi = x.y;
+            }
+        }
+        dre = __builtin_amdgcn_mfma_f64_16x16x4f64(er, xr, dre, 0, 0, 0);
+        if constexpr (!RIN) dre = __builtin_amdgcn_mfma_f64_16x16x4f64(-ei, xi, dre, 0, 0, 0);
+        if constexpr (!ROUT) {
+            dim = __builtin_amdgcn_mfma_f64_16x16x4f64(ei, xr, dim, 0, 0, 0);
+            if constexpr (!RIN) dim = __builtin_amdgcn_mfma_f64_16x16x4f64(er, xi, dim, 0, 0, 0);
+        }
+    }
+    if (wv > 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            red[wv - 1][r][lane] = dre[r];
+            red[wv - 1][4 + r][lane] = dim[r];
+        }
+    }
+    __syncthreads();
+    if (wv > 0 || !cok) return;
+#pragma unroll
+    for (int w = 0; w < MM_W - 1; ++w)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            dre[r] += red[w][r][lane];
+            dim[r] += red[w][4 + r][lane];
+        }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int o = ot * 16 + 4 * r + lk;
+        if (o < O) {
+            const int64_t yi = (a * O + o) * C + cb;
+            if constexpr (ROUT)
+                ((double *)Yv)[yi] = s * dre[r];
+            else
+                ((double2 *)Yv)[yi] = make_double2(s * dre[r], s * dim[r]);
+        }
+    }
+}
+
 // phi(t) of the PSWF window from its Chebyshev series in u = 2 t^2 - 1 (Clenshaw)
 __device__ inline double win_phi(const FarWin &w, double t)
 {
@@ -326,6 +412,13 @@ void mode(const void *X, const double2 *E, int64_t A, int I, int O, int C, int64
 {
     const int64_t n = A * O * C;
     if (n <= 0) return;
+    if (O >= 16 && C >= 16 && I >= 16 && A * ((O + 15) / 16) * ((C + 15) / 16) <= 0x7fffffff) {
+        // 16 x 16 output tiles, one workgroup each, on the matrix cores
+        const int64_t tiles = A * ((O + 15) / 16) * ((C + 15) / 16);
+        hipLaunchKernelGGL((k_mode_mfma<RIN, ROUT, CONJ>), dim3((unsigned)tiles), dim3(MM_W * WAVE), 0, st, X, E, A,
+                           I, O, C, si, so, s, Y);
+        return;
+    }
     hipLaunchKernelGGL((k_mode<RIN, ROUT, CONJ>), dim3(nblk(n, 256)), dim3(256), 0, st, X, E, A, I, O, C, si, so, s,
                        Y);
 }

@@ -31,6 +31,7 @@ GEOMS = [
     ((1.0, 1.0, 1.0), (1, 1, 1), 6, (2, 2, 2), 0.3),
     ((2.0, 1.0, 3.0), (2, 1, 3), 5, (3, 1, 4), 0.4),
     ((1.0, 1.0, 1.0), (1, 1, 1), 12, (1, 1, 1), 0.5),
+    ((8.0, 1.0, 1.0), (8, 1, 1), 6, (20, 2, 2), 0.35),  # long-axis contractions on the matrix cores
 ]
 
 
