@@ -163,3 +163,20 @@ def test_single_level_split_hasimoto_on_gpu():
     f = np.array([[0.3, -0.5, 0.8]])
     u = host(F.single_level_3p(dev(x), dev(f), "stokeslet", (1.0, 1.0, 1.0), 32.46, 44))[0]
     np.testing.assert_allclose(u, -zeta * f[0] / (6 * np.pi), rtol=3e-7, atol=0)
+
+
+@pytest.mark.parametrize("n,N", [((1, 1, 1), 40), ((2, 2, 2), 40)])
+def test_largest_order(n, N):
+    # p = 64 (the largest order the library takes), 9 components: LDS chunks
+    # of a few points, 16 A fragments per matrix-core block; 40 points in one
+    # box (matrix-core forms) or over 8 boxes (thread forms)
+    p, m = 64, 9
+    rng = np.random.default_rng(11)
+    Lv = (1.0, 1.0, 1.0)
+    x = rng.random((N, 3))
+    rho = rng.normal(size=(N, m))
+    b = R.tree_bin(Lv, 3, n, dev(x))
+    print("largest order", n, N, flush=True)
+    assert_parity(host(F.cheb_anterp(b, p, dev(rho))), OC.anterp(Lv, 3, n, p, x, rho), 1e-12, "anterp p=64")
+    ug = rng.normal(size=(m, n[0] * p, n[1] * p, n[2] * p))
+    assert_parity(host(F.cheb_eval(b, p, dev(ug))), OC.evaluate(Lv, 3, n, p, x, ug), 1e-12, "eval p=64")

@@ -117,3 +117,13 @@ def test_far_edge_cases(kernel):
     ref = oracle.far_3p_grid(kernel, Lv, M, p, K, 0.4, rho)
     got = host(F.far3p_eval(Lv, M, p, K, kernel, 0.4, dev(rho)))
     assert_parity(got, ref, 1e-12, "far p=1 %s" % kernel)
+
+
+def test_far_largest_order():
+    # p = 64 on one cube, stresslet (9 strength components)
+    Lv, M, p, K = (1.0, 1.0, 1.0), (1, 1, 1), 64, (1, 2, 1)
+    rng = np.random.default_rng(82)
+    rho = rng.normal(size=(9, p, p, p))
+    ref = oracle.far_3p_grid("stresslet", Lv, M, p, K, 0.4, rho)
+    got = host(F.far3p_eval(Lv, M, p, K, "stresslet", 0.4, dev(rho)))
+    assert_parity(got, ref, 1e-12, "far p=64")
