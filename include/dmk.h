@@ -239,7 +239,8 @@ const char *dmk_version(void);
  * DMK_EINVAL (null pointer, p outside [1, DMK_FAR_PMAX], M_i outside
  * [1, DMK_FAR_MMAX], K_i outside [0, DMK_FAR_KMAX], cubes that do not tile the
  * cell), DMK_ECUTOFF (sigma0 <= 0), DMK_EUNSUPPORTED (bad window, or
- * |k|max sigma0 > 4096 with the PSWF window), DMK_ESIZE (workspace too small).
+ * |k|max sigma0 > 4096 with the PSWF window), DMK_ESIZE (workspace too small,
+ * or more than 8.5e9 wave numbers in all).
  */
 #define DMK_FAR_PMAX 64
 #define DMK_FAR_MMAX 4096

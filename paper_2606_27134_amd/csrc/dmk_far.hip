@@ -463,6 +463,8 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
         }
         if (sqrt(kk) * sigma0 > 4096.0) return DMK_EUNSUPPORTED;
     }
+    // launch-size limits: 4 modes per workgroup of the weights kernel
+    if ((int64_t)g.W[0] * g.W[1] * g.W[2] / 4 >= 0x7fffffff) return DMK_ESIZE;
     const FarLayout l = far_layout(g, kernel);
     if (ws_bytes < (size_t)l.total) return DMK_ESIZE;
     char *b = (char *)ws;

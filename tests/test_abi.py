@@ -147,6 +147,9 @@ def test_far3p_host_argument_checks():
     assert L.dmk_far3p_eval(fg, 1, 1.0, None, 0, fake, fake, nb, 0) == L.DMK_EINVAL
     bad = L.dmk_pswf()  # c = 0: not a window
     assert L.dmk_far3p_eval(fg, 1, 1.0, bad, fake, fake, fake, nb, 0) == L.DMK_EUNSUPPORTED
+    # the largest mode ranges on every axis: more wave numbers than one launch covers
+    huge = L.make_far_grid((1, 1, 1), (1, 1, 1), 2, (L.FAR_KMAX,) * 3)
+    assert L.dmk_far3p_eval(huge, 0, 1.0, None, fake, fake, fake, 1 << 62, 0) == L.DMK_ESIZE
     for args in [((1, 1, 1), (1, 1, 2), 8, (2, 2, 2)),      # cubes do not tile the cell
                  ((1, 1, 1), (1, 1, 1), 0, (2, 2, 2)),      # p < 1
                  ((1, 1, 1), (1, 1, 1), L.FAR_PMAX + 1, (2, 2, 2)),
