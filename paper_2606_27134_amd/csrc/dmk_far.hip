@@ -29,8 +29,9 @@
 //   stresslet  i [(k_m d_jl + k_j d_lm + k_l d_mj) k^2 - 2 k_j k_l k_m] Bhat
 //   rotlet     -(i/2) eps_jlm k_m Hhat
 // with phihat(q) = exp(-q^2/4) for the Gaussian window and, for the PSWF
-// window of support sigma, phihat(q) = 2 int_0^1 phi(t) cos(q t) dt by
-// composite Gauss-Legendre quadrature of the window's Chebyshev series.
+// window of support sigma, phihat(q) = phi(q/c) / phi(0) inside the band
+// |q| <= c and 2 int_0^1 phi(t) cos(q t) dt by composite Gauss-Legendre
+// quadrature of the window's Chebyshev series beyond it.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -52,7 +53,9 @@ struct FarWin {
     int pswf;      // 0 Gaussian, 1 PSWF series
     int nterms;
     double sigma;
+    double c;                        // bandwidth
     double cheb[DMK_PSWF_MAXTERMS];  // phi(t) = sum_m cheb[m] T_m(2 t^2 - 1), t in [0, 1]
+    double dcheb[DMK_PSWF_MAXTERMS]; // phi'(t) / t in the same form
     double gx[GL_N], gw[GL_N];       // Gauss-Legendre nodes / weights on [0, 1]
 };
 
@@ -196,18 +199,20 @@ __global__ __launch_bounds__(MM_W * WAVE) void k_mode_mfma(const void *__restric
     }
 }
 
-// phi(t) of the PSWF window from its Chebyshev series in u = 2 t^2 - 1 (Clenshaw)
-__device__ inline double win_phi(const FarWin &w, double t)
+// a Chebyshev series of the PSWF window in u = 2 t^2 - 1 (Clenshaw)
+__device__ inline double win_series(const FarWin &w, const double *cf, double t)
 {
     const double u = 2.0 * t * t - 1.0;
     double b1 = 0.0, b2 = 0.0;
     for (int m = w.nterms - 1; m >= 1; --m) {
-        const double b0 = fma(2.0 * u, b1, w.cheb[m] - b2);
+        const double b0 = fma(2.0 * u, b1, cf[m] - b2);
         b2 = b1;
         b1 = b0;
     }
-    return fma(u, b1, w.cheb[0] - b2);
+    return fma(u, b1, cf[0] - b2);
 }
+
+__device__ inline double win_phi(const FarWin &w, double t) { return win_series(w, w.cheb, t); }
 
 // phihat(q) and phihat'(q); the quadrature nodes are split over the 64
 // lanes of the wavefront and the partial sums combined with shuffles (in a
@@ -219,7 +224,15 @@ __device__ inline void win_hat(const FarWin &w, double q, int lane, double &ph, 
         dph = -0.5 * q * ph;
         return;
     }
-    // 2 int_0^1 phi(t) cos(q t) dt and -2 int_0^1 t phi(t) sin(q t) dt on
+    if (q <= w.c) {
+        // in the band the window's transform is the window itself (the
+        // eigen-relation of psi_0^c, Sec. 2.2): phihat(q) = phi(q/c) / phi(0)
+        const double t = q / w.c, phi0 = win_phi(w, 0.0);
+        ph = win_phi(w, t) / phi0;
+        dph = t * win_series(w, w.dcheb, t) / (w.c * phi0);
+        return;
+    }
+    // beyond it: 2 int_0^1 phi(t) cos(q t) dt and -2 int_0^1 t phi(t) sin(q t) dt on
     // panels over which q t varies by at most 4; at least two panels, as phi is
     // a polynomial of degree up to ~60 in t
     const int np = 2 + (int)(q * 0.25);
@@ -453,7 +466,11 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
             return DMK_EUNSUPPORTED;
         w.pswf = 1;
         w.nterms = win->nterms64;
-        for (int m = 0; m < DMK_PSWF_MAXTERMS; ++m) w.cheb[m] = win->cheb[0][m];
+        w.c = win->c;
+        for (int m = 0; m < DMK_PSWF_MAXTERMS; ++m) {
+            w.cheb[m] = win->cheb[0][m];
+            w.dcheb[m] = win->cheb[2][m];
+        }
         gauss_legendre01(w.gx, w.gw);
         // the quadrature grows with |k| sigma: bound it
         double kk = 0.0;
