@@ -347,6 +347,14 @@ def main():
         "kernel_fwd_ms": r["kernel_fwd_ms"], "kernel_bwd_ms": r["kernel_bwd_ms"],
         "roofline": roof, "kernel_hash": khash,
     }
+    # the paper's own timings, as context: it reports full-DMK runtimes of a
+    # MATLAB code only in figures (normalized), none for the residual path
+    line["paper_context"] = {
+        "residual_path_timing": None,
+        "platform": "MATLAB (not optimized for runtime), AMD EPYC 9655P 96-core CPU, FP64, full DMK",
+        "published": "normalized runtimes (t(L)/N)/(t(unit cube)/N) within [0.9, 1.1] for cells [1,L2,L3], "
+                     "L2,L3 in 1..5, 1e4 points per unit volume, tolerance 1e-6 (Sec. 6); achieved rel l2 "
+                     "of the full method 1.0e-7 (Laplace) / 1.7e-7 (Stokeslet) at tolerance 1e-6"}
     if "fp64" in res and head != "fp64":
         f = res["fp64"]
         line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "fwd_ms": f["fwd_ms"],
