@@ -373,8 +373,8 @@ __device__ inline int cost_key(int64_t cost)
 
 // One wavefront per leaf column (b0, b1).  The lanes first stage, for the
 // column's z range, the target count of each box and the slab count (sources
-// in the 9 stencil columns at that z) in LDS; lane 0 then walks the column in
-// z, growing a tile while its targets, its staged sources and its z extent
+// in the 9 stencil columns at that z) in LDS; the column is then walked in z,
+// each tile growing while its targets, its staged sources and its z extent
 // fit.  Columns taller than TW_ZST boxes read the rest from the box starts.
 constexpr int TW_ZST = 2048;
 
@@ -418,51 +418,68 @@ __global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int32_t *__restrict_
         ssl[z] = sc;
     }
     __syncthreads();
-    if (lane != 0) return;
+    // The walk, with the whole wavefront on every step (z stays uniform).  A
+    // tile starting at z may end at z + l for the l whose extent, targets and
+    // staged sources all fit; each of these only grows with l, so the lanes
+    // that fit form a prefix and one ballot gives the end.
     const ColView cv{&g, ccol, snt, ssl, col};
     int cnt = 0;
-    int out = WRITE ? counts[col] : 0;
+    const int out = WRITE ? counts[col] : 0;
     int z = 0;
     while (z < n2) {
-        const int nt = cv.nt(z);
-        if (nt == 0) {
-            ++z;
-            continue;
+        {  // next box with targets
+            const int zz = z + lane;
+            const uint64_t m = __ballot(zz < n2 && cv.nt(zz) > 0);
+            if (m == 0) {
+                z += WAVE;
+                continue;
+            }
+            z += __ffsll((unsigned long long)m) - 1;
         }
+        const int nt = cv.nt(z);
         const int q1 = cv.sl(z - 1) + cv.sl(z) + cv.sl(z + 1);
         const int first = g.bs[(int64_t)col * n2 + z];
         if (nt > TILE_T || q1 > TILE_CAP) {
-            for (int c = 0; c < nt; c += TILE_T) {
-                if (WRITE) {
-                    const int m = nt - c < TILE_T ? nt - c : TILE_T;
-                    tiles[out + cnt] = make_int4(col, z, -(z + 1), first + c);
-                    tkey[out + cnt] = cost_key((int64_t)m * q1);
+            const int nd = (nt + TILE_T - 1) / TILE_T;
+            if (WRITE)
+                for (int c = lane; c < nd; c += WAVE) {
+                    const int m = nt - c * TILE_T < TILE_T ? nt - c * TILE_T : TILE_T;
+                    tiles[out + cnt + c] = make_int4(col, z, -(z + 1), first + c * TILE_T);
+                    tkey[out + cnt + c] = cost_key((int64_t)m * q1);
                 }
-                ++cnt;
-            }
+            cnt += nd;
             ++z;
             continue;
         }
-        int z1 = z, tacc = nt, q = q1;
-        int64_t cost = (int64_t)nt * q1;
-        while (z1 + 1 < n2 && (z1 + 1 - z + 1) <= TILE_ZMAX) {
-            const int nn = cv.nt(z1 + 1);
-            const int s2 = cv.sl(z1 + 2);
-            const int qn = q + s2;
-            if (tacc + nn > TILE_T || qn > TILE_CAP) break;
-            if (WRITE && nn > 0) cost += (int64_t)nn * (cv.sl(z1) + cv.sl(z1 + 1) + s2);
-            ++z1;
-            tacc += nn;
-            q = qn;
+        // candidate end ze = z + lane: targets of boxes z..ze, sources of
+        // slabs z-1..ze+1, by inclusive scans over the lanes
+        const int ze = z + lane;
+        const bool inr = ze < n2 && lane < TILE_ZMAX;
+        const int ntl = inr ? cv.nt(ze) : 0;
+        int T = ntl, Q = inr ? cv.sl(ze + 1) : 0;
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const int t = __shfl_up(T, off), q = __shfl_up(Q, off);
+            if (lane >= off) {
+                T += t;
+                Q += q;
+            }
         }
+        Q += cv.sl(z - 1) + cv.sl(z);
+        const int len = __popcll(__ballot(inr && T <= TILE_T && Q <= TILE_CAP));
+        const int z1 = z + len - 1;
         if (WRITE) {
-            tiles[out + cnt] = make_int4(col, z, z1, first);
-            tkey[out + cnt] = cost_key(cost);
+            // cost: sum over the tile's boxes of targets x the three slabs
+            long long c = lane < len ? (long long)ntl * (cv.sl(ze - 1) + cv.sl(ze) + cv.sl(ze + 1)) : 0;
+            for (int off = WAVE / 2; off > 0; off >>= 1) c += __shfl_xor(c, off);
+            if (lane == 0) {
+                tiles[out + cnt] = make_int4(col, z, z1, first);
+                tkey[out + cnt] = cost_key((int64_t)c);
+            }
         }
         ++cnt;
         z = z1 + 1;
     }
-    if (!WRITE) counts[col] = cnt;
+    if (!WRITE && lane == 0) counts[col] = cnt;
 }
 
 __global__ void k_gather_tiles(const int4 *__restrict__ tin, const int32_t *__restrict__ order, int64_t n,
