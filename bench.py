@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the leaf-level residual interaction on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload laplace_n1m]
 
 One step = dmk_residual_eval (forward) + dmk_residual_backward (adjoint) of
 the whole workload, with the points already binned and all inputs resident
@@ -179,7 +179,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--workload", default="laplace_n1m")
     ap.add_argument("--kernel", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precs", default="fp32c,fp64")

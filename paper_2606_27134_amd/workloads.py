@@ -94,18 +94,21 @@ def _strengths(rng, kernel, N, neutral_charges=False, zero_mean=True):
 
 def make(name: str, seed: int | None = None, N: int | None = None, kernel: str | None = None) -> Workload:
     """Build one named workload.  ``N`` overrides the point count (same
-    distribution and tiling), ``kernel`` picks the kernel for the mixed C4."""
+    distribution and tiling), ``kernel`` picks the kernel of stokes_n2m_rod
+    (stresslet by default, or rotlet)."""
     cfgs = {
         # Laplace D=3, unit cube, 2000 uniform points, +-1 charges, 8^3 leaves.
-        "C1": dict(kernel="laplace", D=3, L=(1.0, 1.0, 1.0), n=(8, 8, 8), N=2000, dist="uniform",
-                   sigma=0.05, rc=1.0 / 8, neutral=True),
+        "laplace_n2k": dict(kernel="laplace", D=3, L=(1.0, 1.0, 1.0), n=(8, 8, 8), N=2000, dist="uniform",
+                            sigma=0.05, rc=1.0 / 8, neutral=True, seed=1000),
         # Laplace D=3, unit cube, 1e6 uniform points, 64^3 leaves.
-        "C2": dict(kernel="laplace", D=3, L=(1.0, 1.0, 1.0), n=(64, 64, 64), N=1_000_000, dist="uniform"),
+        "laplace_n1m": dict(kernel="laplace", D=3, L=(1.0, 1.0, 1.0), n=(64, 64, 64), N=1_000_000, dist="uniform",
+                            seed=1001),
         # Stokeslet D=2, (1,1,4) cuboid, 5e5 points, 70% clustered, 32x32x128 leaves.
-        "C3": dict(kernel="stokeslet", D=2, L=(1.0, 1.0, 4.0), n=(32, 32, 128), N=500_000, dist="clustered"),
+        "stokeslet_n500k_clustered": dict(kernel="stokeslet", D=2, L=(1.0, 1.0, 4.0), n=(32, 32, 128), N=500_000,
+                                          dist="clustered", seed=1002),
         # Stresslet / rotlet D=1, (32,1,1) cuboid, 2e6 uniform points, 1024x32x32 leaves.
-        "C4": dict(kernel="stresslet", D=1, L=(32.0, 1.0, 1.0), n=(1024, 32, 32), N=2_000_000,
-                   dist="uniform"),
+        "stokes_n2m_rod": dict(kernel="stresslet", D=1, L=(32.0, 1.0, 1.0), n=(1024, 32, 32), N=2_000_000,
+                               dist="uniform", seed=1003),
     }
     if name not in cfgs:
         raise KeyError(name)
@@ -114,8 +117,7 @@ def make(name: str, seed: int | None = None, N: int | None = None, kernel: str |
         c["kernel"] = kernel
     if N is not None:
         c["N"] = int(N)
-    idx = ["C1", "C2", "C3", "C4"].index(name)
-    seed = 1000 + idx if seed is None else seed
+    seed = c.pop("seed") if seed is None else seed
     rng = np.random.default_rng(seed)
     L = c["L"]
     if c["dist"] == "uniform":

@@ -67,7 +67,7 @@ def _local_energy_fd(w, prec, samples, h=1e-6):
     return fd
 
 
-@pytest.mark.parametrize("name,kernel", [("C2", "laplace"), ("C3", "stokeslet")])
+@pytest.mark.parametrize("name,kernel", [("laplace_n1m", "laplace"), ("stokeslet_n500k_clustered", "stokeslet")])
 def test_fd_energy_full_size(name, kernel):
     w = W.make(name, kernel=kernel)
     rng = np.random.default_rng(5)

@@ -81,14 +81,14 @@ def test_backward_small(i, prec):
 
 @pytest.mark.parametrize("prec", ["fp64"])
 def test_c1_full(prec):
-    w = W.make("C1")
+    w = W.make("laplace_n2k")
     got, _ = run_fwd(w, prec)
-    assert_parity(got, oracle_fwd(w), TOL[prec], "C1 fwd")
+    assert_parity(got, oracle_fwd(w), TOL[prec], "laplace_n2k fwd")
     G = w.rho.copy()
     gr, gx = run_bwd(w, prec, G)
     rr, rx = oracle.residual_vjp(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, G)
-    assert_parity(gr, rr, TOL[prec], "C1 grad_rho")
-    assert_parity(gx, rx, TOL[prec], "C1 grad_x")
+    assert_parity(gr, rr, TOL[prec], "laplace_n2k grad_rho")
+    assert_parity(gx, rx, TOL[prec], "laplace_n2k grad_x")
 
 
 # --------------------------------------------------------------------------
@@ -161,7 +161,7 @@ def _sample(w, k=64, seed=0):
     return np.sort(t)
 
 
-FULL = [("C2", "laplace"), ("C3", "stokeslet"), ("C4", "stresslet"), ("C4", "rotlet")]
+FULL = [("laplace_n1m", "laplace"), ("stokeslet_n500k_clustered", "stokeslet"), ("stokes_n2m_rod", "stresslet"), ("stokes_n2m_rod", "rotlet")]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
@@ -171,7 +171,7 @@ def test_full_size_sampled(name, kernel, prec):
     print("full", name, kernel, prec, w.N, flush=True)
     got, b = run_fwd(w, prec)
     t = _sample(w)
-    if name == "C3":  # include targets of the densest boxes
+    if name == "stokeslet_n500k_clustered":  # include targets of the densest boxes
         sk = host(b.skey())
         perm = host(b.perm())
         dense_box = np.bincount(sk).argmax()
@@ -181,7 +181,7 @@ def test_full_size_sampled(name, kernel, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
-@pytest.mark.parametrize("name,kernel", [("C2", "laplace"), ("C3", "stokeslet")])
+@pytest.mark.parametrize("name,kernel", [("laplace_n1m", "laplace"), ("stokeslet_n500k_clustered", "stokeslet")])
 def test_full_size_backward_sampled(name, kernel, prec):
     w = W.make(name, kernel=kernel)
     print("full bwd", name, kernel, prec, flush=True)

@@ -94,10 +94,10 @@ def test_pswf_dense_boxes(kernel, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 def test_pswf_full_size_sampled_c2_geometry(prec):
     # the 1e6-point Laplace workload's geometry with the PSWF split (support = leaf box)
-    w = W.make("C2")
+    w = W.make("laplace_n1m")
     c = 14.5
     b = R.tree_bin(w.L, w.D, w.n, dev(w.x))
     got = host(R.residual_eval(b, w.kernel, prec, 0.0, w.rc, dev(w.rho), pswf_c=c))
     t = np.sort(np.random.default_rng(9).choice(w.N, size=400, replace=False))
     ref = oracle.residual(w.kernel, w.D, w.L, w.rc, w.rc, w.x, w.rho, targets=t, window=_ow(c))
-    assert_parity(got[t], ref, TOL[prec], "pswf C2 %s" % prec)
+    assert_parity(got[t], ref, TOL[prec], "pswf laplace_n1m %s" % prec)
