@@ -37,6 +37,17 @@ struct ChebGeom {
 
 constexpr int CB_T = 256;
 
+// accumulator tile of v_mfma_f64_16x16x4 (4 doubles per lane)
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// LDS stores of a wavefront made visible to all its lanes, in order (no
+// other wavefront touches the same region)
+__device__ inline void wave_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // l_j(t_ax(s)) for the sorted points s, stored node-fastest lag[s][ax][j]
 // (anterpolation: the lanes of a wavefront are consecutive nodes of one point)
 // or point-fastest lag[ax][j][s] (PT; evaluation: the lanes are consecutive
@@ -147,7 +158,6 @@ __global__ __launch_bounds__(CB_T) void k_cheb_anterp(ChebGeom g, int ch, int ns
 // of (j0, (j1, j2)) in one row of tiles (sharing the A fragment) and adds 4
 // points per v_mfma_f64_16x16x4 from the LDS chunk (lane layout as in
 // k_cheb_eval_mfma); the workgroups of a box share its tiles.
-typedef double dbl4a __attribute__((ext_vector_type(4)));
 
 template <int M>
 struct AnterpTiles {
@@ -207,11 +217,11 @@ __global__ __launch_bounds__(CB_T) void k_cheb_anterp_mfma(ChebGeom g, int ch, i
         }
         __syncthreads();
         if (!active) continue;
-        dbl4a d[NT][M];
+        dbl4 d[NT][M];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int q = 0; q < M; ++q) d[t][q] = (dbl4a){0.0, 0.0, 0.0, 0.0};
+            for (int q = 0; q < M; ++q) d[t][q] = (dbl4){0.0, 0.0, 0.0, 0.0};
         for (int k0 = 0; k0 < nc; k0 += 4) {
             const int k = k0 + lk;
             const bool kok = k < nc;
@@ -301,18 +311,10 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval(ChebGeom g, const int32_t *_
 //   V[i][n] = sum_{j2} l2(s_i, j2) U[n][j2],   n = (j0, j1),
 // is a (16 x p) by (p x p^2) product, done with v_mfma_f64_16x16x4 (A: lane l
 // holds A[l % 16][l / 16], B: B[l / 16][l % 16], D: D[4 r + l / 16][l % 16]);
-// each D element is then weighted by l0(s_i, j0) l1(s_i, j1) and the 16
-// lanes that hold a point's row are summed with shuffles.  One workgroup per
-// box; its wavefronts take the box's 16-point blocks in turn.
-// LDS stores of a wavefront made visible to all its lanes, in order (no
-// other wavefront touches the same region)
-__device__ inline void wave_barrier()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-typedef double dbl4 __attribute__((ext_vector_type(4)));
+// each D element is then weighted by l0(s_i, j0) l1(s_i, j1) (the block's
+// l0 and l1 rows staged in the wavefront's LDS) and the 16 lanes that hold a
+// point's row are summed with shuffles.  One workgroup per box; its
+// wavefronts take the box's 16-point blocks in turn.
 constexpr int KMAX = DMK_FAR_PMAX / 4;
 
 template <int M, bool ACC>

@@ -214,9 +214,9 @@ __device__ inline double win_series(const FarWin &w, const double *cf, double t)
 
 __device__ inline double win_phi(const FarWin &w, double t) { return win_series(w, w.cheb, t); }
 
-// phihat(q) and phihat'(q); the quadrature nodes are split over the 64
-// lanes of the wavefront and the partial sums combined with shuffles (in a
-// fixed order), so every lane returns the same values
+// phihat(q) and phihat'(q), the same on every lane of the wavefront.  Beyond
+// the band the quadrature nodes are split over the 64 lanes and the partial
+// sums combined with shuffles in a fixed order.
 __device__ inline void win_hat(const FarWin &w, double q, int lane, double &ph, double &dph)
 {
     if (!w.pswf) {
@@ -225,7 +225,7 @@ __device__ inline void win_hat(const FarWin &w, double q, int lane, double &ph, 
         return;
     }
     if (q <= w.c) {
-        // in the band the window's transform is the window itself (the
+        // in the band the window's transform is the window rescaled (the
         // eigen-relation of psi_0^c, Sec. 2.2): phihat(q) = phi(q/c) / phi(0)
         const double t = q / w.c, phi0 = win_phi(w, 0.0);
         ph = win_phi(w, t) / phi0;
