@@ -62,10 +62,14 @@ struct Cfg {
     static constexpr bool DRAIN_HALF = F32 || !BWD || KERN == 0;
     static constexpr int QCAP = DRAIN_HALF ? 2 * WAVE : 3 * WAVE;
     // LDS bytes of the staged sources and of one wavefront's queue; tiles use
-    // TILE_NW wavefronts unless that would not fit in the 160 KiB of a CU
+    // TILE_NW wavefronts, 8 when only one workgroup fits in the 160 KiB of a
+    // CU (more resident waves for the same staged tile; the rest of the
+    // workgroup's LDS is below 16 KiB), and 2 if TILE_NW would not fit at all
     static constexpr int STAGE_B = TILE_CAP * (16 + (F32 ? 16 + 4 * (NPL - 1) : 8 * (3 + NPL)));
     static constexpr int WAVE_B = QCAP * 4;
-    static constexpr int NW = (STAGE_B + TILE_NW * WAVE_B <= 150 * 1024) ? TILE_NW : 2;
+    static constexpr int NW = (STAGE_B + TILE_NW * WAVE_B > 150 * 1024) ? 2
+                              : (STAGE_B + TILE_NW * WAVE_B + 16 * 1024 > 80 * 1024) ? 8
+                                                                                       : TILE_NW;
     static constexpr int TPW = TILE_T / NW;              // targets per wavefront
 };
 
@@ -575,7 +579,7 @@ __device__ inline void wave_sum(T *v)
 }
 
 template <int KERN, typename FP, bool BWD, int WIN>
-__global__ __launch_bounds__(TILE_NW * WAVE) void k_residual(ResParams P, WinArg<WIN, FP> WC)
+__global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(ResParams P, WinArg<WIN, FP> WC)
 {
     using C = Cfg<KERN, FP, BWD>;
     using T = FP;
