@@ -45,6 +45,9 @@ struct KDim {
     static constexpr int MOUT = (K == 0) ? 1 : 3;
 };
 
+// a scan step reads a window of 128 staged slots
+static_assert(TILE_CAP >= 2 * WAVE && TILE_CAP < 65536, "staged slots per tile");
+
 template <int KERN, typename FP, bool BWD>
 struct Cfg {
     static constexpr int K = KERN;
@@ -551,6 +554,19 @@ __device__ inline bool seg_sum(int tag, T *v)
 
 // inclusive prefix sum over the 64 lanes (shifts within rows, then carries
 // into the following rows)
+// lanes 0 .. n-1 of a wavefront as a bit mask (n clamped to [0, 64])
+__device__ inline uint64_t lanes_below(int n)
+{
+    return n <= 0 ? 0ull : (n >= WAVE ? ~0ull : (1ull << n) - 1ull);
+}
+
+// whether this lane's bit of a uniform mask is set (the mask itself serves
+// as the lane condition, no per-lane shift)
+__device__ inline bool lane_in(uint64_t m)
+{
+    return __builtin_amdgcn_inverse_ballot_w64(m);
+}
+
 __device__ inline int wave_incl_scan(int v)
 {
     v += dpp_int<DPP_ROW_SHR + 1, 0xf>(v, 0);
@@ -860,26 +876,33 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
             const uint32_t tag = (uint32_t)t << 16;
             // Each step tests sources [p, p + 128) (slots past b belong to other
             // slabs, farther than the cutoff, and fail the pair step's exact
-            // test).  Hits are appended at queue[qn ..) in lane order, those of
-            // the first half first; entry = (t << 16) | source slot.  A step
-            // reaching past the staged sources clamps its reads and drops the
-            // hits there.
+            // test).  The step reads the 128-slot window at pr = min(p, TILE_CAP
+            // - 128), inside the staging arrays; its lanes below p (tested by
+            // the step before, or outside the target's range) and at or past
+            // clen (not staged) get a threshold of -inf, so the hit test is one
+            // compare and its ballot is the compare's lane mask.  Hits are
+            // appended at queue[qn ..) in lane order, those of the first half
+            // first; entry = (t << 16) | source slot.
             for (int p = a; p < b; p += 2 * WAVE) {
-                int i0 = p + lane, i1 = p + WAVE + lane;
-                bool in0 = true, in1 = true;
+                // a shifted window (p > TILE_CAP - 128) reaches past clen too
+                int pr = p;
+                uint64_t m0 = ~0ull, m1 = ~0ull;  // lanes of each half that take part
                 if (p + 2 * WAVE > clen) {
-                    in0 = i0 < clen;
-                    in1 = i1 < clen;
-                    i0 = in0 ? i0 : 0;
-                    i1 = in1 ? i1 : 0;
+                    pr = min(p, TILE_CAP - 2 * WAVE);
+                    const int lo = p - pr, hi = clen - pr;
+                    m0 = lanes_below(hi) & ~lanes_below(lo);
+                    m1 = lanes_below(hi - WAVE) & ~lanes_below(lo - WAVE);
                 }
-                const float4 s0 = S.sc[i0], s1 = S.sc[i1];
+                const float thr0 = lane_in(m0) ? thr : -INFINITY;
+                const float thr1 = lane_in(m1) ? thr : -INFINITY;
+                const float4 *win = &S.sc[pr];
+                const float4 s0 = win[lane], s1 = win[WAVE + lane];
                 // (|s|^2 - 2 s.t) / 2 against (rc2s - |t|^2) / 2
                 const float ra = fmaf(-s0.x, tx, fmaf(-s0.y, ty, fmaf(-s0.z, tz, s0.w)));
                 const float rb = fmaf(-s1.x, tx, fmaf(-s1.y, ty, fmaf(-s1.z, tz, s1.w)));
-                const bool ha = (ra < thr) && in0, hb = (rb < thr) && in1;
-                const uint64_t ma = __ballot(ha), mb = __ballot(hb);
-                const uint32_t ea = (tag | (uint32_t)p) + (uint32_t)lane;
+                const bool ha = ra < thr0, hb = rb < thr1;
+                const uint64_t ma = __builtin_amdgcn_ballot_w64(ha), mb = __builtin_amdgcn_ballot_w64(hb);
+                const uint32_t ea = (tag | (uint32_t)pr) + (uint32_t)lane;
                 const uint32_t ra_ = __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u));
                 const uint32_t rb_ = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
                 if constexpr (C::DRAIN_HALF) {
