@@ -240,7 +240,9 @@ const char *dmk_version(void);
  * [1, DMK_FAR_MMAX], K_i outside [0, DMK_FAR_KMAX], cubes that do not tile the
  * cell), DMK_ECUTOFF (sigma0 <= 0), DMK_EUNSUPPORTED (bad window, or
  * |k|max sigma0 > 4096 with the PSWF window), DMK_ESIZE (workspace too small,
- * or more than 8.5e9 wave numbers in all).
+ * or sizes for which one kernel launch would hold 2^32 or more work-items:
+ * about 6.7e7 wave numbers with all n_i >= 0, 4.3e9 in all, or grid
+ * contractions of that order).
  */
 #define DMK_FAR_PMAX 64
 #define DMK_FAR_MMAX 4096

@@ -16,6 +16,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "dmk_internal.h"
 
 #pragma clang fp contract(off)
@@ -395,12 +397,12 @@ struct ColView {
 };
 
 template <bool WRITE>
-__global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int32_t *__restrict__ counts, int4 *__restrict__ tiles,
-                                                int32_t *__restrict__ tkey)
+__global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *__restrict__ counts,
+                                                int4 *__restrict__ tiles, int32_t *__restrict__ tkey)
 {
     __shared__ int snt[TW_ZST];
     __shared__ int ssl[TW_ZST];
-    const int col = blockIdx.x;
+    const int col = col0 + (int)blockIdx.x;
     const int lane = threadIdx.x;
     const int b0 = col / g.n[1], b1 = col % g.n[1];
     int ccol[9];
@@ -674,12 +676,18 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     int32_t *tkey2 = tkey + bins->max_tiles;
     int32_t *torder = tkey2 + bins->max_tiles;
     int32_t *thist = torder + bins->max_tiles;
-    hipLaunchKernelGGL(k_tiles<false>, dim3((unsigned)ncol), dim3(WAVE), 0, stream, tg, colcnt, tiles_u, tkey);
+    // one wavefront per column, in launches of fewer than 2^32 work-items
+    constexpr int64_t TCB = 0xffffffffu / WAVE;
+    for (int64_t c0 = 0; c0 < ncol; c0 += TCB)
+        hipLaunchKernelGGL(k_tiles<false>, dim3((unsigned)std::min(TCB, ncol - c0)), dim3(WAVE), 0, stream, tg,
+                           (int)c0, colcnt, tiles_u, tkey);
     // keep the raw count of the last column, scan, then total
     DMK_HIP_CHECK(hipMemcpyAsync(bins->status + 2, colcnt + ncol - 1, sizeof(int32_t), hipMemcpyDeviceToDevice,
                                  stream));
     scan_excl(colcnt, ncol, thist + 256 * ((bins->max_tiles + RS_TILE - 1) / RS_TILE), stream);
-    hipLaunchKernelGGL(k_tiles<true>, dim3((unsigned)ncol), dim3(WAVE), 0, stream, tg, colcnt, tiles_u, tkey);
+    for (int64_t c0 = 0; c0 < ncol; c0 += TCB)
+        hipLaunchKernelGGL(k_tiles<true>, dim3((unsigned)std::min(TCB, ncol - c0)), dim3(WAVE), 0, stream, tg,
+                           (int)c0, colcnt, tiles_u, tkey);
     hipLaunchKernelGGL(k_tile_total, dim3(1), dim3(1), 0, stream, colcnt, (int)ncol, bins->status + 2,
                        bins->status);
     DMK_HIP_CHECK(hipGetLastError());

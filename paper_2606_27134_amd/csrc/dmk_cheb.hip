@@ -22,6 +22,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "dmk_internal.h"
 
 namespace dmk {
@@ -33,9 +35,12 @@ struct ChebGeom {
     int p;
     int64_t N;
     int64_t G[3];   // n_i p
+    int64_t wg0;    // first workgroup of this launch (per-box kernels, launched in chunks)
 };
 
 constexpr int CB_T = 256;
+// workgroups of one launch (fewer than 2^32 work-items)
+constexpr int64_t MAX_WG = 0xffffffffu / CB_T;
 
 // accumulator tile of v_mfma_f64_16x16x4 (4 doubles per lane)
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -104,8 +109,9 @@ __global__ __launch_bounds__(CB_T) void k_cheb_anterp(ChebGeom g, int ch, int ns
 {
     extern __shared__ double sm[];
     const int p = g.p;
-    const int64_t box = blockIdx.x / nsplit;
-    const int part = blockIdx.x - (int)(box * nsplit);
+    const int64_t wg = g.wg0 + blockIdx.x;
+    const int64_t box = wg / nsplit;
+    const int part = (int)(wg - box * nsplit);
     const int64_t b0 = box / ((int64_t)g.n[1] * g.n[2]), b1 = (box / g.n[2]) % g.n[1], b2 = box % g.n[2];
     const int64_t tot = g.G[0] * g.G[1] * g.G[2];
     const int nn = p * p * p;
@@ -174,8 +180,9 @@ __global__ __launch_bounds__(CB_T) void k_cheb_anterp_mfma(ChebGeom g, int ch, i
     constexpr int NT = AnterpTiles<M>::NT;
     extern __shared__ double sm[];
     const int p = g.p;
-    const int64_t box = blockIdx.x / nsplit;
-    const int part = blockIdx.x - (int)(box * nsplit);
+    const int64_t wg = g.wg0 + blockIdx.x;
+    const int64_t box = wg / nsplit;
+    const int part = (int)(wg - box * nsplit);
     const int64_t b0 = box / ((int64_t)g.n[1] * g.n[2]), b1 = (box / g.n[2]) % g.n[1], b2 = box % g.n[2];
     const int64_t tot = g.G[0] * g.G[1] * g.G[2];
     const int pp = p * p;
@@ -326,7 +333,7 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32
     extern __shared__ double sm[];
     const int p = g.p;
     const int64_t N = g.N;
-    const int64_t box = blockIdx.x;
+    const int64_t box = g.wg0 + blockIdx.x;
     const int64_t b0 = box / ((int64_t)g.n[1] * g.n[2]), b1 = (box / g.n[2]) % g.n[1], b2 = box % g.n[2];
     const int64_t tot = g.G[0] * g.G[1] * g.G[2];
     const int lane = threadIdx.x & (WAVE - 1);
@@ -423,8 +430,6 @@ struct SelfWin {
 __global__ void k_self_term_w(int ncomp, int64_t N, int pswf, int nterms, SelfWin w, double sigma0,
                               const double *__restrict__ rho, double *__restrict__ u)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= N * ncomp) return;
     double phi0;
     if (pswf) {
         phi0 = 0.0;
@@ -432,7 +437,9 @@ __global__ void k_self_term_w(int ncomp, int64_t N, int pswf, int nterms, SelfWi
     } else {
         phi0 = 1.0 / sqrt(M_PI);
     }
-    u[e] += -phi0 / (2.0 * M_PI * sigma0) * rho[e];
+    const double f = -phi0 / (2.0 * M_PI * sigma0);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N * ncomp; e += (int64_t)gridDim.x * blockDim.x)
+        u[e] += f * rho[e];
 }
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -495,24 +502,26 @@ extern "C" int dmk_cheb_anterp(const dmk_grid *grid, const dmk_bins *bins, int p
         const int ngroup = ((p + 15) / 16) * (((p * p + 15) / 16 + nt - 1) / nt);
         const int nsplit = (ngroup + CB_T / WAVE - 1) / (CB_T / WAVE);
         const int64_t nwg = nbox * nsplit;
-        if (nwg > 0x7fffffff) return DMK_ESIZE;
-        const dim3 grd((unsigned)nwg);
-        switch (m) {
-        case 1: hipLaunchKernelGGL(k_cheb_anterp_mfma<1>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
-        case 3: hipLaunchKernelGGL(k_cheb_anterp_mfma<3>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
-        default: hipLaunchKernelGGL(k_cheb_anterp_mfma<9>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
+        for (g.wg0 = 0; g.wg0 < nwg; g.wg0 += MAX_WG) {
+            const dim3 grd((unsigned)std::min(MAX_WG, nwg - g.wg0));
+            switch (m) {
+            case 1: hipLaunchKernelGGL(k_cheb_anterp_mfma<1>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
+            case 3: hipLaunchKernelGGL(k_cheb_anterp_mfma<3>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
+            default: hipLaunchKernelGGL(k_cheb_anterp_mfma<9>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
+            }
         }
         DMK_HIP_CHECK(hipGetLastError());
         return DMK_OK;
     }
     const int nsplit = (p * p * p + CB_NODES - 1) / CB_NODES;
     const int64_t nwg = nbox * nsplit;
-    if (nwg > 0x7fffffff) return DMK_ESIZE;
-    const dim3 grd((unsigned)nwg);
-    switch (m) {
-    case 1: hipLaunchKernelGGL(k_cheb_anterp<1>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
-    case 3: hipLaunchKernelGGL(k_cheb_anterp<3>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
-    default: hipLaunchKernelGGL(k_cheb_anterp<9>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
+    for (g.wg0 = 0; g.wg0 < nwg; g.wg0 += MAX_WG) {
+        const dim3 grd((unsigned)std::min(MAX_WG, nwg - g.wg0));
+        switch (m) {
+        case 1: hipLaunchKernelGGL(k_cheb_anterp<1>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
+        case 3: hipLaunchKernelGGL(k_cheb_anterp<3>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
+        default: hipLaunchKernelGGL(k_cheb_anterp<9>, grd, dim3(CB_T), lds, stream, g, ch, nsplit, bsp, pm, lag, rho, rho_grid); break;
+        }
     }
     DMK_HIP_CHECK(hipGetLastError());
     return DMK_OK;
@@ -534,8 +543,9 @@ extern "C" int dmk_cheb_eval(const dmk_grid *grid, const dmk_bins *bins, int p, 
     const int64_t nbox = (g.G[0] / p) * (g.G[1] / p) * (g.G[2] / p);
     if (g.N >= 16 * nbox) {
         // boxes of 16 or more points on average: matrix-core contraction per box
-        const dim3 grd((unsigned)nbox);
         const size_t elds = sizeof(double) * (size_t)(CB_T / WAVE) * 32 * p;
+        for (g.wg0 = 0; g.wg0 < nbox; g.wg0 += MAX_WG) {
+        const dim3 grd((unsigned)std::min(MAX_WG, nbox - g.wg0));
         if (accumulate) {
             switch (m) {
             case 1: hipLaunchKernelGGL((k_cheb_eval_mfma<1, true>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
@@ -548,6 +558,7 @@ extern "C" int dmk_cheb_eval(const dmk_grid *grid, const dmk_bins *bins, int p, 
             case 3: hipLaunchKernelGGL((k_cheb_eval_mfma<3, false>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
             default: hipLaunchKernelGGL((k_cheb_eval_mfma<9, false>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
             }
+        }
         }
         DMK_HIP_CHECK(hipGetLastError());
         return DMK_OK;
@@ -588,7 +599,10 @@ extern "C" int dmk_self_term(int kernel, double sigma0, const dmk_pswf *win, int
     if (kernel == 2 || kernel == 3 || N == 0) return DMK_OK;  // no self term for stresslet and rotlet
     if (!rho || !u) return DMK_EINVAL;
     const int nc = kernel == 0 ? 1 : 3;
-    hipLaunchKernelGGL(k_self_term_w, dim3(nblk(N * nc, 256)), dim3(256), 0, stream, nc, N, win ? 1 : 0, nterms, w,
+    // grid-stride over the N m elements (at most 65536 workgroups)
+    const unsigned nb = (unsigned)std::min<int64_t>(65536, (N + 255) / 256 * nc);
+    hipLaunchKernelGGL(k_self_term_w, dim3(nb), dim3(256), 0, stream, nc, N,
+                       win ? 1 : 0, nterms, w,
                        sigma0, rho, u);
     DMK_HIP_CHECK(hipGetLastError());
     return DMK_OK;

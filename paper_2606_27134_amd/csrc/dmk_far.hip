@@ -60,9 +60,8 @@ struct FarWin {
 };
 
 // E_i[g][n] = exp(2 pi i n X_i[g] / L_i), X_i[g] / L_i = (b + 1/2 + cos((2j+1) pi/(2p))/2) / M_i
-__global__ void k_far_tables(FarGeom g, double2 *__restrict__ E)
+__device__ inline void far_table_entry(const FarGeom &g, double2 *__restrict__ E, int64_t t)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int ax = 0;
     int64_t r = t;
     while (ax < 3 && r >= (int64_t)g.G[ax] * g.W[ax]) {
@@ -255,19 +254,54 @@ __device__ inline void win_hat(const FarWin &w, double q, int lane, double &ph, 
     dph = -2.0 * hw * b;
 }
 
-// W[j][m] = sum_q Khat_jq(k_m) chi[q][m] for every mode m (0 at k = 0)
-// (one wavefront per mode)
+// phihat(q) and phihat'(q) at q = |k| sigma for the wave numbers of one
+// octant, n_i = 0 .. K_i: the mode weights depend on the sign of each n_i only
+// through k itself, so the window's transform (a quadrature beyond the band)
+// is evaluated once per octant mode m, by one wavefront.  k^2 is formed as in
+// the weights kernel, so both see the same q.
+__device__ inline void far_phihat_mode(const FarGeom &g, const FarWin &w, double2 *__restrict__ PH, int64_t m,
+                                       int lane)
+{
+    const int64_t o1 = g.K[1] + 1, o2 = g.K[2] + 1;
+    if (m >= (int64_t)(g.K[0] + 1) * o1 * o2) return;
+    const int a0 = (int)(m / (o1 * o2)), a1 = (int)((m / o2) % o1), a2 = (int)(m % o2);
+    double ph = 0.0, dph = 0.0;
+    if (a0 != 0 || a1 != 0 || a2 != 0) {
+        const double k[3] = {2.0 * M_PI * a0 / g.L[0], 2.0 * M_PI * a1 / g.L[1], 2.0 * M_PI * a2 / g.L[2]};
+        const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        win_hat(w, sqrt(k2) * w.sigma, lane, ph, dph);
+    }
+    if (lane == 0) PH[m] = make_double2(ph, dph);
+}
+
+// One launch for the two independent set-up tables: workgroups below nbt
+// write the phase tables E (one entry per thread), the rest the window's
+// transform per octant mode (one mode per wavefront).
+constexpr int PREP_T = 256;
+
+__global__ __launch_bounds__(PREP_T) void k_far_prep(FarGeom g, FarWin w, double2 *__restrict__ E,
+                                                     double2 *__restrict__ PH, unsigned nbt)
+{
+    if (blockIdx.x < nbt) {
+        far_table_entry(g, E, (int64_t)blockIdx.x * PREP_T + threadIdx.x);
+        return;
+    }
+    const int64_t m = (int64_t)(blockIdx.x - nbt) * (PREP_T / WAVE) + threadIdx.x / WAVE;
+    far_phihat_mode(g, w, PH, m, threadIdx.x & (WAVE - 1));
+}
+
+// W[j][m] = sum_q Khat_jq(k_m) chi[q][m] for every mode m (0 at k = 0), one
+// thread per mode, with phihat and phihat' from the octant table
 constexpr int FW_T = 256;
 
 template <int KERN>
-__global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, FarWin w, const double2 *__restrict__ chi,
-                                                      double2 *__restrict__ Wt)
+__global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, double sigma, const double2 *__restrict__ PH,
+                                                      const double2 *__restrict__ chi, double2 *__restrict__ Wt)
 {
     constexpr int MI = KERN == 0 ? 1 : (KERN == 2 ? 9 : 3);
     constexpr int MO = KERN == 0 ? 1 : 3;
     const int64_t nm = (int64_t)g.W[0] * g.W[1] * g.W[2];
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t m = (int64_t)blockIdx.x * (FW_T / WAVE) + threadIdx.x / WAVE;
+    const int64_t m = (int64_t)blockIdx.x * FW_T + threadIdx.x;
     if (m >= nm) return;
     const int n0 = (int)(m / ((int64_t)g.W[1] * g.W[2])) - g.K[0];
     const int n1 = (int)((m / g.W[2]) % g.W[1]) - g.K[1];
@@ -277,9 +311,11 @@ __global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, FarWin w, const
     if (n0 != 0 || n1 != 0 || n2 != 0) {
         const double k[3] = {2.0 * M_PI * n0 / g.L[0], 2.0 * M_PI * n1 / g.L[1], 2.0 * M_PI * n2 / g.L[2]};
         const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-        const double q = sqrt(k2) * w.sigma;
-        double ph, dph;
-        win_hat(w, q, lane, ph, dph);
+        const double q = sqrt(k2) * sigma;
+        const int64_t o =
+            ((int64_t)abs(n0) * (g.K[1] + 1) + abs(n1)) * (int64_t)(g.K[2] + 1) + abs(n2);
+        const double2 pd = PH[o];
+        const double ph = pd.x, dph = pd.y;
         const double Hh = ph / k2;
         const double Bh = (ph - 0.5 * q * dph) / (k2 * k2);
         double2 x[MI];
@@ -321,15 +357,14 @@ __global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, FarWin w, const
             for (int j = 0; j < 3; ++j) out[j] = make_double2(-h * ci[j], h * cr[j]);
         }
     }
-    if (lane == 0)
-        for (int j = 0; j < MO; ++j) Wt[j * nm + m] = out[j];
+    for (int j = 0; j < MO; ++j) Wt[j * nm + m] = out[j];
 }
 
 int m_in_k(int k) { return k == 0 ? 1 : (k == 2 ? 9 : 3); }
 int m_out_k(int k) { return k == 0 ? 1 : 3; }
 
 struct FarLayout {
-    int64_t E, T1, T2, CHI, WT, V1, V2, total;  // byte offsets
+    int64_t E, T1, T2, CHI, WT, V1, V2, PH, total;  // byte offsets
 };
 
 FarLayout far_layout(const FarGeom &g, int kernel)
@@ -354,6 +389,8 @@ FarLayout far_layout(const FarGeom &g, int kernel)
     off = al(off + z * J * G0 * W1 * W2);
     l.V2 = off;
     off = al(off + z * J * G0 * G1 * W2);
+    l.PH = off;
+    off = al(off + z * (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1));
     l.total = off;
     return l;
 }
@@ -417,7 +454,22 @@ void gauss_legendre01(double *x, double *w)
     }
 }
 
-inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+inline int64_t nblk(int64_t n, int t) { return (n + t - 1) / t; }
+
+// a dispatch holds fewer than 2^32 work-items
+inline bool grid_fits(int64_t blocks, int threads) { return blocks * threads <= (int64_t)0xffffffff; }
+
+// the contraction runs on the matrix cores (16 x 16 output tiles, one
+// workgroup each) when every dimension fills a tile and the grid fits
+inline bool mode_on_mfma(int64_t A, int I, int O, int C)
+{
+    return O >= 16 && C >= 16 && I >= 16 && grid_fits(A * ((O + 15) / 16) * ((C + 15) / 16), MM_W * WAVE);
+}
+
+inline bool mode_fits(int64_t A, int I, int O, int C)
+{
+    return mode_on_mfma(A, I, O, C) || grid_fits(nblk(A * O * C, 256), 256);
+}
 
 template <bool RIN, bool ROUT, bool CONJ>
 void mode(const void *X, const double2 *E, int64_t A, int I, int O, int C, int64_t si, int64_t so, double s, void *Y,
@@ -425,14 +477,14 @@ void mode(const void *X, const double2 *E, int64_t A, int I, int O, int C, int64
 {
     const int64_t n = A * O * C;
     if (n <= 0) return;
-    if (O >= 16 && C >= 16 && I >= 16 && A * ((O + 15) / 16) * ((C + 15) / 16) <= 0x7fffffff) {
+    if (mode_on_mfma(A, I, O, C)) {
         // 16 x 16 output tiles, one workgroup each, on the matrix cores
         const int64_t tiles = A * ((O + 15) / 16) * ((C + 15) / 16);
         hipLaunchKernelGGL((k_mode_mfma<RIN, ROUT, CONJ>), dim3((unsigned)tiles), dim3(MM_W * WAVE), 0, st, X, E, A,
                            I, O, C, si, so, s, Y);
         return;
     }
-    hipLaunchKernelGGL((k_mode<RIN, ROUT, CONJ>), dim3(nblk(n, 256)), dim3(256), 0, st, X, E, A, I, O, C, si, so, s,
+    hipLaunchKernelGGL((k_mode<RIN, ROUT, CONJ>), dim3((unsigned)nblk(n, 256)), dim3(256), 0, st, X, E, A, I, O, C, si, so, s,
                        Y);
 }
 
@@ -480,32 +532,48 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
         }
         if (sqrt(kk) * sigma0 > 4096.0) return DMK_EUNSUPPORTED;
     }
-    // launch-size limits: 4 modes per workgroup of the weights kernel
-    if ((int64_t)g.W[0] * g.W[1] * g.W[2] / 4 >= 0x7fffffff) return DMK_ESIZE;
+    // launch sizes: every dispatch of the evaluation below holds fewer than 2^32 work-items
+    {
+        const int64_t Q = m_in_k(kernel), J = m_out_k(kernel);
+        const int64_t G0 = g.G[0], G1 = g.G[1], W1 = g.W[1], W2 = g.W[2];
+        const int64_t ne = G0 * g.W[0] + G1 * W1 + (int64_t)g.G[2] * W2;
+        const int64_t no = (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1);
+        const int64_t nm = (int64_t)g.W[0] * W1 * W2;
+        if (!grid_fits((int64_t)nblk(ne, PREP_T) + (int64_t)nblk(no, PREP_T / WAVE), PREP_T) ||
+            !grid_fits(nblk(nm, FW_T), FW_T) || !mode_fits(Q * G0 * G1, g.G[2], g.W[2], 1) ||
+            !mode_fits(Q * G0, g.G[1], g.W[1], g.W[2]) || !mode_fits(Q, g.G[0], g.W[0], (int)(W1 * W2)) ||
+            !mode_fits(J, g.W[0], g.G[0], (int)(W1 * W2)) || !mode_fits(J * G0, g.W[1], g.G[1], g.W[2]) ||
+            !mode_fits(J * G0 * G1, g.W[2], g.G[2], 1))
+            return DMK_ESIZE;
+    }
     const FarLayout l = far_layout(g, kernel);
     if (ws_bytes < (size_t)l.total) return DMK_ESIZE;
     char *b = (char *)ws;
     double2 *E = (double2 *)(b + l.E);
     double2 *T1 = (double2 *)(b + l.T1), *T2 = (double2 *)(b + l.T2), *CHI = (double2 *)(b + l.CHI);
     double2 *WT = (double2 *)(b + l.WT), *V1 = (double2 *)(b + l.V1), *V2 = (double2 *)(b + l.V2);
+    double2 *PH = (double2 *)(b + l.PH);
     const int64_t Q = m_in_k(kernel), J = m_out_k(kernel);
     const int G0 = g.G[0], G1 = g.G[1], G2 = g.G[2], W0 = g.W[0], W1 = g.W[1], W2 = g.W[2];
     const double2 *E0 = E + g.eoff[0], *E1 = E + g.eoff[1], *E2 = E + g.eoff[2];
     const double invV = 1.0 / (g.L[0] * g.L[1] * g.L[2]);
 
     const int64_t ne = (int64_t)G0 * W0 + (int64_t)G1 * W1 + (int64_t)G2 * W2;
-    hipLaunchKernelGGL(k_far_tables, dim3(nblk(ne, 256)), dim3(256), 0, stream, g, E);
+    const int64_t no = (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1);
+    const unsigned nbt = (unsigned)nblk(ne, PREP_T);
+    hipLaunchKernelGGL(k_far_prep, dim3(nbt + (unsigned)nblk(no, PREP_T / WAVE)), dim3(PREP_T), 0, stream, g, w, E, PH, nbt);
     // structure factor (eq. (structurefac)): contract g2, g1, g0 with conj(E)
     mode<true, false, true>(rho_grid, E2, Q * G0 * G1, G2, W2, 1, W2, 1, 1.0, T1, stream);
     mode<false, false, true>(T1, E1, Q * G0, G1, W1, W2, W1, 1, 1.0, T2, stream);
     mode<false, false, true>(T2, E0, Q, G0, W0, (int)((int64_t)W1 * W2), W0, 1, invV, CHI, stream);
-    // mode weights
+    // mode weights (with the window's transform per octant mode from k_far_prep)
     const int64_t nm = (int64_t)W0 * W1 * W2;
+    const dim3 gw((unsigned)nblk(nm, FW_T));
     switch (kernel) {
-    case 0: hipLaunchKernelGGL(k_far_weights<0>, dim3(nblk(nm, FW_T / WAVE)), dim3(FW_T), 0, stream, g, w, CHI, WT); break;
-    case 1: hipLaunchKernelGGL(k_far_weights<1>, dim3(nblk(nm, FW_T / WAVE)), dim3(FW_T), 0, stream, g, w, CHI, WT); break;
-    case 2: hipLaunchKernelGGL(k_far_weights<2>, dim3(nblk(nm, FW_T / WAVE)), dim3(FW_T), 0, stream, g, w, CHI, WT); break;
-    default: hipLaunchKernelGGL(k_far_weights<3>, dim3(nblk(nm, FW_T / WAVE)), dim3(FW_T), 0, stream, g, w, CHI, WT); break;
+    case 0: hipLaunchKernelGGL(k_far_weights<0>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, WT); break;
+    case 1: hipLaunchKernelGGL(k_far_weights<1>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, WT); break;
+    case 2: hipLaunchKernelGGL(k_far_weights<2>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, WT); break;
+    default: hipLaunchKernelGGL(k_far_weights<3>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, WT); break;
     }
     // evaluation on the grids (eq. (eval_tensor)): contract n0, n1, n2 with E
     mode<false, false, false>(WT, E0, J, W0, G0, (int)((int64_t)W1 * W2), 1, W0, 1.0, V1, stream);

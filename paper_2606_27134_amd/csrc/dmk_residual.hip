@@ -81,7 +81,7 @@ struct ResParams {
     int n[3], D;
     double sigma, rc;
     int64_t N;
-    int ntiles;
+    int ntiles, tile0;  // tiles in all; first tile of this launch
     const double *ys;
     const int32_t *skey, *bs, *perm, *nbr;
     const int8_t *img;
@@ -607,7 +607,7 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
     const int w = __builtin_amdgcn_readfirstlane(tid / WAVE);
     // tiles are ordered heavy-first by the binning; consecutive workgroups go
     // to different XCDs, which spreads the heavy tiles over all of them
-    const int tile = blockIdx.x;
+    const int tile = P.tile0 + (int)blockIdx.x;
     if (tile >= P.ntiles) return;
 
     const int4 TD = P.tiles[tile];
@@ -1072,8 +1072,16 @@ void launch_one(const ResParams &P, const dmk_pswf *w, hipStream_t s)
     } else {
         (void)w;
     }
-    hipLaunchKernelGGL((k_residual<KERN, FP, BWD, WIN>), dim3((unsigned)P.ntiles),
-                       dim3(Cfg<KERN, FP, BWD>::NW * WAVE), 0, s, P, wc);
+    // one workgroup per tile, in launches of fewer than 2^32 work-items
+    constexpr int NT = Cfg<KERN, FP, BWD>::NW * WAVE;
+    constexpr int MAXB = (int)(0xffffffffu / NT);
+    for (int t0 = 0; t0 < P.ntiles; t0 += MAXB) {
+        ResParams Q = P;
+        Q.tile0 = t0;
+        hipLaunchKernelGGL((k_residual<KERN, FP, BWD, WIN>), dim3((unsigned)min(MAXB, P.ntiles - t0)), dim3(NT), 0, s,
+                           Q, wc);
+        if (P.ntiles - t0 <= MAXB) break;
+    }
 }
 
 template <bool BWD, int WIN>

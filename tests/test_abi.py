@@ -150,6 +150,10 @@ def test_far3p_host_argument_checks():
     # the largest mode ranges on every axis: more wave numbers than one launch covers
     huge = L.make_far_grid((1, 1, 1), (1, 1, 1), 2, (L.FAR_KMAX,) * 3)
     assert L.dmk_far3p_eval(huge, 0, 1.0, None, fake, fake, fake, 1 << 62, 0) == L.DMK_ESIZE
+    # 6.8e7 wave numbers with n_i >= 0 (a wavefront each: 4.4e9 work-items in
+    # one launch), though only 5.4e8 in all
+    wide = L.make_far_grid((1, 1, 1), (1, 1, 1), 2, (1024, 1024, 64))
+    assert L.dmk_far3p_eval(wide, 0, 1.0, None, fake, fake, fake, 1 << 62, 0) == L.DMK_ESIZE
     for args in [((1, 1, 1), (1, 1, 2), 8, (2, 2, 2)),      # cubes do not tile the cell
                  ((1, 1, 1), (1, 1, 1), 0, (2, 2, 2)),      # p < 1
                  ((1, 1, 1), (1, 1, 1), L.FAR_PMAX + 1, (2, 2, 2)),
