@@ -36,6 +36,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "dmk_internal.h"
 
 namespace dmk {
@@ -110,6 +113,103 @@ __global__ void k_mode(const void *__restrict__ Xv, const double2 *__restrict__ 
         ((double *)Yv)[yi] = s * re;
     else
         ((double2 *)Yv)[yi] = make_double2(s * re, s * im);
+}
+
+// The same mode product with its operands staged in LDS (few terms i, a small
+// coefficient table): a workgroup takes AB consecutive a and CB consecutive
+// c, copies coef(i, o) for all (i, o) and its block of X (AB x I x CB, rows of
+// CB contiguous values) into LDS with coalesced loads, and evaluates its
+// AB x O x CB outputs from there in the order of k_mode (same terms, same
+// fused multiply-adds), so the results are identical.
+constexpr int ML_T = 256;
+constexpr int ML_LDS = 48 * 1024;
+
+struct ModeBlock {
+    int ab, cb;   // a and c per workgroup
+    int64_t nwg;  // workgroups
+    size_t lds;   // bytes of LDS
+};
+
+template <bool RIN, bool ROUT, bool CONJ>
+__global__ __launch_bounds__(ML_T) void k_mode_lds(const void *__restrict__ Xv, const double2 *__restrict__ E,
+                                                   int64_t A, int I, int O, int C, int64_t si, int64_t so, double s,
+                                                   int ab, int cb, void *__restrict__ Yv)
+{
+    extern __shared__ double2 ml[];
+    double2 *es = ml;                         // coef(i, o) at es[i * O + o]
+    double *xr = (double *)(ml + (int64_t)I * O);  // X block (RIN)
+    double2 *xc = ml + (int64_t)I * O;        // X block (complex)
+    const int ncb = (C + cb - 1) / cb;
+    const int64_t a0 = (int64_t)(blockIdx.x / ncb) * ab;
+    const int c0 = (int)(blockIdx.x % ncb) * cb;
+    const int na = (int)min((int64_t)ab, A - a0), nc = min(cb, C - c0);
+    // staging, ML_U loads of a thread in flight before its stores
+    constexpr int ML_U = 8;
+    const int ne = I * O;
+    for (int k0 = threadIdx.x; k0 < ne; k0 += ML_U * ML_T) {
+        double2 v[ML_U];
+#pragma unroll
+        for (int u = 0; u < ML_U; ++u) {
+            const int k = k0 + u * ML_T;
+            if (k < ne) v[u] = E[(k / O) * si + (k % O) * so];
+        }
+#pragma unroll
+        for (int u = 0; u < ML_U; ++u)
+            if (k0 + u * ML_T < ne) es[k0 + u * ML_T] = v[u];
+    }
+    // block element (al, i, cl) at (al * I + i) * nc + cl
+    const int nx = na * I * nc;
+    for (int k0 = threadIdx.x; k0 < nx; k0 += ML_U * ML_T) {
+        typename std::conditional<RIN, double, double2>::type v[ML_U];
+#pragma unroll
+        for (int u = 0; u < ML_U; ++u) {
+            const int k = k0 + u * ML_T;
+            if (k < nx) {
+                const int row = k / nc, cl = k - row * nc;
+                const int64_t g = (a0 + row / I) * I * C + (int64_t)(row % I) * C + c0 + cl;
+                if constexpr (RIN)
+                    v[u] = ((const double *)Xv)[g];
+                else
+                    v[u] = ((const double2 *)Xv)[g];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < ML_U; ++u) {
+            const int k = k0 + u * ML_T;
+            if (k < nx) {
+                if constexpr (RIN)
+                    xr[k] = v[u];
+                else
+                    xc[k] = v[u];
+            }
+        }
+    }
+    __syncthreads();
+    const int ny = na * O * nc;
+    for (int k = threadIdx.x; k < ny; k += ML_T) {
+        const int cl = k % nc, o = (k / nc) % O, al = k / (nc * O);
+        double re = 0.0, im = 0.0;
+        const int xb = al * I * nc + cl;
+#pragma unroll 4
+        for (int i = 0; i < I; ++i) {
+            const double2 e = es[i * O + o];
+            const double ei = CONJ ? -e.y : e.y;
+            if constexpr (RIN) {
+                const double x = xr[xb + i * nc];
+                re = fma(e.x, x, re);
+                im = fma(ei, x, im);
+            } else {
+                const double2 x = xc[xb + i * nc];
+                re = fma(e.x, x.x, fma(-ei, x.y, re));
+                im = fma(e.x, x.y, fma(ei, x.x, im));
+            }
+        }
+        const int64_t yi = ((a0 + al) * O + o) * C + c0 + cl;
+        if constexpr (ROUT)
+            ((double *)Yv)[yi] = s * re;
+        else
+            ((double2 *)Yv)[yi] = make_double2(s * re, s * im);
+    }
 }
 
 // The same mode product on the FP64 matrix cores, for contractions large
@@ -466,9 +566,37 @@ inline bool mode_on_mfma(int64_t A, int I, int O, int C)
     return O >= 16 && C >= 16 && I >= 16 && grid_fits(A * ((O + 15) / 16) * ((C + 15) / 16), MM_W * WAVE);
 }
 
+// Blocks of the LDS form, used for the contractions along the last axis
+// (C = 1), where the direct form reads X and coef with strides across the
+// lanes: AB consecutive a per workgroup, up to 8 outputs per thread while the
+// grid keeps 512 workgroups or more and the staged tiles stay within 16 KiB
+// (more resident workgroups), so that each copy of coef serves many outputs.
+inline ModeBlock mode_block(int64_t A, int I, int O, int C, bool rin)
+{
+    ModeBlock b;
+    b.cb = 1;
+    for (int64_t r = std::max<int64_t>(1, std::min<int64_t>(8, A * O / (512 * ML_T)));; --r) {
+        b.ab = (int)std::min<int64_t>(A, std::max<int64_t>(1, (r * ML_T + O - 1) / O));
+        b.nwg = nblk(A, b.ab);
+        b.lds = sizeof(double2) * (size_t)I * O + (rin ? sizeof(double) : sizeof(double2)) * (size_t)b.ab * I;
+        if (r == 1 || b.lds <= 16 * 1024) break;
+    }
+    (void)C;
+    return b;
+}
+
+// used for C = 1 when its tiles fit and give at least one workgroup per CU
+// (smaller grids are latency-bound, where the direct form does better)
+inline bool mode_on_lds(int64_t A, int I, int O, int C, bool rin)
+{
+    if (C != 1) return false;
+    const ModeBlock b = mode_block(A, I, O, C, rin);
+    return b.lds <= (size_t)ML_LDS && b.nwg >= 256 && grid_fits(b.nwg, ML_T);
+}
+
 inline bool mode_fits(int64_t A, int I, int O, int C)
 {
-    return mode_on_mfma(A, I, O, C) || grid_fits(nblk(A * O * C, 256), 256);
+    return mode_on_mfma(A, I, O, C) || mode_on_lds(A, I, O, C, false) || grid_fits(nblk(A * O * C, 256), 256);
 }
 
 template <bool RIN, bool ROUT, bool CONJ>
@@ -482,6 +610,12 @@ void mode(const void *X, const double2 *E, int64_t A, int I, int O, int C, int64
         const int64_t tiles = A * ((O + 15) / 16) * ((C + 15) / 16);
         hipLaunchKernelGGL((k_mode_mfma<RIN, ROUT, CONJ>), dim3((unsigned)tiles), dim3(MM_W * WAVE), 0, st, X, E, A,
                            I, O, C, si, so, s, Y);
+        return;
+    }
+    if (mode_on_lds(A, I, O, C, RIN)) {
+        const ModeBlock b = mode_block(A, I, O, C, RIN);
+        hipLaunchKernelGGL((k_mode_lds<RIN, ROUT, CONJ>), dim3((unsigned)b.nwg), dim3(ML_T), b.lds, st, X, E, A, I, O,
+                           C, si, so, s, b.ab, b.cb, Y);
         return;
     }
     hipLaunchKernelGGL((k_mode<RIN, ROUT, CONJ>), dim3((unsigned)nblk(n, 256)), dim3(256), 0, st, X, E, A, I, O, C, si, so, s,
