@@ -228,14 +228,18 @@ constexpr int MM_W = 8;  // wavefronts per tile
 template <bool RIN, bool ROUT, bool CONJ>
 __global__ __launch_bounds__(MM_W * WAVE) void k_mode_mfma(const void *__restrict__ Xv,
                                                            const double2 *__restrict__ E, int64_t A, int I, int O,
-                                                           int C, int64_t si, int64_t so, double s,
-                                                           void *__restrict__ Yv)
+                                                           int C, int64_t si, int64_t so, double s, int nsplit,
+                                                           double2 *__restrict__ part, void *__restrict__ Yv)
 {
     __shared__ double red[MM_W - 1][8][WAVE];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
     const int to = (O + 15) / 16, tc = (C + 15) / 16;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = blockIdx.x / nsplit;
+    const int sp = (int)(blockIdx.x - tile * nsplit);
+    // this workgroup's groups of 4 terms: [g0, g1) of the split's share
+    const int ng = (I + 3) / 4;
+    const int g0 = (int)((int64_t)ng * sp / nsplit), g1 = (int)((int64_t)ng * (sp + 1) / nsplit);
     const int64_t a = tile / ((int64_t)to * tc);
     const int rem = (int)(tile - a * to * tc);
     const int ot = rem / tc, ct = rem - (rem / tc) * tc;
@@ -243,8 +247,8 @@ __global__ __launch_bounds__(MM_W * WAVE) void k_mode_mfma(const void *__restric
     const int oa = ot * 16 + li, cb = ct * 16 + li;
     const bool ook = oa < O, cok = cb < C;
     dbl4m dre = {0.0, 0.0, 0.0, 0.0}, dim = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 4 * wv; k0 < I; k0 += 4 * MM_W) {
-        const int k = k0 + lk;
+    for (int gq = g0 + wv; gq < g1; gq += MM_W) {
+        const int k = 4 * gq + lk;
         const bool kok = k < I;
         double er = 0.0, ei = 0.0, xr = 0.0, xi = 0.0;
         if (kok && ook) {
@@ -290,12 +294,33 @@ __global__ __launch_bounds__(MM_W * WAVE) void k_mode_mfma(const void *__restric
         const int o = ot * 16 + 4 * r + lk;
         if (o < O) {
             const int64_t yi = (a * O + o) * C + cb;
-            if constexpr (ROUT)
+            if (nsplit > 1) {
+                part[(int64_t)sp * A * O * C + yi] = make_double2(dre[r], dim[r]);
+            } else if constexpr (ROUT) {
                 ((double *)Yv)[yi] = s * dre[r];
-            else
+            } else {
                 ((double2 *)Yv)[yi] = make_double2(s * dre[r], s * dim[r]);
+            }
         }
     }
+}
+
+// Y = s * (sum of the nsplit partial results, in split order)
+template <bool ROUT>
+__global__ void k_mode_sum(const double2 *__restrict__ part, int64_t n, int nsplit, double s, void *__restrict__ Yv)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double re = 0.0, im = 0.0;
+    for (int q = 0; q < nsplit; ++q) {
+        const double2 v = part[q * n + t];
+        re += v.x;
+        im += v.y;
+    }
+    if constexpr (ROUT)
+        ((double *)Yv)[t] = s * re;
+    else
+        ((double2 *)Yv)[t] = make_double2(s * re, s * im);
 }
 
 // a Chebyshev series of the PSWF window in u = 2 t^2 - 1 (Clenshaw)
@@ -463,38 +488,6 @@ __global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, double sigma, c
 int m_in_k(int k) { return k == 0 ? 1 : (k == 2 ? 9 : 3); }
 int m_out_k(int k) { return k == 0 ? 1 : 3; }
 
-struct FarLayout {
-    int64_t E, T1, T2, CHI, WT, V1, V2, PH, total;  // byte offsets
-};
-
-FarLayout far_layout(const FarGeom &g, int kernel)
-{
-    const int64_t Q = m_in_k(kernel), J = m_out_k(kernel);
-    const int64_t G0 = g.G[0], G1 = g.G[1], W0 = g.W[0], W1 = g.W[1], W2 = g.W[2];
-    auto al = [](int64_t v) { return (v + 255) & ~(int64_t)255; };
-    FarLayout l{};
-    int64_t off = 0;
-    const int64_t z = (int64_t)sizeof(double2);
-    l.E = off;
-    off = al(off + z * ((int64_t)g.G[0] * W0 + (int64_t)g.G[1] * W1 + (int64_t)g.G[2] * W2));
-    l.T1 = off;
-    off = al(off + z * Q * G0 * G1 * W2);
-    l.T2 = off;
-    off = al(off + z * Q * G0 * W1 * W2);
-    l.CHI = off;
-    off = al(off + z * Q * W0 * W1 * W2);
-    l.WT = off;
-    off = al(off + z * J * W0 * W1 * W2);
-    l.V1 = off;
-    off = al(off + z * J * G0 * W1 * W2);
-    l.V2 = off;
-    off = al(off + z * J * G0 * G1 * W2);
-    l.PH = off;
-    off = al(off + z * (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1));
-    l.total = off;
-    return l;
-}
-
 int far_geom(const dmk_far_grid *fg, FarGeom &g)
 {
     if (!fg) return DMK_EINVAL;
@@ -559,11 +552,34 @@ inline int64_t nblk(int64_t n, int t) { return (n + t - 1) / t; }
 // a dispatch holds fewer than 2^32 work-items
 inline bool grid_fits(int64_t blocks, int threads) { return blocks * threads <= (int64_t)0xffffffff; }
 
-// the contraction runs on the matrix cores (16 x 16 output tiles, one
-// workgroup each) when every dimension fills a tile and the grid fits
+// Workgroups per 16 x 16 output tile on the matrix cores: with fewer tiles
+// than CUs the terms are split over several workgroups (partial tiles summed
+// by k_mode_sum) up to about 512 workgroups, each split keeping two groups of
+// 4 terms per wavefront (the 32-cube cuboid's first long-axis contraction: 114
+// tiles, 31 us in one workgroup each, 24 us in five with the sum)
+inline int mode_nsplit(int64_t A, int I, int O, int C)
+{
+    const int64_t tiles = A * ((O + 15) / 16) * ((C + 15) / 16);
+    if (tiles >= 256) return 1;
+    const int64_t ns = std::min<int64_t>((512 + tiles - 1) / tiles, ((I + 3) / 4) / (2 * MM_W));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(ns, 16));
+}
+
+// the contraction runs on the matrix cores (16 x 16 output tiles) when every
+// dimension fills a tile and the grid fits
 inline bool mode_on_mfma(int64_t A, int I, int O, int C)
 {
-    return O >= 16 && C >= 16 && I >= 16 && grid_fits(A * ((O + 15) / 16) * ((C + 15) / 16), MM_W * WAVE);
+    return O >= 16 && C >= 16 && I >= 16 &&
+           grid_fits(A * ((O + 15) / 16) * ((C + 15) / 16) * mode_nsplit(A, I, O, C), MM_W * WAVE) &&
+           grid_fits(nblk(A * O * C, 256), 256);
+}
+
+// doubles2 of partial results a contraction needs (0 without a split)
+inline int64_t mode_part(int64_t A, int I, int O, int C)
+{
+    if (!mode_on_mfma(A, I, O, C)) return 0;
+    const int ns = mode_nsplit(A, I, O, C);
+    return ns > 1 ? (int64_t)ns * A * O * C : 0;
 }
 
 // Blocks of the LDS form, used for the contractions along the last axis
@@ -601,15 +617,18 @@ inline bool mode_fits(int64_t A, int I, int O, int C)
 
 template <bool RIN, bool ROUT, bool CONJ>
 void mode(const void *X, const double2 *E, int64_t A, int I, int O, int C, int64_t si, int64_t so, double s, void *Y,
-          hipStream_t st)
+          double2 *part, hipStream_t st)
 {
     const int64_t n = A * O * C;
     if (n <= 0) return;
     if (mode_on_mfma(A, I, O, C)) {
-        // 16 x 16 output tiles, one workgroup each, on the matrix cores
+        // 16 x 16 output tiles on the matrix cores, nsplit workgroups each
         const int64_t tiles = A * ((O + 15) / 16) * ((C + 15) / 16);
-        hipLaunchKernelGGL((k_mode_mfma<RIN, ROUT, CONJ>), dim3((unsigned)tiles), dim3(MM_W * WAVE), 0, st, X, E, A,
-                           I, O, C, si, so, s, Y);
+        const int ns = mode_nsplit(A, I, O, C);
+        hipLaunchKernelGGL((k_mode_mfma<RIN, ROUT, CONJ>), dim3((unsigned)(tiles * ns)), dim3(MM_W * WAVE), 0, st, X,
+                           E, A, I, O, C, si, so, s, ns, part, Y);
+        if (ns > 1)
+            hipLaunchKernelGGL((k_mode_sum<ROUT>), dim3((unsigned)nblk(n, 256)), dim3(256), 0, st, part, n, ns, s, Y);
         return;
     }
     if (mode_on_lds(A, I, O, C, RIN)) {
@@ -620,6 +639,47 @@ void mode(const void *X, const double2 *E, int64_t A, int I, int O, int C, int64
     }
     hipLaunchKernelGGL((k_mode<RIN, ROUT, CONJ>), dim3((unsigned)nblk(n, 256)), dim3(256), 0, st, X, E, A, I, O, C, si, so, s,
                        Y);
+}
+
+struct FarLayout {
+    int64_t E, T1, T2, CHI, WT, V1, V2, PH, PART, total;  // byte offsets
+};
+
+FarLayout far_layout(const FarGeom &g, int kernel)
+{
+    const int64_t Q = m_in_k(kernel), J = m_out_k(kernel);
+    const int64_t G0 = g.G[0], G1 = g.G[1], W0 = g.W[0], W1 = g.W[1], W2 = g.W[2];
+    auto al = [](int64_t v) { return (v + 255) & ~(int64_t)255; };
+    FarLayout l{};
+    int64_t off = 0;
+    const int64_t z = (int64_t)sizeof(double2);
+    l.E = off;
+    off = al(off + z * ((int64_t)g.G[0] * W0 + (int64_t)g.G[1] * W1 + (int64_t)g.G[2] * W2));
+    l.T1 = off;
+    off = al(off + z * Q * G0 * G1 * W2);
+    l.T2 = off;
+    off = al(off + z * Q * G0 * W1 * W2);
+    l.CHI = off;
+    off = al(off + z * Q * W0 * W1 * W2);
+    l.WT = off;
+    off = al(off + z * J * W0 * W1 * W2);
+    l.V1 = off;
+    off = al(off + z * J * G0 * W1 * W2);
+    l.V2 = off;
+    off = al(off + z * J * G0 * G1 * W2);
+    l.PH = off;
+    off = al(off + z * (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1));
+    // partial results of the split contractions (the six of dmk_far3p_eval)
+    const int64_t G2 = g.G[2];
+    int64_t np = 0;
+    for (const int64_t v : {mode_part(Q * G0 * G1, (int)G2, (int)W2, 1), mode_part(Q * G0, (int)G1, (int)W1, (int)W2),
+                            mode_part(Q, (int)G0, (int)W0, (int)(W1 * W2)), mode_part(J, (int)W0, (int)G0, (int)(W1 * W2)),
+                            mode_part(J * G0, (int)W1, (int)G1, (int)W2), mode_part(J * G0 * G1, (int)W2, (int)G2, 1)})
+        np = std::max(np, v);
+    l.PART = off;
+    off = al(off + z * np);
+    l.total = off;
+    return l;
 }
 
 }  // namespace
@@ -686,7 +746,7 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     double2 *E = (double2 *)(b + l.E);
     double2 *T1 = (double2 *)(b + l.T1), *T2 = (double2 *)(b + l.T2), *CHI = (double2 *)(b + l.CHI);
     double2 *WT = (double2 *)(b + l.WT), *V1 = (double2 *)(b + l.V1), *V2 = (double2 *)(b + l.V2);
-    double2 *PH = (double2 *)(b + l.PH);
+    double2 *PH = (double2 *)(b + l.PH), *PART = (double2 *)(b + l.PART);
     const int64_t Q = m_in_k(kernel), J = m_out_k(kernel);
     const int G0 = g.G[0], G1 = g.G[1], G2 = g.G[2], W0 = g.W[0], W1 = g.W[1], W2 = g.W[2];
     const double2 *E0 = E + g.eoff[0], *E1 = E + g.eoff[1], *E2 = E + g.eoff[2];
@@ -697,9 +757,9 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     const unsigned nbt = (unsigned)nblk(ne, PREP_T);
     hipLaunchKernelGGL(k_far_prep, dim3(nbt + (unsigned)nblk(no, PREP_T / WAVE)), dim3(PREP_T), 0, stream, g, w, E, PH, nbt);
     // structure factor (eq. (structurefac)): contract g2, g1, g0 with conj(E)
-    mode<true, false, true>(rho_grid, E2, Q * G0 * G1, G2, W2, 1, W2, 1, 1.0, T1, stream);
-    mode<false, false, true>(T1, E1, Q * G0, G1, W1, W2, W1, 1, 1.0, T2, stream);
-    mode<false, false, true>(T2, E0, Q, G0, W0, (int)((int64_t)W1 * W2), W0, 1, invV, CHI, stream);
+    mode<true, false, true>(rho_grid, E2, Q * G0 * G1, G2, W2, 1, W2, 1, 1.0, T1, PART, stream);
+    mode<false, false, true>(T1, E1, Q * G0, G1, W1, W2, W1, 1, 1.0, T2, PART, stream);
+    mode<false, false, true>(T2, E0, Q, G0, W0, (int)((int64_t)W1 * W2), W0, 1, invV, CHI, PART, stream);
     // mode weights (with the window's transform per octant mode from k_far_prep)
     const int64_t nm = (int64_t)W0 * W1 * W2;
     const dim3 gw((unsigned)nblk(nm, FW_T));
@@ -710,9 +770,9 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     default: hipLaunchKernelGGL(k_far_weights<3>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, WT); break;
     }
     // evaluation on the grids (eq. (eval_tensor)): contract n0, n1, n2 with E
-    mode<false, false, false>(WT, E0, J, W0, G0, (int)((int64_t)W1 * W2), 1, W0, 1.0, V1, stream);
-    mode<false, false, false>(V1, E1, J * G0, W1, G1, W2, 1, W1, 1.0, V2, stream);
-    mode<false, true, false>(V2, E2, J * G0 * G1, W2, G2, 1, 1, W2, 1.0, u_grid, stream);
+    mode<false, false, false>(WT, E0, J, W0, G0, (int)((int64_t)W1 * W2), 1, W0, 1.0, V1, PART, stream);
+    mode<false, false, false>(V1, E1, J * G0, W1, G1, W2, 1, W1, 1.0, V2, PART, stream);
+    mode<false, true, false>(V2, E2, J * G0 * G1, W2, G2, 1, 1, W2, 1.0, u_grid, PART, stream);
     DMK_HIP_CHECK(hipGetLastError());
     return DMK_OK;
 }
