@@ -321,10 +321,14 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval(ChebGeom g, const int32_t *_
 // each D element is then weighted by l0(s_i, j0) l1(s_i, j1) (the block's
 // l0 and l1 rows staged in the wavefront's LDS) and the 16 lanes that hold a
 // point's row are summed with shuffles.  One workgroup per box; its
-// wavefronts take the box's 16-point blocks in turn.
+// wavefronts take the box's 16-point blocks in turn.  Each lane takes the
+// contiguous run j2 = lk nkk .. lk nkk + nkk - 1 (nkk = ceil(p / 4)), and all
+// KM loads of a component's run (addresses clamped into the row, KM >= nkk a
+// compile-time bound) are issued before its products, so that they are in
+// flight together.
 constexpr int KMAX = DMK_FAR_PMAX / 4;
 
-template <int M, bool ACC>
+template <int M, bool ACC, int KM>
 __global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32_t *__restrict__ bs,
                                                          const int32_t *__restrict__ perm,
                                                          const double *__restrict__ lag,
@@ -355,11 +359,12 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32
             W1[e] = i < nv ? lag[(int64_t)(p + j) * N + s0 + i] : 0.0;
         }
         wave_barrier();
-        // A fragments: l2 of point li at j2 = 4 kk + lk
-        double afr[KMAX];
+        // A fragments: l2 of point li at j2 = lk nkk + kk (each lane takes a
+        // contiguous run of j2, so that its values of U are adjacent in memory)
+        double afr[KM];
 #pragma unroll
-        for (int kk = 0; kk < KMAX; ++kk) {
-            const int k = 4 * kk + lk;
+        for (int kk = 0; kk < KM; ++kk) {
+            const int k = lk * nkk + kk;
             afr[kk] = (kk < nkk && k < p && li < nv) ? lag[(int64_t)(2 * p + k) * N + s0 + li] : 0.0;
         }
         double part[M][4];
@@ -376,13 +381,20 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32
 #pragma unroll
             for (int q = 0; q < M; ++q) d[q] = (dbl4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int kk = 0; kk < KMAX; ++kk) {
-                if (kk < nkk) {
-                    const int k = 4 * kk + lk;
+            for (int q = 0; q < M; ++q) {
+                // all loads of this component first (addresses clamped into the
+                // box, so none is conditional), then the products: the loads
+                // are in flight together instead of one per product
+                const double *Uq = U + q * tot + row;
+                double bv[KM];
 #pragma unroll
-                    for (int q = 0; q < M; ++q) {
-                        const double bv = (nok && k < p) ? U[q * tot + row + k] : 0.0;
-                        d[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[kk], bv, d[q], 0, 0, 0);
+                for (int kk = 0; kk < KM; ++kk) bv[kk] = Uq[min(lk * nkk + kk, p - 1)];
+#pragma unroll
+                for (int kk = 0; kk < KM; ++kk) {
+                    if (kk < nkk) {
+                        const int k = lk * nkk + kk;
+                        const double b = (nok && k < p) ? bv[kk] : 0.0;
+                        d[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[kk], b, d[q], 0, 0, 0);
                     }
                 }
             }
@@ -527,6 +539,29 @@ extern "C" int dmk_cheb_anterp(const dmk_grid *grid, const dmk_bins *bins, int p
     return DMK_OK;
 }
 
+namespace dmk {
+namespace {
+template <int KM>
+void launch_eval_mfma(int m, bool acc, dim3 grd, size_t lds, hipStream_t st, const ChebGeom &g, const int32_t *bsp,
+                      const int32_t *pm, const double *lag, const double *U, double *u)
+{
+    if (acc) {
+        switch (m) {
+        case 1: hipLaunchKernelGGL((k_cheb_eval_mfma<1, true, KM>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u); break;
+        case 3: hipLaunchKernelGGL((k_cheb_eval_mfma<3, true, KM>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u); break;
+        default: hipLaunchKernelGGL((k_cheb_eval_mfma<9, true, KM>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u); break;
+        }
+    } else {
+        switch (m) {
+        case 1: hipLaunchKernelGGL((k_cheb_eval_mfma<1, false, KM>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u); break;
+        case 3: hipLaunchKernelGGL((k_cheb_eval_mfma<3, false, KM>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u); break;
+        default: hipLaunchKernelGGL((k_cheb_eval_mfma<9, false, KM>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u); break;
+        }
+    }
+}
+}  // namespace
+}  // namespace dmk
+
 extern "C" int dmk_cheb_eval(const dmk_grid *grid, const dmk_bins *bins, int p, int m, const double *u_grid,
                              int accumulate, double *u, void *ws, size_t ws_bytes, hipStream_t stream)
 {
@@ -546,19 +581,12 @@ extern "C" int dmk_cheb_eval(const dmk_grid *grid, const dmk_bins *bins, int p, 
         const size_t elds = sizeof(double) * (size_t)(CB_T / WAVE) * 32 * p;
         for (g.wg0 = 0; g.wg0 < nbox; g.wg0 += MAX_WG) {
         const dim3 grd((unsigned)std::min(MAX_WG, nbox - g.wg0));
-        if (accumulate) {
-            switch (m) {
-            case 1: hipLaunchKernelGGL((k_cheb_eval_mfma<1, true>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
-            case 3: hipLaunchKernelGGL((k_cheb_eval_mfma<3, true>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
-            default: hipLaunchKernelGGL((k_cheb_eval_mfma<9, true>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
-            }
-        } else {
-            switch (m) {
-            case 1: hipLaunchKernelGGL((k_cheb_eval_mfma<1, false>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
-            case 3: hipLaunchKernelGGL((k_cheb_eval_mfma<3, false>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
-            default: hipLaunchKernelGGL((k_cheb_eval_mfma<9, false>), grd, dim3(CB_T), elds, stream, g, bsp, pm, lag, u_grid, u); break;
-            }
-        }
+        if ((p + 3) / 4 <= 4)
+            launch_eval_mfma<4>(m, accumulate != 0, grd, elds, stream, g, bsp, pm, lag, u_grid, u);
+        else if ((p + 3) / 4 <= 8)
+            launch_eval_mfma<8>(m, accumulate != 0, grd, elds, stream, g, bsp, pm, lag, u_grid, u);
+        else
+            launch_eval_mfma<KMAX>(m, accumulate != 0, grd, elds, stream, g, bsp, pm, lag, u_grid, u);
         }
         DMK_HIP_CHECK(hipGetLastError());
         return DMK_OK;
