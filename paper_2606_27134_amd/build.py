@@ -32,6 +32,11 @@ def flags() -> list:
         "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
         # packed FP32 VALU ops are kept out of the generated code on purpose
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # matrix-core products accumulate in ordinary vector registers (the
+        # accumulation-register form made the compiler copy loop-carried
+        # accumulators out and back on every iteration of the leaf-grid
+        # anterpolation: 15-28 % slower there, no change elsewhere)
+        "-mllvm", "-amdgpu-mfma-vgpr-form=1",
         "-I", os.path.join(ROOT, "include"),
     ]
 

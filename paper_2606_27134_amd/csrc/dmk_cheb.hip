@@ -229,17 +229,24 @@ __global__ __launch_bounds__(CB_T) void k_cheb_anterp_mfma(ChebGeom g, int ch, i
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int q = 0; q < M; ++q) d[t][q] = (dbl4){0.0, 0.0, 0.0, 0.0};
+        // straight-line body: every LDS read at an index clamped into the
+        // staged chunk, the unused values replaced by zero with selects (so
+        // that the accumulators stay in the matrix-core registers)
+        const int j0c = j0a < p ? j0a : 0;
         for (int k0 = 0; k0 < nc; k0 += 4) {
             const int k = k0 + lk;
             const bool kok = k < nc;
-            const double a = (kok && j0a < p) ? L0[k * p + j0a] : 0.0;
+            const int kc = kok ? k : 0;
+            const double a0 = L0[kc * p + j0c];
+            const double a = (kok && j0a < p) ? a0 : 0.0;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const bool ok = kok && nok[t];
-                const double w1 = ok ? L1[k * p + j1[t]] : 0.0;
+                const double w1 = L1[kc * p + j1[t]];
 #pragma unroll
                 for (int q = 0; q < M; ++q) {
-                    const double b = ok ? w1 * Cq[(q * ch + k) * p + j2[t]] : 0.0;
+                    const double c = Cq[(q * ch + kc) * p + j2[t]];
+                    const double b = ok ? w1 * c : 0.0;
                     d[t][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d[t][q], 0, 0, 0);
                 }
             }
