@@ -354,6 +354,8 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32
     const int nblock = (se - sb + 15) / 16;
     const int pp = p * p;
     const int nkk = (p + 3) / 4;
+    const int64_t g12 = g.G[1] * g.G[2];
+    const int64_t rb = ((b0 * p) * g.G[1] + b1 * p) * g.G[2] + b2 * p;  // the box's first grid value
     // this wavefront's copy of the block's l0 and l1: W0[j][i], W1[j][i]
     double *W0 = sm + (size_t)wv * 32 * p, *W1 = W0 + 16 * p;
     for (int blk = wv; blk < nblock; blk += CB_T / WAVE) {
@@ -379,11 +381,13 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32
         for (int q = 0; q < M; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r) part[q][r] = 0.0;
+        // this lane's B / D column n = n0 + li = j0 p + j1, advanced by 16 per
+        // tile without a division
+        int jn0 = li / p, jn1 = li - (li / p) * p;
         for (int n0 = 0; n0 < pp; n0 += 16) {
-            const int n = n0 + li;  // this lane's B / D column
-            const bool nok = n < pp;
-            const int j0 = nok ? n / p : 0, j1 = nok ? n - (n / p) * p : 0;
-            const int64_t row = ((b0 * p + j0) * g.G[1] + (b1 * p + j1)) * g.G[2] + b2 * p;
+            const bool nok = jn0 < p;
+            const int j0 = nok ? jn0 : 0, j1 = nok ? jn1 : 0;
+            const int64_t row = rb + (int64_t)j0 * g12 + (int64_t)j1 * g.G[2];
             dbl4 d[M];
 #pragma unroll
             for (int q = 0; q < M; ++q) d[q] = (dbl4){0.0, 0.0, 0.0, 0.0};
@@ -396,14 +400,11 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32
                 double bv[KM];
 #pragma unroll
                 for (int kk = 0; kk < KM; ++kk) bv[kk] = Uq[min(lk * nkk + kk, p - 1)];
+                // no select on B: A is zero for j2 >= p, and the columns past
+                // p^2 (finite values of the box) get the weight 0 below
 #pragma unroll
-                for (int kk = 0; kk < KM; ++kk) {
-                    if (kk < nkk) {
-                        const int k = lk * nkk + kk;
-                        const double b = (nok && k < p) ? bv[kk] : 0.0;
-                        d[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[kk], b, d[q], 0, 0, 0);
-                    }
-                }
+                for (int kk = 0; kk < KM; ++kk)
+                    if (kk < nkk) d[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[kk], bv[kk], d[q], 0, 0, 0);
             }
             // weights of the four D rows this lane holds (points 4 r + lk)
 #pragma unroll
@@ -412,6 +413,11 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32
                 const double w = nok ? W0[j0 * 16 + i] * W1[j1 * 16 + i] : 0.0;
 #pragma unroll
                 for (int q = 0; q < M; ++q) part[q][r] = fma(w, d[q][r], part[q][r]);
+            }
+            jn1 += 16;
+            while (jn1 >= p) {
+                jn1 -= p;
+                ++jn0;
             }
         }
         // sum over the 16 lanes of a row group, in a fixed order
