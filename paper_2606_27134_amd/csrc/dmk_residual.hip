@@ -36,6 +36,7 @@
 
 #include "dmk_internal.h"
 #include "erfcx_f32.h"
+#include "erfcx_f64.h"
 
 namespace dmk {
 
@@ -139,9 +140,6 @@ struct Smem {
 // scalar helpers
 __device__ inline float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double rsqrt_(double x) { return rsqrt(x); }
-__device__ inline float erfc_(float x) { return erfcf(x); }
-__device__ inline double erfc_(double x) { return erfc(x); }
-__device__ inline float expneg_(float x) { return __expf(-x); }
 __device__ inline double expneg_(double x) { return exp(-x); }
 
 
@@ -219,9 +217,22 @@ __device__ inline Rad<T> radial(T r2, T isig, T isig2, T kexp, const W &wc)
         R.phi = e * (float)INV_SQRT_PI;
         R.Phi = e * (u * pol);
     } else {
+        // the same for FP64: erfcx(t) = u S(x), u = 1/(1 + t/2), S a fitted
+        // Chebyshev series in x = A u + B (Clenshaw); branch-free, unlike a
+        // library erfc whose argument ranges split the lanes of a wavefront
         (void)kexp;
-        R.phi = expneg_(R.t2) * (T)INV_SQRT_PI;
-        R.Phi = erfc_(R.t);
+        const double e = expneg_(R.t2);
+        const double u = 1.0 / (1.0 + ERFCX_F64_SHIFT * R.t);
+        const double x = fma(ERFCX_F64_A, u, ERFCX_F64_B);
+        double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+        for (int k = ERFCX_F64_DEG; k >= 1; --k) {
+            const double b0 = fma(2.0 * x, b1, ERFCX_F64_C[k] - b2);
+            b2 = b1;
+            b1 = b0;
+        }
+        R.phi = e * INV_SQRT_PI;
+        R.Phi = e * (u * fma(x, b1, ERFCX_F64_C[0] - b2));
     }
     (void)wc;
     R.dphi = (T)-2 * R.t * R.phi;                  // phi' = -2 t phi
@@ -552,8 +563,6 @@ __device__ inline bool seg_sum(int tag, T *v)
     return last;
 }
 
-// inclusive prefix sum over the 64 lanes (shifts within rows, then carries
-// into the following rows)
 // lanes 0 .. n-1 of a wavefront as a bit mask (n clamped to [0, 64])
 __device__ inline uint64_t lanes_below(int n)
 {
@@ -567,6 +576,8 @@ __device__ inline bool lane_in(uint64_t m)
     return __builtin_amdgcn_inverse_ballot_w64(m);
 }
 
+// inclusive prefix sum over the 64 lanes (shifts within rows, then carries
+// into the following rows)
 __device__ inline int wave_incl_scan(int v)
 {
     v += dpp_int<DPP_ROW_SHR + 1, 0xf>(v, 0);
