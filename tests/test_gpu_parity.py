@@ -50,6 +50,10 @@ for k in KERNELS:
         (k, 2, (1.0, 1.0, 2.0), (6, 6, 12), 2500, "clustered"),
         (k, 1, (4.0, 1.0, 1.0), (20, 5, 5), 3000, "uniform"),
         (k, 0, (1.0, 1.0, 1.0), (7, 5, 6), 2000, "uniform"),
+        # sparse (under one point per box): stencil ranges of at most 64 slots,
+        # two targets per scan step
+        (k, 3, (1.0, 1.0, 1.0), (12, 12, 12), 1500, "uniform"),
+        (k, 1, (4.0, 1.0, 1.0), (40, 10, 10), 2000, "uniform"),
     ]
 
 
