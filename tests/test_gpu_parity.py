@@ -136,6 +136,7 @@ def test_edge_cases(prec):
     x[100:110] = x[110:120]
     x[200:300, 0] += 1.0
     x[300:400, 1] -= 2.0
+    x[400:405, 2] = 1.0  # exactly L on a periodic axis: the image at 0
     got, _ = run_fwd(w, prec, x=x)
     ref = oracle.residual(w.kernel, w.D, w.L, w.sigma, w.rc, x, w.rho)
     assert_parity(got, ref, TOL[prec], "faces/duplicates/outside")
@@ -147,6 +148,38 @@ def test_edge_cases(prec):
     w2.x = np.array([[0.01, 0.5, 0.5], [0.99, 0.52, 0.49]])
     got, _ = run_fwd(w2, prec)
     assert_parity(got, oracle_fwd(w2), TOL[prec], "pair across face")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_empty_input(prec):
+    """No points: binning, both pair kernels, autograd, the leaf grids and the
+    self term return empty (or zero) results without launching work."""
+    import torch
+    from paper_2606_27134_amd import far as F
+    x = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    b = R.tree_bin((1.0, 1.0, 1.0), 3, (4, 4, 4), x)
+    assert b.ntiles == 0
+    for k in KERNELS:
+        mi, mo = W.M_IN[k], W.M_OUT[k]
+        rho = torch.zeros((0, mi), dtype=torch.float64, device="cuda")
+        u = R.residual_eval(b, k, prec, 0.05, 0.25, rho)
+        assert tuple(u.shape) == (0, mo)
+        gr, gx = R.residual_backward(b, k, prec, 0.05, 0.25, rho, torch.zeros((0, mo), dtype=torch.float64,
+                                                                                device="cuda"))
+        assert tuple(gr.shape) == (0, mi) and tuple(gx.shape) == (0, 3)
+    spec = R.ResidualSpec(L=(1.0, 1.0, 1.0), D=3, n=(4, 4, 4), kernel="laplace", prec=prec, sigma=0.05, rc=0.25)
+    xr = x.clone().requires_grad_(True)
+    q = torch.zeros((0, 1), dtype=torch.float64, device="cuda", requires_grad=True)
+    u = R.dmk_residual(xr, q, spec)
+    u.sum().backward()
+    assert tuple(xr.grad.shape) == (0, 3) and tuple(q.grad.shape) == (0, 1)
+    rg = F.cheb_anterp(b, 6, torch.zeros((0, 1), dtype=torch.float64, device="cuda"))
+    assert tuple(rg.shape) == (1, 24, 24, 24) and float(rg.abs().max()) == 0.0
+    ue = F.cheb_eval(b, 6, torch.ones_like(rg))
+    assert tuple(ue.shape) == (0, 1)
+    us = F.self_term("laplace", 0.05, torch.zeros((0, 1), dtype=torch.float64, device="cuda"),
+                     torch.zeros((0, 1), dtype=torch.float64, device="cuda"))
+    assert tuple(us.shape) == (0, 1)
 
 
 def test_deterministic():
