@@ -63,22 +63,26 @@ struct FarWin {
 };
 
 // E_i[g][n] = exp(2 pi i n X_i[g] / L_i), X_i[g] / L_i = (b + 1/2 + cos((2j+1) pi/(2p))/2) / M_i
+// entries t = 0 .. sum_i G_i (K_i + 1) - 1: one per axis, grid point and
+// n >= 0, which also writes n's mirror -n (the complex conjugate)
 __device__ inline void far_table_entry(const FarGeom &g, double2 *__restrict__ E, int64_t t)
 {
     int ax = 0;
     int64_t r = t;
-    while (ax < 3 && r >= (int64_t)g.G[ax] * g.W[ax]) {
-        r -= (int64_t)g.G[ax] * g.W[ax];
+    while (ax < 3 && r >= (int64_t)g.G[ax] * (g.K[ax] + 1)) {
+        r -= (int64_t)g.G[ax] * (g.K[ax] + 1);
         ++ax;
     }
     if (ax >= 3) return;
-    const int gi = (int)(r / g.W[ax]);
-    const int n = (int)(r % g.W[ax]) - g.K[ax];
+    const int gi = (int)(r / (g.K[ax] + 1));
+    const int n = (int)(r % (g.K[ax] + 1));
     const int b = gi / g.p, j = gi % g.p;
     const double xr = ((double)b + 0.5 + 0.5 * cospi((double)(2 * j + 1) / (double)(2 * g.p))) / (double)g.M[ax];
     double s, c;
     sincospi(2.0 * (double)n * xr, &s, &c);
-    E[g.eoff[ax] + r] = make_double2(c, s);
+    double2 *row = E + g.eoff[ax] + (int64_t)gi * g.W[ax] + g.K[ax];  // entry n = 0 of this grid point
+    row[n] = make_double2(c, s);
+    if (n > 0) row[-n] = make_double2(c, -s);
 }
 
 // Y[a][o][c] = s * sum_i coef(i, o) X[a][i][c], coef(i, o) = E[i*si + o*so]
@@ -730,7 +734,7 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     {
         const int64_t Q = m_in_k(kernel), J = m_out_k(kernel);
         const int64_t G0 = g.G[0], G1 = g.G[1], W1 = g.W[1], W2 = g.W[2];
-        const int64_t ne = G0 * g.W[0] + G1 * W1 + (int64_t)g.G[2] * W2;
+        const int64_t ne = G0 * (g.K[0] + 1) + G1 * (g.K[1] + 1) + (int64_t)g.G[2] * (g.K[2] + 1);
         const int64_t no = (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1);
         const int64_t nm = (int64_t)g.W[0] * W1 * W2;
         if (!grid_fits((int64_t)nblk(ne, PREP_T) + (int64_t)nblk(no, PREP_T / WAVE), PREP_T) ||
@@ -752,7 +756,7 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     const double2 *E0 = E + g.eoff[0], *E1 = E + g.eoff[1], *E2 = E + g.eoff[2];
     const double invV = 1.0 / (g.L[0] * g.L[1] * g.L[2]);
 
-    const int64_t ne = (int64_t)G0 * W0 + (int64_t)G1 * W1 + (int64_t)G2 * W2;
+    const int64_t ne = (int64_t)G0 * (g.K[0] + 1) + (int64_t)G1 * (g.K[1] + 1) + (int64_t)G2 * (g.K[2] + 1);
     const int64_t no = (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1);
     const unsigned nbt = (unsigned)nblk(ne, PREP_T);
     hipLaunchKernelGGL(k_far_prep, dim3(nbt + (unsigned)nblk(no, PREP_T / WAVE)), dim3(PREP_T), 0, stream, g, w, E, PH, nbt);
