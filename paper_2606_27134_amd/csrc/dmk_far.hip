@@ -327,16 +327,21 @@ __global__ void k_mode_sum(const double2 *__restrict__ part, int64_t n, int nspl
         ((double2 *)Yv)[t] = make_double2(s * re, s * im);
 }
 
-// a Chebyshev series of the PSWF window in u = 2 t^2 - 1 (Clenshaw)
+// a Chebyshev series of the PSWF window in u = 2 t^2 - 1 (Clenshaw), over
+// all DMK_PSWF_MAXTERMS coefficients (zero past the window's nterms64, where
+// the recurrence stays exactly zero): a fixed length lets the coefficient
+// loads be issued ahead of the dependent steps
 __device__ inline double win_series(const FarWin &w, const double *cf, double t)
 {
     const double u = 2.0 * t * t - 1.0;
     double b1 = 0.0, b2 = 0.0;
-    for (int m = w.nterms - 1; m >= 1; --m) {
+#pragma unroll
+    for (int m = DMK_PSWF_MAXTERMS - 1; m >= 1; --m) {
         const double b0 = fma(2.0 * u, b1, cf[m] - b2);
         b2 = b1;
         b1 = b0;
     }
+    (void)w;
     return fma(u, b1, cf[0] - b2);
 }
 
@@ -717,9 +722,11 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
         w.pswf = 1;
         w.nterms = win->nterms64;
         w.c = win->c;
+        // the terms past nterms64 are zero here, so that the kernels' fixed-
+        // length recurrence equals the nterms64-term sum exactly
         for (int m = 0; m < DMK_PSWF_MAXTERMS; ++m) {
-            w.cheb[m] = win->cheb[0][m];
-            w.dcheb[m] = win->cheb[2][m];
+            w.cheb[m] = m < w.nterms ? win->cheb[0][m] : 0.0;
+            w.dcheb[m] = m < w.nterms ? win->cheb[2][m] : 0.0;
         }
         gauss_legendre01(w.gx, w.gw);
         // the quadrature grows with |k| sigma: bound it
