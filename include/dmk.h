@@ -61,7 +61,7 @@ typedef enum {
     DMK_EINVAL = 1,       /* bad argument (null pointer, size, enum)                 */
     DMK_EDOMAIN = 2,      /* non-finite coordinate, or free-axis coordinate outside [0,L) */
     DMK_ECUTOFF = 3,      /* rc not in (0, min h_i], or sigma <= 0                   */
-    DMK_EUNSUPPORTED = 4, /* combination not provided by this build                 */
+    DMK_EUNSUPPORTED = 4, /* combination not supported by the library               */
     DMK_EHIP = 5,         /* a HIP runtime call failed                               */
     DMK_ESIZE = 6         /* arena / workspace too small, or N / box count too large */
 } dmk_status;
