@@ -430,7 +430,8 @@ constexpr int FW_T = 256;
 
 template <int KERN>
 __global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, double sigma, const double2 *__restrict__ PH,
-                                                      const double2 *__restrict__ chi, double2 *__restrict__ Wt)
+                                                      const double2 *__restrict__ chi, const double2 *__restrict__ part,
+                                                      int nsplit, double chi_scale, double2 *__restrict__ Wt)
 {
     constexpr int MI = KERN == 0 ? 1 : (KERN == 2 ? 9 : 3);
     constexpr int MO = KERN == 0 ? 1 : 3;
@@ -453,7 +454,21 @@ __global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, double sigma, c
         const double Hh = ph / k2;
         const double Bh = (ph - 0.5 * q * dph) / (k2 * k2);
         double2 x[MI];
-        for (int c = 0; c < MI; ++c) x[c] = chi[c * nm + m];
+        if (nsplit > 1) {
+            // chi from the split partial results of its contraction, added in
+            // split order and scaled as k_mode_sum would
+            for (int c = 0; c < MI; ++c) {
+                double re = 0.0, im = 0.0;
+                for (int q = 0; q < nsplit; ++q) {
+                    const double2 v = part[(int64_t)q * MI * nm + c * nm + m];
+                    re += v.x;
+                    im += v.y;
+                }
+                x[c] = make_double2(chi_scale * re, chi_scale * im);
+            }
+        } else {
+            for (int c = 0; c < MI; ++c) x[c] = chi[c * nm + m];
+        }
         if constexpr (KERN == 0) {
             out[0] = make_double2(Hh * x[0].x, Hh * x[0].y);
         } else if constexpr (KERN == 1) {
@@ -624,30 +639,34 @@ inline bool mode_fits(int64_t A, int I, int O, int C)
     return mode_on_mfma(A, I, O, C) || mode_on_lds(A, I, O, C, false) || grid_fits(nblk(A * O * C, 256), 256);
 }
 
+// Returns 1, or (defer_sum) the number of split partial results left in part
+// for the consumer to add up (k_mode_sum's order and scale) instead of Y.
 template <bool RIN, bool ROUT, bool CONJ>
-void mode(const void *X, const double2 *E, int64_t A, int I, int O, int C, int64_t si, int64_t so, double s, void *Y,
-          double2 *part, hipStream_t st)
+int mode(const void *X, const double2 *E, int64_t A, int I, int O, int C, int64_t si, int64_t so, double s, void *Y,
+         double2 *part, hipStream_t st, bool defer_sum = false)
 {
     const int64_t n = A * O * C;
-    if (n <= 0) return;
+    if (n <= 0) return 1;
     if (mode_on_mfma(A, I, O, C)) {
         // 16 x 16 output tiles on the matrix cores, nsplit workgroups each
         const int64_t tiles = A * ((O + 15) / 16) * ((C + 15) / 16);
         const int ns = mode_nsplit(A, I, O, C);
         hipLaunchKernelGGL((k_mode_mfma<RIN, ROUT, CONJ>), dim3((unsigned)(tiles * ns)), dim3(MM_W * WAVE), 0, st, X,
                            E, A, I, O, C, si, so, s, ns, part, Y);
+        if (ns > 1 && defer_sum) return ns;
         if (ns > 1)
             hipLaunchKernelGGL((k_mode_sum<ROUT>), dim3((unsigned)nblk(n, 256)), dim3(256), 0, st, part, n, ns, s, Y);
-        return;
+        return 1;
     }
     if (mode_on_lds(A, I, O, C, RIN)) {
         const ModeBlock b = mode_block(A, I, O, C, RIN);
         hipLaunchKernelGGL((k_mode_lds<RIN, ROUT, CONJ>), dim3((unsigned)b.nwg), dim3(ML_T), b.lds, st, X, E, A, I, O,
                            C, si, so, s, b.ab, b.cb, Y);
-        return;
+        return 1;
     }
     hipLaunchKernelGGL((k_mode<RIN, ROUT, CONJ>), dim3((unsigned)nblk(n, 256)), dim3(256), 0, st, X, E, A, I, O, C, si, so, s,
                        Y);
+    return 1;
 }
 
 struct FarLayout {
@@ -770,15 +789,16 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     // structure factor (eq. (structurefac)): contract g2, g1, g0 with conj(E)
     mode<true, false, true>(rho_grid, E2, Q * G0 * G1, G2, W2, 1, W2, 1, 1.0, T1, PART, stream);
     mode<false, false, true>(T1, E1, Q * G0, G1, W1, W2, W1, 1, 1.0, T2, PART, stream);
-    mode<false, false, true>(T2, E0, Q, G0, W0, (int)((int64_t)W1 * W2), W0, 1, invV, CHI, PART, stream);
+    const int ns_chi = mode<false, false, true>(T2, E0, Q, G0, W0, (int)((int64_t)W1 * W2), W0, 1, invV, CHI, PART,
+                                                stream, true);
     // mode weights (with the window's transform per octant mode from k_far_prep)
     const int64_t nm = (int64_t)W0 * W1 * W2;
     const dim3 gw((unsigned)nblk(nm, FW_T));
     switch (kernel) {
-    case 0: hipLaunchKernelGGL(k_far_weights<0>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, WT); break;
-    case 1: hipLaunchKernelGGL(k_far_weights<1>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, WT); break;
-    case 2: hipLaunchKernelGGL(k_far_weights<2>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, WT); break;
-    default: hipLaunchKernelGGL(k_far_weights<3>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, WT); break;
+    case 0: hipLaunchKernelGGL(k_far_weights<0>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, PART, ns_chi, invV, WT); break;
+    case 1: hipLaunchKernelGGL(k_far_weights<1>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, PART, ns_chi, invV, WT); break;
+    case 2: hipLaunchKernelGGL(k_far_weights<2>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, PART, ns_chi, invV, WT); break;
+    default: hipLaunchKernelGGL(k_far_weights<3>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, PART, ns_chi, invV, WT); break;
     }
     // evaluation on the grids (eq. (eval_tensor)): contract n0, n1, n2 with E
     mode<false, false, false>(WT, E0, J, W0, G0, (int)((int64_t)W1 * W2), 1, W0, 1.0, V1, PART, stream);
