@@ -180,3 +180,20 @@ def test_largest_order(n, N):
     assert_parity(host(F.cheb_anterp(b, p, dev(rho))), OC.anterp(Lv, 3, n, p, x, rho), 1e-12, "anterp p=64")
     ug = rng.normal(size=(m, n[0] * p, n[1] * p, n[2] * p))
     assert_parity(host(F.cheb_eval(b, p, dev(ug))), OC.evaluate(Lv, 3, n, p, x, ug), 1e-12, "eval p=64")
+
+
+@pytest.mark.parametrize("m", [1, 3])
+def test_cheb_deterministic(m):
+    """Repeated anterpolation and evaluation (matrix-core paths, boxes of many
+    points) give bit-identical results."""
+    import torch
+    rng = np.random.default_rng(83)
+    x = rng.random((60000, 3))
+    b = R.tree_bin((1.0, 1.0, 1.0), 3, (6, 6, 6), dev(x))
+    q = dev(rng.normal(size=(60000, m)))
+    r1 = F.cheb_anterp(b, 20, q)
+    r2 = F.cheb_anterp(b, 20, q)
+    u1 = F.cheb_eval(b, 20, r1)
+    u2 = F.cheb_eval(b, 20, r1)
+    torch.cuda.synchronize()
+    assert torch.equal(r1, r2) and torch.equal(u1, u2)

@@ -127,3 +127,17 @@ def test_far_largest_order():
     ref = oracle.far_3p_grid("stresslet", Lv, M, p, K, 0.4, rho)
     got = host(F.far3p_eval(Lv, M, p, K, "stresslet", 0.4, dev(rho)))
     assert_parity(got, ref, 1e-12, "far p=64")
+
+
+def test_far_deterministic():
+    """Repeated calls give bit-identical grids: every sum (the split long-axis
+    contractions and their partials included) runs in a fixed order."""
+    import torch
+    rng = np.random.default_rng(81)
+    for Lv, M in (((1.0, 1.0, 1.0), (1, 1, 1)), ((32.0, 1.0, 1.0), (32, 1, 1))):
+        K = F.table_modes(29.0, Lv, 1.0)
+        rho = dev(rng.normal(size=(1, 38 * M[0], 38 * M[1], 38 * M[2])))
+        a = F.far3p_eval(Lv, M, 38, K, "laplace", 1.0, rho, pswf_c=29.0)
+        b = F.far3p_eval(Lv, M, 38, K, "laplace", 1.0, rho, pswf_c=29.0)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), Lv
