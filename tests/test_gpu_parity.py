@@ -228,3 +228,35 @@ def test_full_size_backward_sampled(name, kernel, prec):
     rr, rx = oracle.residual_vjp(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, G, targets=t)
     assert_parity(gr[t], rr, TOL[prec], "%s grad_rho %s" % (name, prec))
     assert_parity(gx[t], rx, TOL[prec], "%s grad_x %s" % (name, prec))
+
+
+# --------------------------------------------------------------------------
+# seeded random small cases: kernel, periodicity, box shape, tiling, size,
+# distribution and cutoff drawn at random (a 400-case sweep of this generator
+# found the largest rel l2 at 4.1e-13 FP64 and 6.2e-7 FP32C, stresslet)
+def _random_case(i):
+    rng = np.random.default_rng(9000 + i)
+    k = KERNELS[rng.integers(4)]
+    D = int(rng.integers(4))
+    n = tuple(int(v) for v in rng.integers(1, 14, 3))
+    h = float(rng.uniform(0.05, 0.2))
+    L = tuple(n[j] * h * float(rng.uniform(0.9, 1.1)) for j in range(3))
+    N = int(rng.integers(20, 3000))
+    dist = "clustered" if rng.random() < 0.3 else "uniform"
+    rcf = float(rng.choice([1.0, 1.0, 0.7, 0.4]))
+    return W.random_case(seed=int(rng.integers(1 << 30)), kernel=k, D=D, L=L, n=n, N=N, dist=dist, rc_frac=rcf)
+
+
+@pytest.mark.parametrize("i", range(40))
+def test_random_small_cases(i):
+    w = _random_case(i)
+    print("random", i, w.kernel, w.D, w.n, w.N, flush=True)
+    G = W.cotangent(w.seed, w.N, W.M_OUT[w.kernel])
+    ref = oracle_fwd(w)
+    rr, rx = oracle.residual_vjp(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, G)
+    for prec in ("fp64", "fp32c"):
+        got, _ = run_fwd(w, prec)
+        assert_parity(got, ref, TOL[prec], "random %d fwd %s" % (i, prec))
+        gr, gx = run_bwd(w, prec, G)
+        assert_parity(gr, rr, TOL[prec], "random %d grad_rho %s" % (i, prec))
+        assert_parity(gx, rx, TOL[prec], "random %d grad_x %s" % (i, prec))
