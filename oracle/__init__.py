@@ -242,17 +242,25 @@ def cheb_points(p):
 
 
 def top_grid(L, M, p):
-    """Per-axis coordinates of the root-level Chebyshev grids: the cell
-    [0,L0)x[0,L1)x[0,L2) tiled exactly by M0 x M1 x M2 cubes of side h0;
-    grid index g = b p + (j - 1) on each axis, coordinate (b + 1/2) h0 +
-    (h0/2) eta_j."""
+    """Per-axis coordinates of the root-level (or leaf-box) Chebyshev grids:
+    M0 x M1 x M2 cubes of side h0, grid index g = b p + (j - 1) on each axis,
+    coordinate (b + 1/2) h0 + (h0/2) eta_j.  Either the cubes tile the cell
+    [0,L0)x[0,L1)x[0,L2) exactly (h0 = L_i / M_i on every axis), or they are
+    the smallest union of cubes of side h0 = min_i L_i that covers it (Sec.
+    4.1.1, cube tiling): M_i = ceil(L_i / h0), the last cube along an axis
+    whose length is not a multiple of h0 cut by the cell's face."""
     L = np.asarray(L, dtype=np.float64)
     M = np.asarray(M, dtype=np.int64)
-    h0 = L / M
-    if not np.allclose(h0, h0[0], rtol=0, atol=1e-14 * h0[0]):
-        raise ValueError("the top cubes must tile the cell exactly")
+    h = L / M
+    if np.allclose(h, h[0], rtol=0, atol=1e-14 * h[0]):
+        h0 = float(h[0])
+    else:
+        h0 = float(L.min())
+        need = np.ceil(L / h0 * (1.0 - 1e-12)).astype(np.int64)
+        if not np.array_equal(M, need):
+            raise ValueError("the cubes neither tile the cell nor are the ceil(L_i / min L) cover: %s" % (need,))
     eta = cheb_points(p)
-    return [((np.arange(M[i])[:, None] + 0.5) * h0[i] + 0.5 * h0[i] * eta[None, :]).ravel() for i in range(3)]
+    return [((np.arange(M[i])[:, None] + 0.5) * h0 + 0.5 * h0 * eta[None, :]).ravel() for i in range(3)]
 
 
 def far_3p_grid(kernel, L, M, p, K, sigma, rho_grid, window=None):

@@ -104,3 +104,30 @@ def test_single_level_split_madelung(c, p, K, tol):
     u -= W.phi_at(0.0) * q / (2 * np.pi)
     expect = -M / (4 * np.pi * 0.5) * q[:, 0]
     assert np.abs(u[:, 0] - expect).max() <= tol * np.abs(expect).max()
+
+
+@pytest.mark.parametrize("Lv,M", [((1.0, 1.0, 1.5), (1, 1, 2)), ((1.25, 1.0, 2.6), (2, 1, 3))])
+def test_single_level_split_cut_cubes(Lv, M):
+    """A cell whose sides are not multiples of the shortest one: cubes of
+    side h0 = min L_i cover it (Sec. 4.1.1), the last along such an axis cut
+    by the cell's face.  Proxy strengths on the cubes' grids (the cubes as
+    free boxes), far field on those grids with the cell's wave numbers,
+    evaluation at the points, residual of support h0 on the periodic cell
+    and the self term reproduce the Gaussian Ewald total."""
+    rng = np.random.default_rng(31)
+    c, p = 14.5, 20
+    x = rng.random((24, 3)) * np.asarray(Lv)
+    q = rng.normal(size=(24, 1))
+    q -= q.mean()
+    h0 = min(Lv)
+    cover = tuple(m * h0 for m in M)
+    K = tuple(int(np.floor(c * L / (2 * np.pi * h0))) for L in Lv)
+    W = PswfWindow(c)
+    nu = h0 * (1 - 2.0 ** -30)
+    rg = cheb.anterp(cover, 0, M, p, x, q)
+    ug = oracle.far_3p_grid("laplace", Lv, M, p, K, nu, rg, window=W)
+    u = cheb.evaluate(cover, 0, M, p, x, ug)
+    u += oracle.residual("laplace", 3, Lv, nu, nu, x, q, window=W)
+    u -= W.phi_at(0.0) * q / (2 * np.pi * nu)
+    ref = oracle.full_split_3p("laplace", Lv, 0.08, x, q)
+    assert np.abs(u - ref).max() <= 1e-6 * np.abs(ref).max()
