@@ -213,8 +213,13 @@ const char *dmk_version(void);
  * evaluation of the far-field contribution, eqs. (structurefac),
  * (eval_tensor), wave numbers of eqs. (wavenumbers-3p-trunc), (kintmax)).
  *
- * The cell [0,L0)x[0,L1)x[0,L2) is tiled exactly by M0 x M1 x M2 top-level
- * cubes of side h0 = L_i / M_i (equal on the three axes).  Each cube carries a
+ * The cell [0,L0)x[0,L1)x[0,L2) is covered by M0 x M1 x M2 top-level cubes of
+ * side h0: either they tile it exactly (h0 = L_i / M_i, equal on the three
+ * axes), or they are the smallest cover by cubes of the shortest side
+ * (Sec. 4.1.1), h0 = min_i L_i and M_i = ceil(L_i / h0), the last cube along
+ * an axis whose length is not a multiple of h0 reaching past the cell's face
+ * (its proxy strengths then come from the points inside the cell, as for any
+ * cube; the wave numbers are those of the cell).  Each cube carries a
  * p x p x p grid of first-kind Chebyshev points, (h0/2) cos((2j-1) pi/(2p)),
  * j = 1..p, about its centre.  Along axis i the grid coordinates of all cubes
  * form one list of G_i = M_i p entries, index g = b p + (j - 1) (cube b),
@@ -237,8 +242,8 @@ const char *dmk_version(void);
  * (last index fastest).  `ws` is a device workspace of >= dmk_far3p_ws_bytes
  * bytes.  Asynchronous on `stream`; u_grid is fully overwritten.  Errors:
  * DMK_EINVAL (null pointer, p outside [1, DMK_FAR_PMAX], M_i outside
- * [1, DMK_FAR_MMAX], K_i outside [0, DMK_FAR_KMAX], cubes that do not tile the
- * cell), DMK_ECUTOFF (sigma0 <= 0), DMK_EUNSUPPORTED (bad window, or
+ * [1, DMK_FAR_MMAX], K_i outside [0, DMK_FAR_KMAX], M that is neither an exact
+ * tiling nor the cover above), DMK_ECUTOFF (sigma0 <= 0), DMK_EUNSUPPORTED (bad window, or
  * |k|max sigma0 > 4096 with the PSWF window), DMK_ESIZE (workspace too small,
  * or sizes for which one kernel launch would hold 2^32 or more work-items:
  * about 6.7e7 wave numbers with all n_i >= 0, 4.3e9 in all, or grid

@@ -49,6 +49,8 @@ constexpr int GL_N = 16;  // Gauss-Legendre nodes per quadrature panel
 struct FarGeom {
     int G[3], W[3], K[3], M[3], p;
     double L[3];
+    int cover;        // 1: cubes of side h0 = min L_i cover the cell, the last cut by a face
+    double hr[3];     // h0 / L_i (cover)
     int64_t eoff[3];  // offset of E_i in the table array (double2 entries)
 };
 
@@ -77,7 +79,9 @@ __device__ inline void far_table_entry(const FarGeom &g, double2 *__restrict__ E
     const int gi = (int)(r / (g.K[ax] + 1));
     const int n = (int)(r % (g.K[ax] + 1));
     const int b = gi / g.p, j = gi % g.p;
-    const double xr = ((double)b + 0.5 + 0.5 * cospi((double)(2 * j + 1) / (double)(2 * g.p))) / (double)g.M[ax];
+    // node coordinate over the cell length: ((b + 1/2) h0 + (h0/2) eta_j) / L_i
+    const double v = (double)b + 0.5 + 0.5 * cospi((double)(2 * j + 1) / (double)(2 * g.p));
+    const double xr = g.cover ? v * g.hr[ax] : v / (double)g.M[ax];
     double s, c;
     sincospi(2.0 * (double)n * xr, &s, &c);
     double2 *row = E + g.eoff[ax] + (int64_t)gi * g.W[ax] + g.K[ax];  // entry n = 0 of this grid point
@@ -516,16 +520,24 @@ int far_geom(const dmk_far_grid *fg, FarGeom &g)
 {
     if (!fg) return DMK_EINVAL;
     if (fg->p < 1 || fg->p > DMK_FAR_PMAX) return DMK_EINVAL;
-    double h0 = 0.0;
     for (int i = 0; i < 3; ++i) {
         if (!(fg->L[i] > 0.0) || !isfinite(fg->L[i])) return DMK_EINVAL;
         if (fg->M[i] < 1 || fg->M[i] > DMK_FAR_MMAX) return DMK_EINVAL;
         if (fg->K[i] < 0 || fg->K[i] > DMK_FAR_KMAX) return DMK_EINVAL;
-        const double h = fg->L[i] / fg->M[i];
-        if (i == 0) h0 = h;
-        if (fabs(h - h0) > 1e-12 * h0) return DMK_EINVAL;  // the top cubes must tile the cell
     }
+    // the top cubes either tile the cell (L_i / M_i equal) or are the smallest
+    // cover by cubes of the shortest side (Sec. 4.1.1): M_i = ceil(L_i / h0)
+    const double h0t = fg->L[0] / fg->M[0];
+    bool tiles = true;
+    for (int i = 1; i < 3; ++i)
+        if (fabs(fg->L[i] / fg->M[i] - h0t) > 1e-12 * h0t) tiles = false;
+    const double h0 = fmin(fg->L[0], fmin(fg->L[1], fg->L[2]));
+    if (!tiles)
+        for (int i = 0; i < 3; ++i)
+            if ((double)fg->M[i] != ceil(fg->L[i] / h0 * (1.0 - 1e-12))) return DMK_EINVAL;
     memset(&g, 0, sizeof(g));
+    g.cover = tiles ? 0 : 1;
+    for (int i = 0; i < 3; ++i) g.hr[i] = h0 / fg->L[i];
     g.p = fg->p;
     int64_t off = 0;
     for (int i = 0; i < 3; ++i) {

@@ -107,10 +107,17 @@ def self_term(kernel, sigma0: float, rho: torch.Tensor, u: torch.Tensor, pswf_c:
 def single_level_3p(x: torch.Tensor, rho: torch.Tensor, kernel, Lv, c: float, p: int, K=None,
                     prec="fp64") -> torch.Tensor:
     """Triply periodic sum with the PSWF split at the root level only: the
-    top cubes (side h0 = min L_i, tiling the cell exactly) are the leaf boxes.
+    top cubes (side h0 = min L_i) are the leaf boxes.
     u = residual (support nu) + far field (proxy strengths on the cubes'
     grids -> far field on the grids -> evaluation at the points) + self term.
     K defaults to the mode ranges of the parameter tables (table_modes).
+
+    When the cubes tile the cell exactly they are also the residual's boxes.
+    Otherwise (Sec. 4.1.1) M_i = ceil(L_i / h0) cubes cover it, the last one
+    along such an axis reaching past the cell's face: the residual then bins
+    the periodic cell in floor(L_i / h0) boxes per axis (sides >= h0), and the
+    proxy grids bin the same points on the cubes as free boxes of the cover;
+    the points must then lie in [0, L_i).
 
     The support is nu = h0 (1 - 2^-30), a hair inside the cube side: a
     point's own periodic images lie at distance exactly h0 along the axes of
@@ -118,16 +125,23 @@ def single_level_3p(x: torch.Tensor, rho: torch.Tensor, kernel, Lv, c: float, p:
     the tolerance) at the edge of their support, so such ties are kept
     clearly outside it instead of being left to the rounding of the image
     shift."""
+    import math
     from .residual import residual_eval, tree_bin
     h0 = min(float(v) for v in Lv)
     nu = h0 * (1.0 - 2.0 ** -30)
-    M = tuple(int(round(float(v) / h0)) for v in Lv)
+    M = tuple(int(math.ceil(float(v) / h0 * (1.0 - 1e-12))) for v in Lv)
+    exact = all(abs(float(v) / m - h0) <= 1e-12 * h0 for v, m in zip(Lv, M))
     if K is None:
         K = table_modes(c, Lv, h0)
-    bins = tree_bin(Lv, 3, M, x)
+    if exact:
+        bins = grid_bins = tree_bin(Lv, 3, M, x)
+    else:
+        nres = tuple(max(1, int(math.floor(float(v) / h0 * (1.0 + 1e-12)))) for v in Lv)
+        bins = tree_bin(Lv, 3, nres, x)
+        grid_bins = tree_bin(tuple(m * h0 for m in M), 0, M, x)
     u = residual_eval(bins, kernel, prec, nu, nu, rho, pswf_c=c)
-    ws = cheb_workspace(bins, p)
-    rg = cheb_anterp(bins, p, rho, ws=ws)
+    ws = cheb_workspace(grid_bins, p)
+    rg = cheb_anterp(grid_bins, p, rho, ws=ws)
     ug = far3p_eval(Lv, M, p, K, kernel, nu, rg, pswf_c=c)
-    cheb_eval(bins, p, ug, out=u, accumulate=True, ws=ws)
+    cheb_eval(grid_bins, p, ug, out=u, accumulate=True, ws=ws)
     return self_term(kernel, nu, rho, u, pswf_c=c)

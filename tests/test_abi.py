@@ -154,7 +154,13 @@ def test_far3p_host_argument_checks():
     # one launch), though only 5.4e8 in all
     wide = L.make_far_grid((1, 1, 1), (1, 1, 1), 2, (1024, 1024, 64))
     assert L.dmk_far3p_eval(wide, 0, 1.0, None, fake, fake, fake, 1 << 62, 0) == L.DMK_ESIZE
+    # cubes of the shortest side covering the cell, the last cut by its face
+    for Lv, M in (((1, 1, 1.5), (1, 1, 2)), ((1.25, 1, 2.6), (2, 1, 3)), ((2, 3.5, 2), (1, 2, 1))):
+        assert L.dmk_far3p_ws_bytes(L.make_far_grid(Lv, M, 8, (2, 2, 2)), 0) > 0
     for args in [((1, 1, 1), (1, 1, 2), 8, (2, 2, 2)),      # cubes do not tile the cell
+                 ((1, 1, 1.5), (1, 1, 1), 8, (2, 2, 2)),    # cubes do not cover it
+                 ((1, 1, 1.5), (1, 1, 3), 8, (2, 2, 2)),    # more cubes than the cover
+                 ((2, 3.5, 2), (1, 2, 2), 8, (2, 2, 2)),
                  ((1, 1, 1), (1, 1, 1), 0, (2, 2, 2)),      # p < 1
                  ((1, 1, 1), (1, 1, 1), L.FAR_PMAX + 1, (2, 2, 2)),
                  ((1, 1, 1), (1, 1, 1), 8, (2, -1, 2)),

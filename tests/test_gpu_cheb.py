@@ -104,14 +104,20 @@ def test_self_term(kernel, c):
 
 def _oracle_single_level(kernel, Lv, x, rho, c, p, K):
     # the same support as the library's single-level split: a hair inside the
-    # cube side, so that the points' own images (at exactly h0) lie outside
+    # cube side, so that the points' own images (at exactly h0) lie outside.
+    # Cubes of side h0 = min L_i; where they do not tile the cell they cover
+    # it (M_i = ceil(L_i / h0)) and are free boxes for the proxy grids.
     h0 = min(Lv)
     nu = h0 * (1.0 - 2.0 ** -30)
-    M = tuple(int(round(v / h0)) for v in Lv)
+    M = tuple(int(np.ceil(v / h0 * (1 - 1e-12))) for v in Lv)
+    if all(abs(v / m - h0) <= 1e-12 * h0 for v, m in zip(Lv, M)):
+        box, D = Lv, 3
+    else:
+        box, D = tuple(m * h0 for m in M), 0
     W = _w(c)
-    rg = OC.anterp(Lv, 3, M, p, x, rho)
+    rg = OC.anterp(box, D, M, p, x, rho)
     ug = oracle.far_3p_grid(kernel, Lv, M, p, K, nu, rg, window=W)
-    u = OC.evaluate(Lv, 3, M, p, x, ug)
+    u = OC.evaluate(box, D, M, p, x, ug)
     u += oracle.residual(kernel, 3, Lv, nu, nu, x, rho, window=W)
     if kernel in ("laplace", "stokeslet"):
         u -= W.phi_at(0.0) * rho / (2 * np.pi * nu)
@@ -132,6 +138,39 @@ def test_single_level_split_matches_oracle(kernel, geom):
     got = host(F.single_level_3p(dev(x), dev(rho), kernel, Lv, c, p))
     ref = _oracle_single_level(kernel, Lv, x, rho, c, p, K)
     assert_parity(got, ref, 1e-12, "single level %s" % kernel)
+
+
+@pytest.mark.parametrize("kernel", ["laplace", "stokeslet", "stresslet", "rotlet"])
+@pytest.mark.parametrize("Lv", [(1.0, 1.0, 1.5), (1.25, 1.0, 2.6)])
+def test_single_level_split_cut_cubes(kernel, Lv):
+    """Cells whose sides are not multiples of the shortest one (Sec. 4.1.1):
+    the library against the oracle's composition of the same steps."""
+    c, p = 14.5, 20
+    print("single level cut cubes", kernel, Lv, flush=True)
+    k = oracle.KERNELS[kernel]
+    rng = np.random.default_rng(95 + k)
+    N = 40
+    x = rng.random((N, 3)) * np.asarray(Lv)
+    rho = rng.normal(size=(N, oracle.M_IN[k]))
+    K = F.table_modes(c, Lv, min(Lv))
+    got = host(F.single_level_3p(dev(x), dev(rho), kernel, Lv, c, p))
+    ref = _oracle_single_level(kernel, Lv, x, rho, c, p, K)
+    assert_parity(got, ref, 1e-12, "single level cut %s" % kernel)
+
+
+@pytest.mark.parametrize("Lv", [(1.0, 1.0, 1.5), (1.25, 1.0, 2.6)])
+def test_single_level_cut_cubes_ewald(Lv):
+    """At the Laplace table row 1e-12 (c = 29, p = 38) the split on a cut
+    cover reproduces the Gaussian Ewald sum of neutral charges to 1e-12."""
+    rng = np.random.default_rng(31)
+    N = 24
+    x = rng.random((N, 3)) * np.asarray(Lv)
+    q = rng.normal(size=(N, 1))
+    q -= q.mean()
+    print("single level cut cubes ewald", Lv, flush=True)
+    u = host(F.single_level_3p(dev(x), dev(q), "laplace", Lv, 29.0, 38))
+    ref = oracle.full_split_3p("laplace", Lv, 0.08, x, q)
+    assert np.abs(u - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 def _golden(name, key):

@@ -54,6 +54,34 @@ def test_far_small_grids(kernel, geom, win):
     assert_parity(got, ref, 1e-12, "far %s %d %s" % (kernel, geom, win))
 
 
+# cells whose sides are not multiples of the shortest one: M_i = ceil(L_i / h0)
+# cubes of side h0 = min L_i, the last along such an axis cut by the face
+CUT = [
+    ((1.0, 1.0, 1.5), (1, 1, 2), 6, (2, 2, 3), 0.3),
+    ((1.25, 1.0, 2.6), (2, 1, 3), 5, (3, 1, 5), 0.35),
+    ((2.0, 3.5, 2.0), (1, 2, 1), 7, (2, 4, 2), 0.5),
+]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("geom", range(len(CUT)))
+@pytest.mark.parametrize("win", ["gauss", "pswf"])
+def test_far_cut_cubes(kernel, geom, win):
+    Lv, M, p, K, sg = CUT[geom]
+    print("far cut cubes", kernel, geom, win, flush=True)
+    k = oracle.KERNELS[kernel]
+    G = [m * p for m in M]
+    rng = np.random.default_rng(600 + 10 * geom + k)
+    rho = rng.normal(size=(oracle.M_IN[k], *G))
+    if win == "gauss":
+        c, sigma0 = None, sg
+    else:
+        c, sigma0 = 14.5, min(Lv)
+    ref = oracle.far_3p_grid(kernel, Lv, M, p, K, sigma0, rho, window=_w(c))
+    got = host(F.far3p_eval(Lv, M, p, K, kernel, sigma0, dev(rho), pswf_c=c))
+    assert_parity(got, ref, 1e-12, "far cut %s %d %s" % (kernel, geom, win))
+
+
 def test_far_cube_laplace_1e12_full():
     # Laplace table row 1e-12: c = 29, p = 38, N_per = 9; sigma0 = the cube side
     Lv, M, p = (1.0, 1.0, 1.0), (1, 1, 1), 38
