@@ -131,31 +131,53 @@ def _time_ms(fn, reps, warm=3):
     return ev[0].elapsed_time(ev[1]) / reps
 
 
+def _far_flops(M, p, K):
+    """Algorithmic flops of one root-level far field on an exact tiling of
+    M_i cubes, counting the form the library runs on each axis: the direct
+    contraction over the grid index, or (8 or more cubes, when it at least
+    halves the terms) the DFT over the cube index plus the fold over the
+    Chebyshev index.  Complex multiply-add 8, real by complex or real part
+    only 4."""
+    G = [m * p for m in M]
+    W = [2 * k + 1 for k in K]
+    fac = [8 <= m <= 512 and 2 * (m * m + w) <= w * m for m, w in zip(M, W)]
+    # (A, C) around each axis: axis 2 on [g0][g1][.], axis 1 on [g0][.][n2], axis 0 on [.][n1][n2]
+    cols = {2: (G[0] * G[1], 1), 1: (G[0], W[2]), 0: (1, W[1] * W[2])}
+    fl = 0.0
+    for ax, first_or_last in ((2, True), (1, False), (0, False)):
+        A, C = cols[ax]
+        half = 4.0 if first_or_last else 8.0  # real input (forward) / real part (evaluation)
+        if fac[ax]:
+            fl += 2 * (half * A * M[ax] * M[ax] * p * C + 8.0 * A * W[ax] * p * C)
+        else:
+            fl += 2 * half * A * G[ax] * W[ax] * C
+    return fl
+
+
 def far_leaf_leg(args):
     """Root-level far field (dmk_far3p_eval) and leaf-grid anterpolation /
     evaluation (dmk_cheb_anterp / dmk_cheb_eval), FP64, at the Laplace
     parameters for 1e-12 (c = 29, p = 38, N_per from the table).  Algorithmic
-    flops: the sum-factorized contractions (complex multiply-add 8, real by
-    complex 4, real part only 4) and, for the leaf grids, 4 per point and
-    node (anterpolation) and 2 (evaluation)."""
+    flops: the sum-factorized contractions (_far_flops) and, for the leaf
+    grids, 4 per point and node (anterpolation) and 2 (evaluation)."""
     import torch
     from paper_2606_27134_amd import _lib as L
     from paper_2606_27134_amd import far as F
     from paper_2606_27134_amd import residual as R
     out = {}
     rng = np.random.default_rng(2026)
-    for name, Lv, M in (("cube", (1.0, 1.0, 1.0), (1, 1, 1)), ("cuboid_32x1x1", (32.0, 1.0, 1.0), (32, 1, 1))):
+    for name, Lv, M in (("cube", (1.0, 1.0, 1.0), (1, 1, 1)), ("cuboid_32x1x1", (32.0, 1.0, 1.0), (32, 1, 1)),
+                        ("cuboid_1x1x32", (1.0, 1.0, 32.0), (1, 1, 32)),
+                        ("cuboid_128x1x1", (128.0, 1.0, 1.0), (128, 1, 1))):
         p, c = 38, 29.0
         K = F.table_modes(c, Lv, 1.0)
         G = [m * p for m in M]
-        Wn = [2 * k + 1 for k in K]
         rho = torch.as_tensor(rng.normal(size=(1, *G))).cuda()
         u = torch.empty_like(rho)
         nb = L.dmk_far3p_ws_bytes(L.make_far_grid(Lv, M, p, K), 0)
         ws = torch.empty(nb // 8 + 32, dtype=torch.float64, device="cuda")
         ms = _time_ms(lambda: F.far3p_eval(Lv, M, p, K, "laplace", 1.0, rho, pswf_c=c, out=u, ws=ws), 20)
-        fl = (4.0 * G[0] * G[1] * G[2] * Wn[2] + 8.0 * G[0] * G[1] * Wn[1] * Wn[2] + 8.0 * G[0] * Wn[0] * Wn[1] * Wn[2]
-              + 8.0 * Wn[0] * G[0] * Wn[1] * Wn[2] + 8.0 * G[0] * Wn[1] * G[1] * Wn[2] + 4.0 * G[0] * G[1] * Wn[2] * G[2])
+        fl = _far_flops(M, p, K)
         out["far3p_" + name] = {"L": list(Lv), "cubes": list(M), "p": p, "c": c, "K": list(K), "ms": ms,
                                 "gflops": fl / (ms * 1e-3) / 1e9, "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / 78.6}
     # leaf grids: 100k uniform points on an 8^3 tiling, p = 20 (the 1e-6 order)

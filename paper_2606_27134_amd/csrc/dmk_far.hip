@@ -52,6 +52,9 @@ struct FarGeom {
     int cover;        // 1: cubes of side h0 = min L_i cover the cell, the last cut by a face
     double hr[3];     // h0 / L_i (cover)
     int64_t eoff[3];  // offset of E_i in the table array (double2 entries)
+    int fac[3];       // 1: the sums along axis i factor through a length-M_i DFT over the cube index
+    int64_t doff[3];  // offset of D_i[b][r] = exp(2 pi i r b / M_i) in the table array (fac)
+    int64_t nE, nD;   // set-up entries of the phase tables (one per n >= 0) and of the D_i
 };
 
 struct FarWin {
@@ -69,6 +72,23 @@ struct FarWin {
 // n >= 0, which also writes n's mirror -n (the complex conjugate)
 __device__ inline void far_table_entry(const FarGeom &g, double2 *__restrict__ E, int64_t t)
 {
+    if (t >= g.nE) {
+        // DFT tables of the factored axes, the phase reduced mod M_i exactly
+        int64_t r = t - g.nE;
+        for (int ax = 0; ax < 3; ++ax) {
+            if (!g.fac[ax]) continue;
+            const int64_t m = g.M[ax];
+            if (r < m * m) {
+                const int64_t q = ((r / m) * (r % m)) % m;
+                double s, c;
+                sincospi(2.0 * (double)q / (double)m, &s, &c);
+                E[g.doff[ax] + r] = make_double2(c, s);
+                return;
+            }
+            r -= m * m;
+        }
+        return;
+    }
     int ax = 0;
     int64_t r = t;
     while (ax < 3 && r >= (int64_t)g.G[ax] * (g.K[ax] + 1)) {
@@ -331,6 +351,57 @@ __global__ void k_mode_sum(const double2 *__restrict__ part, int64_t n, int nspl
         ((double2 *)Yv)[t] = make_double2(s * re, s * im);
 }
 
+// Long axes of an exact tiling: the grid index is g = b p + j and the phase
+// factors as E[b p + j][n] = w^(n b) F[j][n], w = exp(2 pi i / M), F the
+// rows of the first cube (b = 0).  A sum over g is then a length-M DFT over
+// the cube index b (a mode product with D[b][r] = w^(r b)) followed by a sum
+// over j for each n, which only reads the DFT at r = n mod M (k_fold); the
+// evaluation runs the transposed steps (k_unfold, then the DFT).
+
+// Y[a][n][c] = s * sum_j F(j, n) Z[a][n mod M][j][c], n = -K..K, F conjugated when CONJ
+template <bool CONJ>
+__global__ void k_fold(const double2 *__restrict__ Z, const double2 *__restrict__ E, int64_t A, int M, int p, int W,
+                       int K, int C, double s, double2 *__restrict__ Y)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= A * W * C) return;
+    const int c = (int)(t % C);
+    const int o = (int)((t / C) % W);
+    const int64_t a = t / ((int64_t)C * W);
+    const int r = ((o - K) % M + M) % M;
+    const double2 *z = Z + ((a * M + r) * p) * (int64_t)C + c;
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < p; ++j) {
+        const double2 e = E[(int64_t)j * W + o];
+        const double ei = CONJ ? -e.y : e.y;
+        const double2 x = z[(int64_t)j * C];
+        re = fma(e.x, x.x, fma(-ei, x.y, re));
+        im = fma(e.x, x.y, fma(ei, x.x, im));
+    }
+    Y[t] = make_double2(s * re, s * im);
+}
+
+// U[a][r][j][c] = sum over n = -K..K with n = r (mod M) of F(j, n) X[a][n][c]
+__global__ void k_unfold(const double2 *__restrict__ X, const double2 *__restrict__ E, int64_t A, int M, int p, int W,
+                         int K, int C, double2 *__restrict__ U)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= A * M * p * C) return;
+    const int c = (int)(t % C);
+    const int j = (int)((t / C) % p);
+    const int r = (int)((t / ((int64_t)C * p)) % M);
+    const int64_t a = t / ((int64_t)C * p * M);
+    double re = 0.0, im = 0.0;
+    // o = n + K runs over the class of r: the first o >= 0 with o = r + K (mod M)
+    for (int o = (r + K) % M; o < W; o += M) {
+        const double2 e = E[(int64_t)j * W + o];
+        const double2 x = X[(a * W + o) * C + c];
+        re = fma(e.x, x.x, fma(-e.y, x.y, re));
+        im = fma(e.x, x.y, fma(e.y, x.x, im));
+    }
+    U[t] = make_double2(re, im);
+}
+
 // a Chebyshev series of the PSWF window in u = 2 t^2 - 1 (Clenshaw), over
 // all DMK_PSWF_MAXTERMS coefficients (zero past the window's nterms64, where
 // the recurrence stays exactly zero): a fixed length lets the coefficient
@@ -548,6 +619,19 @@ int far_geom(const dmk_far_grid *fg, FarGeom &g)
         g.W[i] = 2 * fg->K[i] + 1;
         g.eoff[i] = off;
         off += (int64_t)g.G[i] * g.W[i];
+        g.nE += (int64_t)g.G[i] * (g.K[i] + 1);
+    }
+    // the cube-index DFT where it at least halves the terms of the direct
+    // sums, (M^2 + W) p against W M p per output column, on the cube grid of
+    // an exact tiling (the cubes' centres at multiples of L_i / M_i)
+    for (int i = 0; i < 3; ++i) {
+        const int64_t m = g.M[i], w = g.W[i];
+        g.fac[i] = !g.cover && m >= 8 && m <= 512 && 2 * (m * m + w) <= w * m;
+        if (g.fac[i]) {
+            g.doff[i] = off;
+            off += m * m;
+            g.nD += m * m;
+        }
     }
     return DMK_OK;
 }
@@ -681,8 +765,87 @@ int mode(const void *X, const double2 *E, int64_t A, int I, int O, int C, int64_
     return 1;
 }
 
+// The three contractions of each side, axis ax: A leading and C trailing
+// columns around the contracted index, input Q (forward) or J (evaluation)
+// components.
+struct AxisCols {
+    int64_t A;
+    int C;
+};
+
+inline AxisCols axis_cols(const FarGeom &g, int ax, int64_t comps)
+{
+    // forward: axis 2 on [q][g0][g1][g2], axis 1 on [q][g0][g1][n2], axis 0 on [q][g0][n1][n2];
+    // evaluation: axis 0 on [j][n0][n1][n2], axis 1 on [j][g0][n1][n2], axis 2 on [j][g0][g1][n2]
+    const int64_t G0 = g.G[0], G1 = g.G[1];
+    const int W1 = g.W[1], W2 = g.W[2];
+    if (ax == 2) return {comps * G0 * G1, 1};
+    if (ax == 1) return {comps * G0, W2};
+    return {comps, W1 * W2};
+}
+
+// Launch sizes of one contraction (direct, or the DFT and the fold / unfold)
+inline bool axis_fits(const FarGeom &g, int ax, int64_t comps, bool fwd)
+{
+    const AxisCols ac = axis_cols(g, ax, comps);
+    const int G = g.G[ax], W = g.W[ax], M = g.M[ax];
+    if (!g.fac[ax]) return fwd ? mode_fits(ac.A, G, W, ac.C) : mode_fits(ac.A, W, G, ac.C);
+    const int64_t pc = (int64_t)g.p * ac.C;
+    if (pc > INT32_MAX) return false;
+    return mode_fits(ac.A, M, M, (int)pc) && grid_fits(nblk(ac.A * W * ac.C, 256), 256) &&
+           grid_fits(nblk(ac.A * G * ac.C, 256), 256);
+}
+
+// doubles2 of split partials and of the DFT's output a contraction needs
+inline int64_t axis_part(const FarGeom &g, int ax, int64_t comps, bool fwd)
+{
+    const AxisCols ac = axis_cols(g, ax, comps);
+    if (!g.fac[ax]) return fwd ? mode_part(ac.A, g.G[ax], g.W[ax], ac.C) : mode_part(ac.A, g.W[ax], g.G[ax], ac.C);
+    return mode_part(ac.A, g.M[ax], g.M[ax], g.p * ac.C);
+}
+
+inline int64_t axis_z(const FarGeom &g, int ax, int64_t comps)
+{
+    const AxisCols ac = axis_cols(g, ax, comps);
+    return g.fac[ax] ? ac.A * g.G[ax] * ac.C : 0;
+}
+
+// One contraction of the structure factor along axis ax (conj(E)), scaled by s.
+// Returns mode()'s count of deferred partial results (1 when written to Y).
+template <bool RIN>
+int contract_fwd(const FarGeom &g, int ax, int64_t comps, const void *X, const double2 *E, double s, double2 *Y,
+                 double2 *Z, double2 *part, hipStream_t st, bool defer_sum = false)
+{
+    const AxisCols ac = axis_cols(g, ax, comps);
+    const int W = g.W[ax];
+    if (!g.fac[ax])
+        return mode<RIN, false, true>(X, E + g.eoff[ax], ac.A, g.G[ax], W, ac.C, W, 1, s, Y, part, st, defer_sum);
+    const int M = g.M[ax];
+    mode<RIN, false, true>(X, E + g.doff[ax], ac.A, M, M, g.p * ac.C, M, 1, 1.0, Z, part, st);
+    hipLaunchKernelGGL(k_fold<true>, dim3((unsigned)nblk(ac.A * W * ac.C, 256)), dim3(256), 0, st, Z, E + g.eoff[ax],
+                       ac.A, M, g.p, W, g.K[ax], ac.C, s, Y);
+    return 1;
+}
+
+// One contraction of the evaluation along axis ax (E); ROUT: real part only
+template <bool ROUT>
+void contract_eval(const FarGeom &g, int ax, int64_t comps, const double2 *X, const double2 *E, void *Y, double2 *Z,
+                   double2 *part, hipStream_t st)
+{
+    const AxisCols ac = axis_cols(g, ax, comps);
+    const int W = g.W[ax];
+    if (!g.fac[ax]) {
+        mode<false, ROUT, false>(X, E + g.eoff[ax], ac.A, W, g.G[ax], ac.C, 1, W, 1.0, Y, part, st);
+        return;
+    }
+    const int M = g.M[ax];
+    hipLaunchKernelGGL(k_unfold, dim3((unsigned)nblk(ac.A * g.G[ax] * ac.C, 256)), dim3(256), 0, st, X,
+                       E + g.eoff[ax], ac.A, M, g.p, W, g.K[ax], ac.C, Z);
+    mode<false, ROUT, false>(Z, E + g.doff[ax], ac.A, M, M, g.p * ac.C, M, 1, 1.0, Y, part, st);
+}
+
 struct FarLayout {
-    int64_t E, T1, T2, CHI, WT, V1, V2, PH, PART, total;  // byte offsets
+    int64_t E, T1, T2, CHI, WT, V1, V2, PH, PART, Z, total;  // byte offsets
 };
 
 FarLayout far_layout(const FarGeom &g, int kernel)
@@ -694,7 +857,7 @@ FarLayout far_layout(const FarGeom &g, int kernel)
     int64_t off = 0;
     const int64_t z = (int64_t)sizeof(double2);
     l.E = off;
-    off = al(off + z * ((int64_t)g.G[0] * W0 + (int64_t)g.G[1] * W1 + (int64_t)g.G[2] * W2));
+    off = al(off + z * ((int64_t)g.G[0] * W0 + (int64_t)g.G[1] * W1 + (int64_t)g.G[2] * W2 + g.nD));
     l.T1 = off;
     off = al(off + z * Q * G0 * G1 * W2);
     l.T2 = off;
@@ -710,14 +873,16 @@ FarLayout far_layout(const FarGeom &g, int kernel)
     l.PH = off;
     off = al(off + z * (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1));
     // partial results of the split contractions (the six of dmk_far3p_eval)
-    const int64_t G2 = g.G[2];
-    int64_t np = 0;
-    for (const int64_t v : {mode_part(Q * G0 * G1, (int)G2, (int)W2, 1), mode_part(Q * G0, (int)G1, (int)W1, (int)W2),
-                            mode_part(Q, (int)G0, (int)W0, (int)(W1 * W2)), mode_part(J, (int)W0, (int)G0, (int)(W1 * W2)),
-                            mode_part(J * G0, (int)W1, (int)G1, (int)W2), mode_part(J * G0 * G1, (int)W2, (int)G2, 1)})
-        np = std::max(np, v);
+    // and the cube-index DFTs' outputs
+    int64_t np = 0, nz = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        np = std::max({np, axis_part(g, ax, Q, true), axis_part(g, ax, J, false)});
+        nz = std::max({nz, axis_z(g, ax, Q), axis_z(g, ax, J)});
+    }
     l.PART = off;
     off = al(off + z * np);
+    l.Z = off;
+    off = al(off + z * nz);
     l.total = off;
     return l;
 }
@@ -771,16 +936,15 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     // launch sizes: every dispatch of the evaluation below holds fewer than 2^32 work-items
     {
         const int64_t Q = m_in_k(kernel), J = m_out_k(kernel);
-        const int64_t G0 = g.G[0], G1 = g.G[1], W1 = g.W[1], W2 = g.W[2];
-        const int64_t ne = G0 * (g.K[0] + 1) + G1 * (g.K[1] + 1) + (int64_t)g.G[2] * (g.K[2] + 1);
+        const int64_t W1 = g.W[1], W2 = g.W[2];
+        const int64_t ne = g.nE + g.nD;
         const int64_t no = (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1);
         const int64_t nm = (int64_t)g.W[0] * W1 * W2;
         if (!grid_fits((int64_t)nblk(ne, PREP_T) + (int64_t)nblk(no, PREP_T / WAVE), PREP_T) ||
-            !grid_fits(nblk(nm, FW_T), FW_T) || !mode_fits(Q * G0 * G1, g.G[2], g.W[2], 1) ||
-            !mode_fits(Q * G0, g.G[1], g.W[1], g.W[2]) || !mode_fits(Q, g.G[0], g.W[0], (int)(W1 * W2)) ||
-            !mode_fits(J, g.W[0], g.G[0], (int)(W1 * W2)) || !mode_fits(J * G0, g.W[1], g.G[1], g.W[2]) ||
-            !mode_fits(J * G0 * G1, g.W[2], g.G[2], 1))
+            !grid_fits(nblk(nm, FW_T), FW_T))
             return DMK_ESIZE;
+        for (int ax = 0; ax < 3; ++ax)
+            if (!axis_fits(g, ax, Q, true) || !axis_fits(g, ax, J, false)) return DMK_ESIZE;
     }
     const FarLayout l = far_layout(g, kernel);
     if (ws_bytes < (size_t)l.total) return DMK_ESIZE;
@@ -788,21 +952,19 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     double2 *E = (double2 *)(b + l.E);
     double2 *T1 = (double2 *)(b + l.T1), *T2 = (double2 *)(b + l.T2), *CHI = (double2 *)(b + l.CHI);
     double2 *WT = (double2 *)(b + l.WT), *V1 = (double2 *)(b + l.V1), *V2 = (double2 *)(b + l.V2);
-    double2 *PH = (double2 *)(b + l.PH), *PART = (double2 *)(b + l.PART);
+    double2 *PH = (double2 *)(b + l.PH), *PART = (double2 *)(b + l.PART), *Z = (double2 *)(b + l.Z);
     const int64_t Q = m_in_k(kernel), J = m_out_k(kernel);
-    const int G0 = g.G[0], G1 = g.G[1], G2 = g.G[2], W0 = g.W[0], W1 = g.W[1], W2 = g.W[2];
-    const double2 *E0 = E + g.eoff[0], *E1 = E + g.eoff[1], *E2 = E + g.eoff[2];
+    const int W0 = g.W[0], W1 = g.W[1], W2 = g.W[2];
     const double invV = 1.0 / (g.L[0] * g.L[1] * g.L[2]);
 
-    const int64_t ne = (int64_t)G0 * (g.K[0] + 1) + (int64_t)G1 * (g.K[1] + 1) + (int64_t)G2 * (g.K[2] + 1);
+    const int64_t ne = g.nE + g.nD;
     const int64_t no = (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1);
     const unsigned nbt = (unsigned)nblk(ne, PREP_T);
     hipLaunchKernelGGL(k_far_prep, dim3(nbt + (unsigned)nblk(no, PREP_T / WAVE)), dim3(PREP_T), 0, stream, g, w, E, PH, nbt);
     // structure factor (eq. (structurefac)): contract g2, g1, g0 with conj(E)
-    mode<true, false, true>(rho_grid, E2, Q * G0 * G1, G2, W2, 1, W2, 1, 1.0, T1, PART, stream);
-    mode<false, false, true>(T1, E1, Q * G0, G1, W1, W2, W1, 1, 1.0, T2, PART, stream);
-    const int ns_chi = mode<false, false, true>(T2, E0, Q, G0, W0, (int)((int64_t)W1 * W2), W0, 1, invV, CHI, PART,
-                                                stream, true);
+    contract_fwd<true>(g, 2, Q, rho_grid, E, 1.0, T1, Z, PART, stream);
+    contract_fwd<false>(g, 1, Q, T1, E, 1.0, T2, Z, PART, stream);
+    const int ns_chi = contract_fwd<false>(g, 0, Q, T2, E, invV, CHI, Z, PART, stream, true);
     // mode weights (with the window's transform per octant mode from k_far_prep)
     const int64_t nm = (int64_t)W0 * W1 * W2;
     const dim3 gw((unsigned)nblk(nm, FW_T));
@@ -813,9 +975,9 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     default: hipLaunchKernelGGL(k_far_weights<3>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, PART, ns_chi, invV, WT); break;
     }
     // evaluation on the grids (eq. (eval_tensor)): contract n0, n1, n2 with E
-    mode<false, false, false>(WT, E0, J, W0, G0, (int)((int64_t)W1 * W2), 1, W0, 1.0, V1, PART, stream);
-    mode<false, false, false>(V1, E1, J * G0, W1, G1, W2, 1, W1, 1.0, V2, PART, stream);
-    mode<false, true, false>(V2, E2, J * G0 * G1, W2, G2, 1, 1, W2, 1.0, u_grid, PART, stream);
+    contract_eval<false>(g, 0, J, WT, E, V1, Z, PART, stream);
+    contract_eval<false>(g, 1, J, V1, E, V2, Z, PART, stream);
+    contract_eval<true>(g, 2, J, V2, E, u_grid, Z, PART, stream);
     DMK_HIP_CHECK(hipGetLastError());
     return DMK_OK;
 }

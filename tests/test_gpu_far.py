@@ -32,6 +32,10 @@ GEOMS = [
     ((2.0, 1.0, 3.0), (2, 1, 3), 5, (3, 1, 4), 0.4),
     ((1.0, 1.0, 1.0), (1, 1, 1), 12, (1, 1, 1), 0.5),
     ((8.0, 1.0, 1.0), (8, 1, 1), 6, (20, 2, 2), 0.35),  # long-axis contractions on the matrix cores
+    # long axes of 8 or more cubes: the sums over them factor through a DFT over the cube index
+    ((1.0, 12.0, 1.0), (1, 12, 1), 5, (2, 30, 2), 0.35),
+    ((1.0, 1.0, 16.0), (1, 1, 16), 4, (1, 1, 40), 0.3),
+    ((10.0, 1.0, 12.0), (10, 1, 12), 3, (25, 1, 30), 0.45),
 ]
 
 
@@ -129,6 +133,20 @@ def test_far_elongated_cell_sampled(kernel, c, p):
     print("far elongated", kernel, K, flush=True)
     got, ref = _sampled(kernel, Lv, M, p, K, c, 1500, 128, 79)
     assert_parity(got, ref, 1e-12, "far elongated %s" % kernel)
+
+
+@pytest.mark.parametrize("kernel,axis", [("laplace", 2), ("stokeslet", 1), ("rotlet", 2)])
+def test_far_elongated_other_axes_sampled(kernel, axis):
+    # the 32-cube cuboid along axis 1 or 2 (the contraction over the
+    # innermost grid index, or the middle one, on a DFT of length 32)
+    c, p = (29.0, 38) if kernel == "laplace" else (32.46, 44)
+    Lv, M = [1.0, 1.0, 1.0], [1, 1, 1]
+    Lv[axis], M[axis] = 32.0, 32
+    Lv, M = tuple(Lv), tuple(M)
+    K = F.table_modes(c, Lv, 1.0)
+    print("far elongated axis", axis, kernel, K, flush=True)
+    got, ref = _sampled(kernel, Lv, M, p, K, c, 1500, 128, 84 + axis)
+    assert_parity(got, ref, 1e-12, "far elongated axis %d %s" % (axis, kernel))
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
