@@ -54,6 +54,7 @@ struct FarGeom {
     int64_t eoff[3];  // offset of E_i in the table array (double2 entries)
     int fac[3];       // 1: the sums along axis i factor through a length-M_i DFT over the cube index
     int64_t doff[3];  // offset of D_i[b][r] = exp(2 pi i r b / M_i) in the table array (fac)
+    int64_t foff[3];  // offset of FT_i[n][j] = E_i[j][n], j < p: the first cube's rows transposed (fac)
     int64_t nE, nD;   // set-up entries of the phase tables (one per n >= 0) and of the D_i
 };
 
@@ -107,6 +108,11 @@ __device__ inline void far_table_entry(const FarGeom &g, double2 *__restrict__ E
     double2 *row = E + g.eoff[ax] + (int64_t)gi * g.W[ax] + g.K[ax];  // entry n = 0 of this grid point
     row[n] = make_double2(c, s);
     if (n > 0) row[-n] = make_double2(c, -s);
+    if (g.fac[ax] && gi < g.p) {
+        double2 *ft = E + g.foff[ax] + (int64_t)(g.K[ax] + n) * g.p + gi;
+        ft[0] = make_double2(c, s);
+        if (n > 0) ft[-(int64_t)2 * n * g.p] = make_double2(c, -s);
+    }
 }
 
 // Y[a][o][c] = s * sum_i coef(i, o) X[a][i][c], coef(i, o) = E[i*si + o*so]
@@ -381,8 +387,40 @@ __global__ void k_fold(const double2 *__restrict__ Z, const double2 *__restrict_
     Y[t] = make_double2(s * re, s * im);
 }
 
-// U[a][r][j][c] = sum over n = -K..K with n = r (mod M) of F(j, n) X[a][n][c]
-__global__ void k_unfold(const double2 *__restrict__ X, const double2 *__restrict__ E, int64_t A, int M, int p, int W,
+// k_fold for one column (C = 1), one workgroup per a: the slice Z[a] (M p
+// values, read by about W / M outputs each) is staged in LDS with coalesced
+// loads; same terms and order as k_fold
+constexpr int FL_T = 256;
+constexpr int FL_LDS = 48 * 1024;
+
+template <bool CONJ>
+__global__ __launch_bounds__(FL_T) void k_fold_lds(const double2 *__restrict__ Z, const double2 *__restrict__ E, int M,
+                                                   int p, int W, int K, double s, double2 *__restrict__ Y)
+{
+    extern __shared__ double2 zs[];
+    const int64_t a = blockIdx.x;
+    const int n = M * p;
+    const double2 *za = Z + a * n;
+    for (int i = threadIdx.x; i < n; i += FL_T) zs[i] = za[i];
+    __syncthreads();
+    for (int o = threadIdx.x; o < W; o += FL_T) {
+        const int r = ((o - K) % M + M) % M;
+        const double2 *z = zs + r * p;
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < p; ++j) {
+            const double2 e = E[(int64_t)j * W + o];
+            const double ei = CONJ ? -e.y : e.y;
+            const double2 x = z[j];
+            re = fma(e.x, x.x, fma(-ei, x.y, re));
+            im = fma(e.x, x.y, fma(ei, x.x, im));
+        }
+        Y[a * W + o] = make_double2(s * re, s * im);
+    }
+}
+
+// U[a][r][j][c] = sum over n = -K..K with n = r (mod M) of F(j, n) X[a][n][c],
+// F read from its transpose FT[n][j] (coalesced across j)
+__global__ void k_unfold(const double2 *__restrict__ X, const double2 *__restrict__ FT, int64_t A, int M, int p, int W,
                          int K, int C, double2 *__restrict__ U)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -394,7 +432,7 @@ __global__ void k_unfold(const double2 *__restrict__ X, const double2 *__restric
     double re = 0.0, im = 0.0;
     // o = n + K runs over the class of r: the first o >= 0 with o = r + K (mod M)
     for (int o = (r + K) % M; o < W; o += M) {
-        const double2 e = E[(int64_t)j * W + o];
+        const double2 e = FT[(int64_t)o * p + j];
         const double2 x = X[(a * W + o) * C + c];
         re = fma(e.x, x.x, fma(-e.y, x.y, re));
         im = fma(e.x, x.y, fma(e.y, x.x, im));
@@ -633,6 +671,11 @@ int far_geom(const dmk_far_grid *fg, FarGeom &g)
             g.nD += m * m;
         }
     }
+    for (int i = 0; i < 3; ++i)
+        if (g.fac[i]) {
+            g.foff[i] = off;
+            off += (int64_t)g.p * g.W[i];
+        }
     return DMK_OK;
 }
 
@@ -810,6 +853,12 @@ inline int64_t axis_z(const FarGeom &g, int ax, int64_t comps)
     return g.fac[ax] ? ac.A * g.G[ax] * ac.C : 0;
 }
 
+// the fold of one column (C = 1) stages Z[a] in LDS when it fits
+inline bool fold_on_lds(const FarGeom &g, int ax, const AxisCols &ac)
+{
+    return ac.C == 1 && (int64_t)g.M[ax] * g.p * (int64_t)sizeof(double2) <= FL_LDS && grid_fits(ac.A, FL_T);
+}
+
 // One contraction of the structure factor along axis ax (conj(E)), scaled by s.
 // Returns mode()'s count of deferred partial results (1 when written to Y).
 template <bool RIN>
@@ -822,8 +871,12 @@ int contract_fwd(const FarGeom &g, int ax, int64_t comps, const void *X, const d
         return mode<RIN, false, true>(X, E + g.eoff[ax], ac.A, g.G[ax], W, ac.C, W, 1, s, Y, part, st, defer_sum);
     const int M = g.M[ax];
     mode<RIN, false, true>(X, E + g.doff[ax], ac.A, M, M, g.p * ac.C, M, 1, 1.0, Z, part, st);
-    hipLaunchKernelGGL(k_fold<true>, dim3((unsigned)nblk(ac.A * W * ac.C, 256)), dim3(256), 0, st, Z, E + g.eoff[ax],
-                       ac.A, M, g.p, W, g.K[ax], ac.C, s, Y);
+    if (fold_on_lds(g, ax, ac))
+        hipLaunchKernelGGL(k_fold_lds<true>, dim3((unsigned)ac.A), dim3(FL_T), (size_t)M * g.p * sizeof(double2), st, Z,
+                           E + g.eoff[ax], M, g.p, W, g.K[ax], s, Y);
+    else
+        hipLaunchKernelGGL(k_fold<true>, dim3((unsigned)nblk(ac.A * W * ac.C, 256)), dim3(256), 0, st, Z,
+                           E + g.eoff[ax], ac.A, M, g.p, W, g.K[ax], ac.C, s, Y);
     return 1;
 }
 
@@ -840,7 +893,7 @@ void contract_eval(const FarGeom &g, int ax, int64_t comps, const double2 *X, co
     }
     const int M = g.M[ax];
     hipLaunchKernelGGL(k_unfold, dim3((unsigned)nblk(ac.A * g.G[ax] * ac.C, 256)), dim3(256), 0, st, X,
-                       E + g.eoff[ax], ac.A, M, g.p, W, g.K[ax], ac.C, Z);
+                       E + g.foff[ax], ac.A, M, g.p, W, g.K[ax], ac.C, Z);
     mode<false, ROUT, false>(Z, E + g.doff[ax], ac.A, M, M, g.p * ac.C, M, 1, 1.0, Y, part, st);
 }
 
@@ -857,7 +910,10 @@ FarLayout far_layout(const FarGeom &g, int kernel)
     int64_t off = 0;
     const int64_t z = (int64_t)sizeof(double2);
     l.E = off;
-    off = al(off + z * ((int64_t)g.G[0] * W0 + (int64_t)g.G[1] * W1 + (int64_t)g.G[2] * W2 + g.nD));
+    int64_t nft = 0;
+    for (int i = 0; i < 3; ++i)
+        if (g.fac[i]) nft += (int64_t)g.p * g.W[i];
+    off = al(off + z * ((int64_t)g.G[0] * W0 + (int64_t)g.G[1] * W1 + (int64_t)g.G[2] * W2 + g.nD + nft));
     l.T1 = off;
     off = al(off + z * Q * G0 * G1 * W2);
     l.T2 = off;
