@@ -259,13 +259,13 @@ __global__ __launch_bounds__(ML_T) void k_mode_lds(const void *__restrict__ Xv, 
 typedef double dbl4m __attribute__((ext_vector_type(4)));
 constexpr int MM_W = 8;  // wavefronts per tile
 
-template <bool RIN, bool ROUT, bool CONJ>
-__global__ __launch_bounds__(MM_W * WAVE) void k_mode_mfma(const void *__restrict__ Xv,
+template <bool RIN, bool ROUT, bool CONJ, int NW = MM_W>
+__global__ __launch_bounds__(NW * WAVE) void k_mode_mfma(const void *__restrict__ Xv,
                                                            const double2 *__restrict__ E, int64_t A, int I, int O,
                                                            int C, int64_t si, int64_t so, double s, int nsplit,
                                                            double2 *__restrict__ part, void *__restrict__ Yv)
 {
-    __shared__ double red[MM_W - 1][8][WAVE];
+    __shared__ double red[NW > 1 ? NW - 1 : 1][8][WAVE];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
     const int to = (O + 15) / 16, tc = (C + 15) / 16;
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(MM_W * WAVE) void k_mode_mfma(const void *__restric
     const int oa = ot * 16 + li, cb = ct * 16 + li;
     const bool ook = oa < O, cok = cb < C;
     dbl4m dre = {0.0, 0.0, 0.0, 0.0}, dim = {0.0, 0.0, 0.0, 0.0};
-    for (int gq = g0 + wv; gq < g1; gq += MM_W) {
+    for (int gq = g0 + wv; gq < g1; gq += NW) {
         const int k = 4 * gq + lk;
         const bool kok = k < I;
         double er = 0.0, ei = 0.0, xr = 0.0, xi = 0.0;
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(MM_W * WAVE) void k_mode_mfma(const void *__restric
     __syncthreads();
     if (wv > 0 || !cok) return;
 #pragma unroll
-    for (int w = 0; w < MM_W - 1; ++w)
+    for (int w = 0; w < NW - 1; ++w)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             dre[r] += red[w][r][lane];
@@ -737,6 +737,11 @@ inline bool mode_on_mfma(int64_t A, int I, int O, int C)
            grid_fits(nblk(A * O * C, 256), 256);
 }
 
+// Few terms (at most two groups of 4 per wavefront of the 8-wave form) over
+// many tiles: one wavefront per tile takes all groups in order, without the
+// reduction through LDS (the cube-index DFTs of short axes)
+inline bool mode_one_wave(int I, int64_t tiles) { return I <= 64 && tiles >= 1024; }
+
 // doubles2 of partial results a contraction needs (0 without a split)
 inline int64_t mode_part(int64_t A, int I, int O, int C)
 {
@@ -790,6 +795,11 @@ int mode(const void *X, const double2 *E, int64_t A, int I, int O, int C, int64_
         // 16 x 16 output tiles on the matrix cores, nsplit workgroups each
         const int64_t tiles = A * ((O + 15) / 16) * ((C + 15) / 16);
         const int ns = mode_nsplit(A, I, O, C);
+        if (ns == 1 && mode_one_wave(I, tiles)) {
+            hipLaunchKernelGGL((k_mode_mfma<RIN, ROUT, CONJ, 1>), dim3((unsigned)tiles), dim3(WAVE), 0, st, X, E, A, I,
+                               O, C, si, so, s, 1, part, Y);
+            return 1;
+        }
         hipLaunchKernelGGL((k_mode_mfma<RIN, ROUT, CONJ>), dim3((unsigned)(tiles * ns)), dim3(MM_W * WAVE), 0, st, X,
                            E, A, I, O, C, si, so, s, ns, part, Y);
         if (ns > 1 && defer_sum) return ns;
