@@ -149,6 +149,18 @@ def test_far_elongated_other_axes_sampled(kernel, axis):
     assert_parity(got, ref, 1e-12, "far elongated axis %d %s" % (axis, kernel))
 
 
+@pytest.mark.parametrize("kernel,Lv,M,c,p", [("laplace", (128.0, 1.0, 1.0), (128, 1, 1), 29.0, 38),
+                                              ("stokeslet", (1.0, 1.0, 64.0), (1, 1, 64), 32.46, 44)])
+def test_far_long_cuboid_sampled(kernel, Lv, M, c, p):
+    # 128 cubes (DFT of 128 terms, eight wavefronts per tile) and 64 cubes
+    # along the innermost axis (64 terms, one wavefront per tile), the
+    # paper's 1e-12 parameters
+    K = F.table_modes(c, Lv, 1.0)
+    print("far long cuboid", kernel, M, K, flush=True)
+    got, ref = _sampled(kernel, Lv, M, p, K, c, 1200, 96, 88)
+    assert_parity(got, ref, 1e-12, "far long cuboid %s %s" % (kernel, M))
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_far_edge_cases(kernel):
     k = oracle.KERNELS[kernel]
