@@ -3,11 +3,15 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload laplace_n1m]
 
-One step = dmk_residual_eval (forward) + dmk_residual_backward (adjoint) of
-the whole workload, with the points already binned and all inputs resident
-in HBM (the binning, the paper's tree construction, is timed separately and
-reported as bin_ms).  The headline is the FP32-compensated path; the FP64
-path is timed the same way and reported beside it.
+One step = the forward (strength gather into the sorted order + pair kernel)
+and the adjoint (cotangent gather + adjoint pair kernel, reusing the
+forward's sorted strengths) of the whole workload, with the points already
+binned and all inputs resident in HBM.  The binning (the paper's tree
+construction, which its timings exclude) is timed on its own and reported as
+bin_ms, and the end-to-end autograd step (bin + forward + backward through
+DmkResidual) beside it.  The headline is the FP32-compensated path on
+laplace_n1m; the FP64 path is timed the same way, and every other workload
+of the metric's configuration list gets its own object in the line.
 
 Metric: in-cutoff ordered pair interactions (0 < r < rc, P_in) per second of
 forward + backward.  Prints ONE JSON line.
@@ -30,19 +34,38 @@ from paper_2606_27134_amd import workloads as W  # noqa: E402
 
 METRIC = "residual pair-interactions/s fwd+bwd, FP32-compensated vs FP64 at stated rel err"
 
-# Algorithmic flops per in-cutoff pair (add/mul = 1, fma = 2, each elementary
-# function rsqrt/exp/erfc = 1), counted from the kernel formulas.
+# Floating-point operations per in-cutoff pair of the pair step as compiled
+# for gfx950 (distance from the staged coordinates, cutoff test, residual
+# kernel or its adjoint with the Gaussian window): counted from the ISA of
+# the kernels' pair arithmetic, FMA = 2, add / mul = 1, each rsq / rcp / exp
+# = 1 (the FP64 exponential is a software sequence of adds and FMAs).  The
+# FP64 accumulation into the target's sum runs in the LDS unit and is not
+# counted.
 FLOPS_PER_PAIR = {
-    ("laplace", "fwd"): 19, ("laplace", "bwd"): 34,
-    ("stokeslet", "fwd"): 42, ("stokeslet", "bwd"): 95,
-    ("stresslet", "fwd"): 68, ("stresslet", "bwd"): 190,
-    ("rotlet", "fwd"): 33, ("rotlet", "bwd"): 70,
+    ("laplace", "fp32c", "fwd"): 44, ("laplace", "fp32c", "bwd"): 58,
+    ("stokeslet", "fp32c", "fwd"): 67, ("stokeslet", "fp32c", "bwd"): 146,
+    ("stresslet", "fp32c", "fwd"): 113, ("stresslet", "fp32c", "bwd"): 399,
+    ("rotlet", "fp32c", "fwd"): 61, ("rotlet", "fp32c", "bwd"): 107,
+    ("laplace", "fp64", "fwd"): 128, ("laplace", "fp64", "bwd"): 142,
+    ("stokeslet", "fp64", "fwd"): 151, ("stokeslet", "fp64", "bwd"): 230,
+    ("stresslet", "fp64", "fwd"): 196, ("stresslet", "fp64", "bwd"): 482,
+    ("rotlet", "fp64", "fwd"): 145, ("rotlet", "fp64", "bwd"): 191,
 }
-PEAK_TFLOPS = {"fp32c": 157.3, "fp64": 78.6}  # MI355X vector peaks
+# MI355X published vector peaks (TFLOP/s).  FP32 157.3 needs packed FP32
+# instructions, which this build keeps out of the generated code; one
+# unpacked FP32 (or FP64) instruction per lane per cycle is 78.6.
+PEAK_TFLOPS = {"fp32c": 157.3, "fp64": 78.6}
+PEAK_UNPACKED_TFLOPS = 78.6
 # PSWF bandwidth c for a requested tolerance 1e-6 (the paper's parameter
 # tables for the Laplace and Stokes kernels)
 PSWF_C_1E6 = {"laplace": 14.5, "stokeslet": 17.80, "stresslet": 17.80, "rotlet": 13.61}
 HBM_PEAK_GBS = 8000.0
+# the workloads of the metric's configuration list, beside the headline:
+# (label, workload, kernel)
+CONFIGS = [("laplace_n2k", "laplace_n2k", None),
+           ("stokeslet_n500k_clustered", "stokeslet_n500k_clustered", None),
+           ("stresslet_n2m_rod", "stokes_n2m_rod", "stresslet"),
+           ("rotlet_n2m_rod", "stokes_n2m_rod", "rotlet")]
 
 
 def count_pairs(w, targets=None):
@@ -90,14 +113,26 @@ def read_traffic(workload, prec, khash, field=None):
     return d.get(prec)
 
 
+def _omp_threads(n):
+    """Set the OpenMP thread count of this process (the oracle's runtime)."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except OSError:
+        return False
+
+
 def cpu_baseline(w, budget_s=15.0):
-    """The oracle (fwd + vjp) on a bounded sample of targets of the same workload."""
+    """The oracle (fwd + vjp, O(N^2) brute force) on a bounded sample of
+    targets of the same workload, on all host cores and on one core."""
     import oracle
     oracle.build()
     rng = np.random.default_rng(123)
     G = W.cotangent(w.seed, w.N, W.M_OUT[w.kernel])
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cores = min(cores, os.cpu_count() or cores)
+    _omp_threads(cores)
     n_try = 2 * cores
     t = np.sort(rng.choice(w.N, size=n_try, replace=False))
     t0 = time.perf_counter()
@@ -111,10 +146,29 @@ def cpu_baseline(w, budget_s=15.0):
     u = oracle.residual(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, targets=t)
     gr, gx = oracle.residual_vjp(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, G, targets=t)
     dt = time.perf_counter() - t0
+    # one core, on a sixteenth of the sample
+    n1 = max(1, n // 16)
+    t1s = t[:n1]
+    one = None
+    if _omp_threads(1):
+        t0 = time.perf_counter()
+        oracle.residual(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, targets=t1s)
+        oracle.residual_vjp(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, G, targets=t1s)
+        one = time.perf_counter() - t0
+        _omp_threads(cores)
     pin = count_pairs(w, targets=t)
-    return dict(value=pin / dt, unit="pair-interactions/s", cores=cores, kind="oracle",
-                sample="%d seeded targets of %s (all %d sources, every image), fwd + vjp, %.1f s, "
-                       "P_in(sample)=%d" % (n, w.name, w.N, dt, pin)), (t, u, gr, gx, G)
+    tests = 2.0 * n * w.N  # forward and vjp each test every (target, source) pair
+    out = dict(value=pin / dt, unit="pair-interactions/s", cores=cores, kind="oracle",
+               label="O(N^2) brute-force reference (long double, every source and image per target), "
+                     "not a tuned CPU code",
+               sample="%d seeded targets of %s (all %d sources, every image), fwd + vjp, %.1f s on %d cores, "
+                      "P_in(sample)=%d" % (n, w.name, w.N, dt, cores, pin),
+               pair_tests_per_s=tests / dt, seconds_all_cores=dt, targets=n)
+    if one is not None:
+        out.update(seconds_one_core=one, targets_one_core=n1,
+                   pair_tests_per_s_one_core=2.0 * n1 * w.N / one,
+                   seconds_one_core_per_target=one / n1, seconds_all_cores_per_target=dt / n)
+    return out, (t, u, gr, gx, G)
 
 
 def _time_ms(fn, reps, warm=3):
@@ -131,6 +185,162 @@ def _time_ms(fn, reps, warm=3):
     return ev[0].elapsed_time(ev[1]) / reps
 
 
+def time_residual(w, bins, prec, steps, warmup, pswf_c=None):
+    """Time `steps` forward + adjoint steps on the current stream.  Events
+    bracket every call: the gathers and the pair kernels, so the pair
+    kernels' durations are measured in the timed region itself."""
+    import torch
+    from paper_2606_27134_amd import residual as R
+    k = w.kernel
+    dev = "cuda"
+    rho = torch.as_tensor(w.rho).to(dev)
+    G = torch.as_tensor(W.cotangent(w.seed, w.N, W.M_OUT[k])).to(dev)
+    rho_s = torch.empty((W.M_IN[k], w.N), dtype=torch.float64, device=dev)
+    gu_s = torch.empty((W.M_OUT[k], w.N), dtype=torch.float64, device=dev)
+    u = torch.empty((w.N, W.M_OUT[k]), dtype=torch.float64, device=dev)
+    gr = torch.empty((w.N, W.M_IN[k]), dtype=torch.float64, device=dev)
+    gx = torch.empty((w.N, 3), dtype=torch.float64, device=dev)
+    sig = 0.0 if pswf_c else w.sigma
+
+    def fwd():
+        R.gather_sorted(bins, rho, out=rho_s)
+        R.residual_eval_sorted(bins, k, prec, sig, w.rc, rho_s, out=u, pswf_c=pswf_c)
+
+    def bwd():
+        R.gather_sorted(bins, G, out=gu_s)
+        R.residual_backward_sorted(bins, k, prec, sig, w.rc, rho_s, gu_s, out=(gr, gx), pswf_c=pswf_c)
+
+    for _ in range(warmup):
+        fwd()
+        bwd()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    start.record(stream)
+    for s in range(steps):
+        e = ev[s]
+        e[0].record(stream)
+        R.gather_sorted(bins, rho, out=rho_s)
+        e[1].record(stream)
+        R.residual_eval_sorted(bins, k, prec, sig, w.rc, rho_s, out=u, pswf_c=pswf_c)
+        e[2].record(stream)
+        R.gather_sorted(bins, G, out=gu_s)
+        e[3].record(stream)
+        R.residual_backward_sorted(bins, k, prec, sig, w.rc, rho_s, gu_s, out=(gr, gx), pswf_c=pswf_c)
+        e[4].record(stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = start.elapsed_time(stop) / steps
+    el = lambda a, b: float(np.mean([ev[s][a].elapsed_time(ev[s][b]) for s in range(steps)]))  # noqa: E731
+    res = dict(ms_per_step=ms, fwd_ms=el(0, 2), bwd_ms=el(2, 4), kernel_fwd_ms=el(1, 2), kernel_bwd_ms=el(3, 4),
+               gather_fwd_ms=el(0, 1), gather_bwd_ms=el(2, 3), wall_s=t_wall)
+    outs = (u.cpu().numpy(), gr.cpu().numpy(), gx.cpu().numpy())
+    return res, outs
+
+
+def roofline(kernel, prec, P_in, r, khash=None, workload=None):
+    """Roofline of the dominant pair-kernel launch of a step (the longer of
+    forward and adjoint): algorithmic flops of the in-cutoff pairs over its
+    measured duration, against the vector peak of the precision."""
+    dom = "bwd" if r["kernel_bwd_ms"] >= r["kernel_fwd_ms"] else "fwd"
+    dur_ms = r["kernel_%s_ms" % dom]
+    fpp = FLOPS_PER_PAIR[(kernel, prec, dom)]
+    achieved = fpp * P_in / (dur_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS[prec], "traffic": None,
+            "kernel": "k_residual<%s,%s,%s>" % (kernel, prec, dom), "flops_per_pair": fpp, "launch_ms": dur_ms}
+    if prec == "fp32c":
+        roof["peak_unpacked"] = PEAK_UNPACKED_TFLOPS
+        roof["frac_unpacked"] = achieved / PEAK_UNPACKED_TFLOPS
+    if khash is not None and workload is not None:
+        tr = read_traffic(workload, prec, khash)
+        roof["traffic"] = None if tr is None else tr.get(dom)
+        vi = read_traffic(workload, prec, khash, field="valu_issue")
+        roof["valu_issue_frac"] = None if vi is None else vi.get(dom)
+        ex = read_traffic(workload, prec, khash, field="valu_tflops")
+        roof["valu_executed_tflops"] = None if ex is None else ex.get(dom)
+    return roof
+
+
+def oracle_errors(w, outs, ntgt=64, seed=321):
+    """rel l2 of every result on ntgt seeded targets against the oracle."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    t = np.sort(rng.choice(w.N, size=min(ntgt, w.N), replace=False))
+    G = W.cotangent(w.seed, w.N, W.M_OUT[w.kernel])
+    u_o = oracle.residual(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, targets=t)
+    gr_o, gx_o = oracle.residual_vjp(w.kernel, w.D, w.L, w.sigma, w.rc, w.x, w.rho, G, targets=t)
+
+    def rl2(a, b):
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    errs = {prec: {"u": rl2(u[t], u_o), "grad_rho": rl2(gr[t], gr_o), "grad_x": rl2(gx[t], gx_o)}
+            for prec, (u, gr, gx) in outs.items()}
+    errs["sample_targets"] = int(len(t))
+    return errs
+
+
+def bench_workload(w, precs, steps, warmup):
+    """Binning, P_in and the timed fwd + adjoint steps of one workload."""
+    import torch
+    from paper_2606_27134_amd import residual as R
+    x = torch.as_tensor(w.x).cuda()
+    bins = R.Bins(w.L, w.D, w.n, w.N)
+    bins.bin(x)
+    torch.cuda.synchronize()
+    tb = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        bins.bin(x)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+    res, outs = {}, {}
+    for prec in precs:
+        res[prec], outs[prec] = time_residual(w, bins, prec, steps, warmup)
+    return bins, 1e3 * float(np.median(tb)), res, outs
+
+
+def config_object(label, w, P_in, bin_ms, res, errs):
+    o = {"workload": "%s: %s D=%d L=%s n=%s N=%d sigma=%.6g rc=%.6g" % (
+        w.name, w.kernel, w.D, list(w.L), list(w.n), w.N, w.sigma, w.rc), "P_in": P_in, "bin_ms": bin_ms}
+    for prec, r in res.items():
+        o[prec] = {"value": P_in / (r["ms_per_step"] * 1e-3), "value_fwd": P_in / (r["fwd_ms"] * 1e-3),
+                   "ms_per_step": r["ms_per_step"], "fwd_ms": r["fwd_ms"], "bwd_ms": r["bwd_ms"],
+                   "kernel_fwd_ms": r["kernel_fwd_ms"], "kernel_bwd_ms": r["kernel_bwd_ms"],
+                   "roofline": roofline(w.kernel, prec, P_in, r)}
+    if "fp32c" in res and "fp64" in res:
+        o["fp32c_speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res["fp32c"]["ms_per_step"]
+    if errs is not None:
+        o["rel_l2_vs_oracle"] = errs
+    return o
+
+
+def autograd_step(w, prec, steps, warmup):
+    """End to end through DmkResidual: bin + forward + backward of
+    E = 1/2 sum rho . u w.r.t. positions and strengths."""
+    import torch
+    from paper_2606_27134_amd import residual as R
+    x = torch.as_tensor(w.x).cuda().requires_grad_(True)
+    rho = torch.as_tensor(w.rho).cuda().requires_grad_(True)
+    spec = R.ResidualSpec(L=w.L, D=w.D, n=w.n, kernel=w.kernel, prec=prec, sigma=w.sigma, rc=w.rc)
+
+    def step():
+        u = R.dmk_residual(x, rho, spec)
+        E = 0.5 * (rho * u).sum()
+        torch.autograd.grad(E, (x, rho))
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / steps
+
+
 def _far_flops(M, p, K):
     """Algorithmic flops of one root-level far field on an exact tiling of
     M_i cubes, counting the form the library runs on each axis: the direct
@@ -139,18 +349,18 @@ def _far_flops(M, p, K):
     Chebyshev index.  Complex multiply-add 8, real by complex or real part
     only 4."""
     G = [m * p for m in M]
-    W = [2 * k + 1 for k in K]
-    fac = [8 <= m <= 512 and 2 * (m * m + w) <= w * m for m, w in zip(M, W)]
+    Wn = [2 * k + 1 for k in K]
+    fac = [8 <= m <= 512 and 2 * (m * m + w) <= w * m for m, w in zip(M, Wn)]
     # (A, C) around each axis: axis 2 on [g0][g1][.], axis 1 on [g0][.][n2], axis 0 on [.][n1][n2]
-    cols = {2: (G[0] * G[1], 1), 1: (G[0], W[2]), 0: (1, W[1] * W[2])}
+    cols = {2: (G[0] * G[1], 1), 1: (G[0], Wn[2]), 0: (1, Wn[1] * Wn[2])}
     fl = 0.0
     for ax, first_or_last in ((2, True), (1, False), (0, False)):
         A, C = cols[ax]
         half = 4.0 if first_or_last else 8.0  # real input (forward) / real part (evaluation)
         if fac[ax]:
-            fl += 2 * (half * A * M[ax] * M[ax] * p * C + 8.0 * A * W[ax] * p * C)
+            fl += 2 * (half * A * M[ax] * M[ax] * p * C + 8.0 * A * Wn[ax] * p * C)
         else:
-            fl += 2 * half * A * G[ax] * W[ax] * C
+            fl += 2 * half * A * G[ax] * Wn[ax] * C
     return fl
 
 
@@ -209,6 +419,13 @@ def main():
                     help="bandwidth of the PSWF-split leg (default: the paper's 1e-6 value for the kernel; 0 skips)")
     ap.add_argument("--no-far", action="store_true",
                     help="skip the root-level far field and leaf-grid leg")
+    ap.add_argument("--configs", default="all",
+                    help="comma-separated labels of the other configurations to time ('none' skips them)")
+    ap.add_argument("--config-steps", type=int, default=10)
+    ap.add_argument("--oracle-targets", type=int, default=64,
+                    help="sampled targets per configuration for the error against the oracle (0 skips)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline workload's timed steps (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -235,78 +452,16 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
         return
 
-    from paper_2606_27134_amd import residual as R
-    from paper_2606_27134_amd import _lib as L
-
-    w = W.make(args.workload, kernel=args.kernel)
-    stream = torch.cuda.current_stream()
-    x = torch.as_tensor(w.x).cuda()
-    rho = torch.as_tensor(w.rho).cuda()
-    G = torch.as_tensor(W.cotangent(w.seed, w.N, W.M_OUT[w.kernel])).cuda()
-
-    # binning (setup), timed on its own
-    bins = R.Bins(w.L, w.D, w.n, w.N)
-    bins.bin(x)
-    torch.cuda.synchronize()
-    tb = []
-    for _ in range(3):
-        t0 = time.perf_counter()
-        bins.bin(x)
-        torch.cuda.synchronize()
-        tb.append(time.perf_counter() - t0)
-    bin_ms = 1e3 * float(np.median(tb))
-
-    P_in = count_pairs(w)
     precs = [p for p in args.precs.split(",") if p]
-    res = {}
-    outs = {}
-    for prec in precs:
-        ws_f = R.workspace(bins, w.kernel, prec, False)
-        ws_b = R.workspace(bins, w.kernel, prec, True)
-        u = torch.empty((w.N, W.M_OUT[w.kernel]), dtype=torch.float64, device="cuda")
-        gr = torch.empty((w.N, W.M_IN[w.kernel]), dtype=torch.float64, device="cuda")
-        gx = torch.empty((w.N, 3), dtype=torch.float64, device="cuda")
-
-        def step():
-            R.residual_eval(bins, w.kernel, prec, w.sigma, w.rc, rho, out=u, ws=ws_f)
-            R.residual_backward(bins, w.kernel, prec, w.sigma, w.rc, rho, G, out=(gr, gx), ws=ws_b)
-
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.steps + 2)]
-        start, stop = ev[-2], ev[-1]
-        # events the library records around the pair kernel alone (the call
-        # also gathers the strengths into the sorted order first)
-        kev = [torch.cuda.Event(enable_timing=True) for _ in range(4 * args.steps)]
-        for e in kev:
-            e.record(stream)  # creates the device event
-        torch.cuda.synchronize()
-        t_wall = time.perf_counter()
-        start.record(stream)
-        for k in range(args.steps):
-            ev[3 * k].record(stream)
-            L.dmk_residual_set_kernel_events(kev[4 * k].cuda_event, kev[4 * k + 1].cuda_event)
-            R.residual_eval(bins, w.kernel, prec, w.sigma, w.rc, rho, out=u, ws=ws_f)
-            ev[3 * k + 1].record(stream)
-            L.dmk_residual_set_kernel_events(kev[4 * k + 2].cuda_event, kev[4 * k + 3].cuda_event)
-            R.residual_backward(bins, w.kernel, prec, w.sigma, w.rc, rho, G, out=(gr, gx), ws=ws_b)
-            ev[3 * k + 2].record(stream)
-        stop.record(stream)
-        L.dmk_residual_set_kernel_events(0, 0)
-        torch.cuda.synchronize()
-        t_wall = time.perf_counter() - t_wall
-        total_ms = start.elapsed_time(stop)
-        fwd = [ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in range(args.steps)]
-        bwd = [ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in range(args.steps)]
-        kfwd = [kev[4 * k].elapsed_time(kev[4 * k + 1]) for k in range(args.steps)]
-        kbwd = [kev[4 * k + 2].elapsed_time(kev[4 * k + 3]) for k in range(args.steps)]
-        ms_step = total_ms / args.steps
-        res[prec] = dict(ms_per_step=ms_step, fwd_ms=float(np.mean(fwd)), bwd_ms=float(np.mean(bwd)),
-                         fwd_ms_median=float(np.median(fwd)), bwd_ms_median=float(np.median(bwd)),
-                         kernel_fwd_ms=float(np.mean(kfwd)), kernel_bwd_ms=float(np.mean(kbwd)),
-                         value=P_in / (ms_step * 1e-3), wall_s=t_wall)
-        outs[prec] = (u.cpu().numpy(), gr.cpu().numpy(), gx.cpu().numpy())
+    w = W.make(args.workload, kernel=args.kernel)
+    bins, bin_ms, res, outs = bench_workload(w, precs, args.steps, args.warmup)
+    print("headline %s timed" % w.name, file=sys.stderr, flush=True)
+    if args.headline_only:
+        r = res[precs[0]]
+        print(json.dumps({"workload": w.name, "ms_per_step": r["ms_per_step"], "kernel_fwd_ms": r["kernel_fwd_ms"],
+                          "kernel_bwd_ms": r["kernel_bwd_ms"]}), flush=True)
+        return
+    P_in = count_pairs(w)
 
     # ---- PSWF split (Sec. 2.2) on the same points: support nu = rc, so the
     # same in-cutoff pairs; bandwidth c from the paper's parameter tables
@@ -315,49 +470,17 @@ def main():
     if pc and pc > 0:
         pswf = {"c": pc, "nu": w.rc}
         for prec in precs:
-            ws_f = R.workspace(bins, w.kernel, prec, False)
-            ws_b = R.workspace(bins, w.kernel, prec, True)
-            u = torch.empty((w.N, W.M_OUT[w.kernel]), dtype=torch.float64, device="cuda")
-            gr = torch.empty((w.N, W.M_IN[w.kernel]), dtype=torch.float64, device="cuda")
-            gx = torch.empty((w.N, 3), dtype=torch.float64, device="cuda")
-            for _ in range(args.warmup):
-                R.residual_eval(bins, w.kernel, prec, 0.0, w.rc, rho, out=u, ws=ws_f, pswf_c=pc)
-                R.residual_backward(bins, w.kernel, prec, 0.0, w.rc, rho, G, out=(gr, gx), ws=ws_b, pswf_c=pc)
-            torch.cuda.synchronize()
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.steps)]
-            for k in range(args.steps):
-                ev[3 * k].record(stream)
-                R.residual_eval(bins, w.kernel, prec, 0.0, w.rc, rho, out=u, ws=ws_f, pswf_c=pc)
-                ev[3 * k + 1].record(stream)
-                R.residual_backward(bins, w.kernel, prec, 0.0, w.rc, rho, G, out=(gr, gx), ws=ws_b, pswf_c=pc)
-                ev[3 * k + 2].record(stream)
-            torch.cuda.synchronize()
-            fwd = float(np.mean([ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in range(args.steps)]))
-            bwd = float(np.mean([ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in range(args.steps)]))
-            pswf[prec] = {"value": P_in / ((fwd + bwd) * 1e-3), "fwd_ms": fwd, "bwd_ms": bwd}
-            outs["pswf_" + prec] = (u.cpu().numpy(), gr.cpu().numpy(), gx.cpu().numpy())
+            r, o = time_residual(w, bins, prec, max(5, args.steps // 2), args.warmup, pswf_c=pc)
+            pswf[prec] = {"value": P_in / (r["ms_per_step"] * 1e-3), "fwd_ms": r["fwd_ms"], "bwd_ms": r["bwd_ms"],
+                          "kernel_fwd_ms": r["kernel_fwd_ms"], "kernel_bwd_ms": r["kernel_bwd_ms"]}
+            outs["pswf_" + prec] = o
 
     head = "fp32c" if "fp32c" in res else precs[0]
     r = res[head]
-    # dominant kernel: the larger of the two launches of the headline step
-    dom = "bwd" if r["kernel_bwd_ms"] >= r["kernel_fwd_ms"] else "fwd"
-    dur_ms = r["kernel_%s_ms" % dom]  # average duration of that k_residual launch
-    flops = FLOPS_PER_PAIR[(w.kernel, dom)] * P_in
-    achieved = flops / (dur_ms * 1e-3) / 1e12
     khash = kernel_hash()
-    tr = read_traffic(w.name, head, khash)
-    traffic = None if tr is None else tr.get(dom)
-    vi = read_traffic(w.name, head, khash, field="valu_issue")
-    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS[head], "traffic": traffic,
-            # share of the SIMDs' VALU issue slots the launch used (SQ_INSTS_VALU
-            # x 4 cycles over the launch's cycles), from the same counter runs
-            "valu_issue_frac": None if vi is None else vi.get(dom),
-            "kernel": "k_residual<%s,%s,%s>" % (w.kernel, head, dom),
-            "flops_per_pair": FLOPS_PER_PAIR[(w.kernel, dom)], "launch_ms": dur_ms}
-
+    roof = roofline(w.kernel, head, P_in, r, khash=khash, workload=w.name)
     line = {
-        "metric": METRIC, "value": r["value"], "unit": "pair-interactions/s", "n_gpus": 1,
+        "metric": METRIC, "value": P_in / (r["ms_per_step"] * 1e-3), "unit": "pair-interactions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if head == "fp32c" else "f64", "data": "synthetic",
@@ -367,6 +490,7 @@ def main():
         "P_in": P_in, "bin_ms": bin_ms,
         "fwd_ms": r["fwd_ms"], "bwd_ms": r["bwd_ms"],
         "kernel_fwd_ms": r["kernel_fwd_ms"], "kernel_bwd_ms": r["kernel_bwd_ms"],
+        "gather_fwd_ms": r["gather_fwd_ms"], "gather_bwd_ms": r["gather_bwd_ms"],
         "roofline": roof, "kernel_hash": khash,
     }
     # the paper's own timings, as context: it reports full-DMK runtimes of a
@@ -379,12 +503,35 @@ def main():
                      "of the full method 1.0e-7 (Laplace) / 1.7e-7 (Stokeslet) at tolerance 1e-6"}
     if "fp64" in res and head != "fp64":
         f = res["fp64"]
-        line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "fwd_ms": f["fwd_ms"],
-                        "bwd_ms": f["bwd_ms"]}
+        line["fp64"] = {"value": P_in / (f["ms_per_step"] * 1e-3), "ms_per_step": f["ms_per_step"],
+                        "fwd_ms": f["fwd_ms"], "bwd_ms": f["bwd_ms"], "kernel_fwd_ms": f["kernel_fwd_ms"],
+                        "kernel_bwd_ms": f["kernel_bwd_ms"],
+                        "roofline": roofline(w.kernel, "fp64", P_in, f, khash=khash, workload=w.name)}
         line["fp32c_speedup_vs_fp64"] = f["ms_per_step"] / r["ms_per_step"]
-
+    # end to end through the autograd function: bin + forward + backward
+    line["autograd_step_ms"] = {p: autograd_step(w, p, max(5, args.steps // 5), 2) for p in precs}
     if pswf is not None:
         line["pswf"] = pswf
+
+    # ---- the other workloads of the configuration list
+    if args.configs != "none":
+        want = None if args.configs == "all" else set(args.configs.split(","))
+        cfg_out = {}
+        pin_cache = {}
+        for label, name, kern in CONFIGS:
+            if want is not None and label not in want:
+                continue
+            wc = W.make(name, kernel=kern)
+            _, cbin, cres, couts = bench_workload(wc, precs, args.config_steps, 3)
+            key = (name, wc.D)
+            if key not in pin_cache:
+                pin_cache[key] = count_pairs(wc)
+            errs = oracle_errors(wc, couts, args.oracle_targets) if args.oracle_targets > 0 else None
+            cfg_out[label] = config_object(label, wc, pin_cache[key], cbin, cres, errs)
+            print("config %s timed" % label, file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+        line["configs"] = cfg_out
+
     if not args.no_far:
         line["far_leaf"] = far_leaf_leg(args)
 

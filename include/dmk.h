@@ -38,8 +38,8 @@
  *    with (m_in, m_out) = (1,1) Laplace, (3,3) Stokeslet, (9,3) stresslet
  *    (rho_lm row-major, u_j = T_jlm rho_lm), (3,3) rotlet.
  *  - prec selects only the internal pair arithmetic: DMK_FP64, or DMK_FP32C
- *    (FP32 pair arithmetic on hi/lo FP32 coordinates formed in FP64, Kahan
- *    compensated FP32 accumulation, FP64 final combine).
+ *    (FP32 pair arithmetic on hi/lo FP32 coordinates formed in FP64; the
+ *    FP32 pair terms are summed per target in FP64).
  *  - Return value: a dmk_status.  Argument errors are detected on the host
  *    before any launch.  dmk_residual_eval / _backward return right after
  *    their launches (asynchronous on `stream`).  dmk_tree_bin synchronises
@@ -99,7 +99,8 @@ typedef struct {
                          /*          for offsets -1,0,+1, or -1 if none (free)  */
     int8_t *axis_img;    /* [n0+n1+n2][3] image index s in {-1,0,1}: the        */
                          /*          neighbour's points sit at x + s*L_i         */
-    int32_t *tiles;      /* [max_tiles][4] target tiles (see DESIGN notes)      */
+    int32_t *tiles;      /* [max_tiles][4] target tiles {leaf column, z0, z1 or  */
+                         /*          -(z0+1) for one dense box, first target}  */
     int32_t *status;     /* [4] device error word, tile count                   */
     int32_t *tmp;        /* sort / tile scratch                                  */
     int64_t tmp_ints;    /* size of tmp in int32                                 */
@@ -192,15 +193,34 @@ int dmk_residual_backward_pswf(const dmk_grid *grid, const dmk_bins *bins, int k
                                void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
- * Timing hook: from now on, record the device events `start` right before and
- * `stop` right after the pair kernel of every dmk_residual_eval /
- * dmk_residual_backward call, on that call's stream (the strength gather
- * that precedes it stays outside the pair).  Events are owned by the caller
- * and must stay valid while set; pass two null events to stop recording.
- * Process-wide setting, not synchronised between host threads; meant for
- * benchmarks.  Returns DMK_OK, or DMK_EINVAL when exactly one event is null.
+ * The residual sums of dmk_residual_eval / dmk_residual_backward split into
+ * their two steps, for callers that keep strengths in the sorted order (an
+ * adjoint that reuses the forward's sorted strengths, or a caller that times
+ * the pair kernel alone with its own events around the call).
+ *
+ * dmk_gather_sorted: dst[c][j] = src[perm[j]][c] for the N points of `bins`
+ * and c < m: src[N][m] (dev, FP64, original order), dst[m][N] (dev, FP64,
+ * sorted order, rows N apart).  1 <= m <= DMK_GATHER_MMAX.  Asynchronous.
+ * DMK_EINVAL on a bad m or null pointer, DMK_ESIZE for more than 2^30 - 1
+ * points.
+ *
+ * dmk_residual_eval_sorted: u[N][m_out] (dev, original order) from the sorted
+ * strengths rho_sorted[m_in][N] (as dmk_gather_sorted writes them).
+ * dmk_residual_backward_sorted: grad_rho[N][m_in], grad_x[N][3] (dev,
+ * original order) from rho_sorted[m_in][N] and the sorted cotangent
+ * gu_sorted[m_out][N].  Both launch the pair kernel only, asynchronously on
+ * `stream`, and need no workspace.  With w == NULL the split is the Gaussian
+ * of width sigma with cutoff rc; with a PSWF window w (dmk_pswf_window) it is
+ * the PSWF split of support nu = rc, and sigma is not used.  Argument rules
+ * and results are those of the calls above (bit-identical output).
  */
-int dmk_residual_set_kernel_events(hipEvent_t start, hipEvent_t stop);
+#define DMK_GATHER_MMAX 12
+int dmk_gather_sorted(const dmk_bins *bins, int m, const double *src, double *dst, hipStream_t stream);
+int dmk_residual_eval_sorted(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma,
+                             double rc, const dmk_pswf *w, const double *rho_sorted, double *u, hipStream_t stream);
+int dmk_residual_backward_sorted(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma,
+                                 double rc, const dmk_pswf *w, const double *rho_sorted, const double *gu_sorted,
+                                 double *grad_rho, double *grad_x, hipStream_t stream);
 
 /* Static description of a status code. */
 const char *dmk_strerror(int status);

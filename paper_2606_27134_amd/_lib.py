@@ -50,6 +50,7 @@ class dmk_far_grid(ctypes.Structure):
 FAR_PMAX = 64
 FAR_MMAX = 4096
 FAR_KMAX = 1024
+GATHER_MMAX = 12
 
 
 class DmkError(RuntimeError):
@@ -69,6 +70,14 @@ def load():
     if not os.path.exists(LIB_PATH):
         from . import build as _build
         _build.build()
+    # PyTorch's HIP libraries load their own HIP runtime by the unversioned
+    # name; loaded first, it also serves this library (same soname), so
+    # streams and device memory from torch are valid here.  Loaded after this
+    # library, torch would bring a second runtime into the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:  # pragma: no cover - binding used without torch
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     G = ctypes.POINTER(dmk_grid)
@@ -96,8 +105,14 @@ def load():
     lib.dmk_residual_backward_pswf.argtypes = [G, B, ctypes.c_int, ctypes.c_int, W, ctypes.c_double, P, P, P, P,
                                                P, ctypes.c_size_t, P]
     lib.dmk_residual_backward_pswf.restype = ctypes.c_int
-    lib.dmk_residual_set_kernel_events.argtypes = [P, P]
-    lib.dmk_residual_set_kernel_events.restype = ctypes.c_int
+    lib.dmk_gather_sorted.argtypes = [B, ctypes.c_int, P, P, P]
+    lib.dmk_gather_sorted.restype = ctypes.c_int
+    lib.dmk_residual_eval_sorted.argtypes = [G, B, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, W,
+                                             P, P, P]
+    lib.dmk_residual_eval_sorted.restype = ctypes.c_int
+    lib.dmk_residual_backward_sorted.argtypes = [G, B, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                 ctypes.c_double, W, P, P, P, P, P]
+    lib.dmk_residual_backward_sorted.restype = ctypes.c_int
     F = ctypes.POINTER(dmk_far_grid)
     lib.dmk_far3p_ws_bytes.argtypes = [F, ctypes.c_int]
     lib.dmk_far3p_ws_bytes.restype = ctypes.c_size_t
@@ -192,8 +207,27 @@ def dmk_residual_backward_pswf(grid, bins, kernel, prec, w, nu, rho_ptr, gu_ptr,
                                                  ctypes.c_void_p(stream)))
 
 
-def dmk_residual_set_kernel_events(start_ptr: int, stop_ptr: int) -> int:
-    return int(load().dmk_residual_set_kernel_events(ctypes.c_void_p(start_ptr), ctypes.c_void_p(stop_ptr)))
+def dmk_gather_sorted(bins, m, src_ptr, dst_ptr, stream) -> int:
+    return int(load().dmk_gather_sorted(ctypes.byref(bins), int(m), ctypes.c_void_p(src_ptr),
+                                        ctypes.c_void_p(dst_ptr), ctypes.c_void_p(stream)))
+
+
+def dmk_residual_eval_sorted(grid, bins, kernel, prec, sigma, rc, w, rho_s_ptr, u_ptr, stream) -> int:
+    """w: a dmk_pswf (PSWF split of support rc) or None (Gaussian of width sigma, cutoff rc)."""
+    return int(load().dmk_residual_eval_sorted(ctypes.byref(grid), ctypes.byref(bins), int(kernel), int(prec),
+                                               float(sigma), float(rc), ctypes.byref(w) if w is not None else None,
+                                               ctypes.c_void_p(rho_s_ptr), ctypes.c_void_p(u_ptr),
+                                               ctypes.c_void_p(stream)))
+
+
+def dmk_residual_backward_sorted(grid, bins, kernel, prec, sigma, rc, w, rho_s_ptr, gu_s_ptr, grho_ptr, gx_ptr,
+                                 stream) -> int:
+    return int(load().dmk_residual_backward_sorted(ctypes.byref(grid), ctypes.byref(bins), int(kernel), int(prec),
+                                                   float(sigma), float(rc),
+                                                   ctypes.byref(w) if w is not None else None,
+                                                   ctypes.c_void_p(rho_s_ptr), ctypes.c_void_p(gu_s_ptr),
+                                                   ctypes.c_void_p(grho_ptr), ctypes.c_void_p(gx_ptr),
+                                                   ctypes.c_void_p(stream)))
 
 
 def make_far_grid(L, M, p, K) -> dmk_far_grid:

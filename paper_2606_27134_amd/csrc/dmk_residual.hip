@@ -18,9 +18,11 @@
 //    distance test; in-cutoff pairs are compacted into an LDS queue
 //    (ballot + mbcnt), so the transcendental pair math runs on full
 //    wavefronts;
-//  * queued pairs are evaluated 64 at a time into an LDS contribution array;
-//    then each target's lane sums its own contiguous run (fixed order: the
-//    result is deterministic; Kahan-compensated in the FP32 path).
+//  * queued pairs are evaluated 64 at a time, one per lane; a segmented sum
+//    over the lanes (DPP moves) gives each target's run its total, which the
+//    run's last lane adds to the target's FP64 sum in LDS.  Only the
+//    wavefront that owns a target adds to its sum, in program order, so the
+//    result is deterministic;
 //  * tiles of very dense boxes stream their neighbourhood through LDS in
 //    chunks.
 //
@@ -69,7 +71,7 @@ struct Cfg {
     // TILE_NW wavefronts, 8 when only one workgroup fits in the 160 KiB of a
     // CU (more resident waves for the same staged tile; the rest of the
     // workgroup's LDS is below 16 KiB), and 2 if TILE_NW would not fit at all
-    static constexpr int STAGE_B = TILE_CAP * (16 + (F32 ? 16 + 4 * (NPL - 1) : 8 * (3 + NPL)));
+    static constexpr int STAGE_B = TILE_CAP * (16 + (F32 ? 16 + 4 * (NPL - 1) : 8 * (3 + NPL))) + 64;
     static constexpr int WAVE_B = QCAP * 4;
     static constexpr int NW = (STAGE_B + TILE_NW * WAVE_B > 150 * 1024) ? 2
                               : (STAGE_B + TILE_NW * WAVE_B + 16 * 1024 > 80 * 1024) ? 8
@@ -87,9 +89,17 @@ struct ResParams {
     const int32_t *skey, *bs, *perm, *nbr;
     const int8_t *img;
     const int4 *tiles;
-    const double *pl;
+    const double *pl;   // sorted strengths [MIN][N]
+    const double *pg;   // sorted cotangent [MOUT][N] (adjoint)
     double *out0, *out1;
 };
+
+// payload component c of sorted point j: strengths, then (adjoint) cotangent
+template <int MIN>
+__device__ inline double payload(const ResParams &P, int c, int64_t j)
+{
+    return c < MIN ? P.pl[(int64_t)c * P.N + j] : P.pg[(int64_t)(c - MIN) * P.N + j];
+}
 
 // one source piece: a z-range of one neighbour column (piece 0: the image
 // box below the domain, 1: boxes inside, 2: the image box above)
@@ -106,7 +116,9 @@ struct Smem {
     static constexpr int NX64 = C::F32 ? 1 : C::NPL;
     static constexpr int TX32 = (C::F32 && C::NTP > 1) ? C::NTP - 1 : 1;
     static constexpr int TX64 = (!C::F32 && C::NTP > 0) ? C::NTP : 1;
-    float4 sc[TILE_CAP];         // FP32 (hi) coords s and |s|^2 / 2 (scan test)
+    // FP32 (hi) coords s and |s|^2 / 2 (scan test); the slot after the last
+    // staged one holds a sentinel that no scan test accepts
+    float4 sc[TILE_CAP + 4];
     float4 sl[S32];              // FP32 lo coords, w = payload 0 (FP32 path)
     float sp[NX32][(C::F32 && C::NPL > 1) ? TILE_CAP : 1];  // FP32 payload 1..
     double sx[S64], sy[S64], sz[S64];
@@ -125,8 +137,7 @@ struct Smem {
             int dtab[(TILE_ZMAX + 2) * 9];
         } st;                               // set-up and staging only
     };
-    typename std::conditional<C::F32, float, double>::type tacc[C::NC][TILE_T];  // per-target sums
-    float tcmp[C::F32 ? C::NC : 1][C::F32 ? TILE_T : 1];  // their Kahan compensation (FP32 path)
+    double tacc[C::NC][TILE_T];  // per-target sums (FP64 in both paths)
     int soff[TILE_ZMAX + 4];        // slab offsets in the staged order
     int ccol[9];
     int qtot;
@@ -432,7 +443,7 @@ __device__ inline void stage_chunk(Smem<C> &S, const ResParams &P, bool dense, i
             X[u] = P.ys[j] + co.x;
             Y[u] = P.ys[N + j] + co.y;
             Z[u] = P.ys[2 * N + j] + S.zoff[g.piece];
-            for (int c = 0; c < C::NPL; ++c) pl[u][c] = P.pl[c * N + j] * KNorm<C::K>::c;  // normalised
+            for (int c = 0; c < C::NPL; ++c) pl[u][c] = payload<C::MIN>(P, c, j) * KNorm<C::K>::c;  // normalised
             sk[u] = dense ? 0 : P.skey[j];
         }
     }
@@ -561,19 +572,6 @@ __device__ inline bool seg_sum(int tag, T *v)
     seg_carry<DPP_ROW_BCAST15, 0xa, NC>(tag, v);
     seg_carry<DPP_ROW_BCAST31, 0xc, NC>(tag, v);
     return last;
-}
-
-// lanes 0 .. n-1 of a wavefront as a bit mask (n clamped to [0, 64])
-__device__ inline uint64_t lanes_below(int n)
-{
-    return n <= 0 ? 0ull : (n >= WAVE ? ~0ull : (1ull << n) - 1ull);
-}
-
-// whether this lane's bit of a uniform mask is set (the mask itself serves
-// as the lane condition, no per-lane shift)
-__device__ inline bool lane_in(uint64_t m)
-{
-    return __builtin_amdgcn_inverse_ballot_w64(m);
 }
 
 // inclusive prefix sum over the 64 lanes (shifts within rows, then carries
@@ -715,10 +713,7 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
             S.st.dtab[idx] = cnt | (pre << 16);
         }
     }
-    for (int idx = tid; idx < C::NC * TILE_T; idx += C::NW * WAVE) {
-        (&S.tacc[0][0])[idx] = 0;
-        if constexpr (C::F32) (&S.tcmp[0][0])[idx] = 0.0f;
-    }
+    for (int idx = tid; idx < C::NC * TILE_T; idx += C::NW * WAVE) (&S.tacc[0][0])[idx] = 0.0;
     int my_zt = 0, my_orig = 0;
     if (tid < TILE_T && tstart + tid < P.N) {  // all 64 slots; ones past ntgt are never used
         const int64_t j = tstart + tid;
@@ -726,14 +721,14 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
         const float hx = (float)X, hy = (float)Y, hz = (float)Z;
         S.tc[tid] = make_float4(hx, hy, hz, 0.5f * (rc2s - (hx * hx + hy * hy + hz * hz)));
         if constexpr (C::F32) {
-            const float t0 = (C::NTP > 0) ? (float)P.pl[j] : 0.0f;
+            const float t0 = (C::NTP > 0) ? (float)payload<C::MIN>(P, 0, j) : 0.0f;
             S.tl[tid] = make_float4((float)(X - (double)hx), (float)(Y - (double)hy), (float)(Z - (double)hz), t0);
-            for (int c = 1; c < C::NTP; ++c) S.tp[c - 1][tid] = (float)P.pl[c * P.N + j];
+            for (int c = 1; c < C::NTP; ++c) S.tp[c - 1][tid] = (float)payload<C::MIN>(P, c, j);
         } else {
             S.tx[tid] = X;
             S.ty[tid] = Y;
             S.tz[tid] = Z;
-            for (int c = 0; c < C::NTP; ++c) S.tpd[c][tid] = P.pl[c * P.N + j];
+            for (int c = 0; c < C::NTP; ++c) S.tpd[c][tid] = payload<C::MIN>(P, c, j);
         }
         if (!dense) my_zt = P.skey[j] - (int)colb;
         my_orig = P.perm[j];
@@ -808,27 +803,14 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
         for (int c = 0; c < C::NC; ++c) v[c] = ok ? v[c] : (T)0;
     };
 
-    // add x[NC] to target t's sums (Kahan-compensated in the FP32 path)
-    auto add_target = [&](int t, const T *x) {
-        for (int c = 0; c < C::NC; ++c) {
-            if constexpr (C::F32) {
-                const float acc = S.tacc[c][t];
-                const float y = x[c] - S.tcmp[c][t];
-                const float s2 = acc + y;
-                S.tcmp[c][t] = (s2 - acc) - y;
-                S.tacc[c][t] = s2;
-            } else {
-                S.tacc[c][t] += x[c];
-            }
-        }
-    };
-
     // Pair step over queue entries [base, base + cnt), cnt <= 64, one per lane.
-    //  * multi-box tiles: a batch holds the runs of several targets in order;
-    //    a segmented sum gives each run's total to its last lane, which adds
-    //    it to the target's sums;
+    //  * multi-box tiles: a batch holds the pairs of several targets; every
+    //    lane adds its pair term to its target's FP64 sum with an LDS atomic
+    //    add (the target's sums are only touched by this wavefront, one
+    //    instruction after another, so the order is fixed);
     //  * dense tiles: a batch holds one target's pairs; each lane keeps a
-    //    running sum part[] that is reduced when the target's range is done.
+    //    running FP32 sum part[] of at most TILE_CAP / 64 terms, reduced when
+    //    the target's range in the chunk is done and added to its FP64 sum.
     T part[C::NC];
     for (int c = 0; c < C::NC; ++c) part[c] = 0;
     auto batch = [&](int base, int cnt) {
@@ -843,8 +825,11 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
         if (dense) {
             for (int c = 0; c < C::NC; ++c) part[c] += v[c];
         } else {
+            // a target's entries are one run of the batch: its total goes to
+            // the run's last lane, the only lane that adds to that target
             const bool last = seg_sum<C::NC>(tag, v);
-            if (lane < cnt && last) add_target(tag - 1, v);
+            if (lane < cnt && last)
+                for (int c = 0; c < C::NC; ++c) S.tacc[c][tag - 1] += (double)v[c];
         }
     };
 
@@ -866,8 +851,10 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
     for (int c0 = 0; c0 < qtot || c0 == 0; c0 += TILE_CAP) {
         const int clen = dense ? min(TILE_CAP, qtot - c0) : qtot;
         // ---- stage sources of this chunk: flat over the concatenated pieces,
-        // all loads of a thread issued before any of its LDS stores
+        // all loads of a thread issued before any of its LDS stores; the slot
+        // after the last one gets the sentinel (|s|^2 / 2 = +inf)
         stage_chunk<C>(S, P, dense, c0, clen, za, n2, tid);
+        if (tid == 0) S.sc[clen] = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
         __syncthreads();
 
         // ---- scan: one target at a time over its contiguous stencil range;
@@ -885,35 +872,23 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
                 b = rg >> 16;
             }
             const uint32_t tag = (uint32_t)t << 16;
-            // Each step tests sources [p, p + 128) (slots past b belong to other
-            // slabs, farther than the cutoff, and fail the pair step's exact
-            // test).  The step reads the 128-slot window at pr = min(p, TILE_CAP
-            // - 128), inside the staging arrays; its lanes below p (tested by
-            // the step before, or outside the target's range) and at or past
-            // clen (not staged) get a threshold of -inf, so the hit test is one
-            // compare and its ballot is the compare's lane mask.  Hits are
-            // appended at queue[qn ..) in lane order, those of the first half
-            // first; entry = (t << 16) | source slot.
+            // Each step tests sources [p, p + 128).  Slots past b belong to
+            // other slabs, farther than the cutoff (the pair step's exact test
+            // rejects any that pass the conservative scan test); a lane whose
+            // slot is at or past clen reads the sentinel slot clen instead,
+            // which fails the test.  The hit test is one compare and its ballot
+            // is the compare's lane mask.  Hits are appended at queue[qn ..) in
+            // lane order, those of the first half first; entry = (t << 16) |
+            // source slot.
             for (int p = a; p < b; p += 2 * WAVE) {
-                // a shifted window (p > TILE_CAP - 128) reaches past clen too
-                int pr = p;
-                uint64_t m0 = ~0ull, m1 = ~0ull;  // lanes of each half that take part
-                if (p + 2 * WAVE > clen) {
-                    pr = min(p, TILE_CAP - 2 * WAVE);
-                    const int lo = p - pr, hi = clen - pr;
-                    m0 = lanes_below(hi) & ~lanes_below(lo);
-                    m1 = lanes_below(hi - WAVE) & ~lanes_below(lo - WAVE);
-                }
-                const float thr0 = lane_in(m0) ? thr : -INFINITY;
-                const float thr1 = lane_in(m1) ? thr : -INFINITY;
-                const float4 *win = &S.sc[pr];
-                const float4 s0 = win[lane], s1 = win[WAVE + lane];
+                const int i0 = min(p + lane, clen), i1 = min(p + WAVE + lane, clen);
+                const float4 s0 = S.sc[i0], s1 = S.sc[i1];
                 // (|s|^2 - 2 s.t) / 2 against (rc2s - |t|^2) / 2
                 const float ra = fmaf(-s0.x, tx, fmaf(-s0.y, ty, fmaf(-s0.z, tz, s0.w)));
                 const float rb = fmaf(-s1.x, tx, fmaf(-s1.y, ty, fmaf(-s1.z, tz, s1.w)));
-                const bool ha = ra < thr0, hb = rb < thr1;
+                const bool ha = ra < thr, hb = rb < thr;
                 const uint64_t ma = __builtin_amdgcn_ballot_w64(ha), mb = __builtin_amdgcn_ballot_w64(hb);
-                const uint32_t ea = (tag | (uint32_t)pr) + (uint32_t)lane;
+                const uint32_t ea = (tag | (uint32_t)p) + (uint32_t)lane;
                 const uint32_t ra_ = __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u));
                 const uint32_t rb_ = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
                 if constexpr (C::DRAIN_HALF) {
@@ -937,7 +912,8 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
                 if (qn > 0) batch(0, qn);
                 qn = 0;
                 wave_sum<C::NC>(part);
-                if (lane == WAVE - 1) add_target(t, part);
+                if (lane == WAVE - 1)
+                    for (int c = 0; c < C::NC; ++c) S.tacc[c][t] += (double)part[c];
                 for (int c = 0; c < C::NC; ++c) part[c] = 0;
                 wave_sync();
             }
@@ -951,13 +927,11 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
         if (!dense) break;
     }
 
-    // ---- each target's sums (FP32 sum minus its compensation, in FP64),
-    // written back in the original order
+    // ---- each target's FP64 sums, written back in the original order
     if (tid < ntgt) {
         const int64_t orig = my_orig;
         double res[C::NC];
-        for (int c = 0; c < C::NC; ++c)
-            res[c] = C::F32 ? (double)S.tacc[c][tid] - (double)S.tcmp[c][tid] : (double)S.tacc[c][tid];
+        for (int c = 0; c < C::NC; ++c) res[c] = S.tacc[c][tid];
         if constexpr (BWD) {
             for (int c = 0; c < C::MIN; ++c) P.out0[orig * C::MIN + c] = res[c];
             for (int c = 0; c < 3; ++c) P.out1[orig * 3 + c] = res[C::MIN + c];
@@ -967,22 +941,19 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
     }
 }
 
-// sorted SoA payload: pl[c][j] = rho[perm[j]][c] (c < m_in), then gu.
-// The gather reads one record of M doubles per point at a random position
-// (perm); every load of a thread is issued before its stores.  Forward: the
-// strengths rho[N][M] themselves.  Adjoint: strengths and cotangent are first
-// interleaved into records of MI + MO doubles in the original order (a
-// coalesced pass), so the random reads touch one record instead of two rows.
+// Sorted SoA copy of a per-point array: dst[c][j] = src[perm[j]][c].  Each
+// thread reads one record of M doubles at a random position (perm) and
+// writes M coalesced values; all of its loads are issued before its stores.
 template <int M>
-__global__ void k_gather_payload(const double *__restrict__ rec, const int32_t *__restrict__ perm, int64_t N,
-                                 double *__restrict__ pl)
+__global__ void k_gather_sorted(const double *__restrict__ src, const int32_t *__restrict__ perm, int64_t N,
+                                double *__restrict__ dst)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
     const int64_t i = perm[j];
     double v[M];
     if constexpr (M % 2 == 0) {
-        const double2 *r2 = (const double2 *)(rec + i * M);
+        const double2 *r2 = (const double2 *)(src + i * M);
 #pragma unroll
         for (int c = 0; c < M / 2; ++c) {
             const double2 t = r2[c];
@@ -991,48 +962,10 @@ __global__ void k_gather_payload(const double *__restrict__ rec, const int32_t *
         }
     } else {
 #pragma unroll
-        for (int c = 0; c < M; ++c) v[c] = rec[i * M + c];
+        for (int c = 0; c < M; ++c) v[c] = src[i * M + c];
     }
 #pragma unroll
-    for (int c = 0; c < M; ++c) pl[c * N + j] = v[c];
-}
-
-template <int MI, int MO>
-__global__ void k_interleave(const double *__restrict__ rho, const double *__restrict__ gu, int64_t N,
-                             double *__restrict__ rec)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-#pragma unroll
-    for (int c = 0; c < MI; ++c) rec[i * (MI + MO) + c] = rho[i * MI + c];
-#pragma unroll
-    for (int c = 0; c < MO; ++c) rec[i * (MI + MO) + MI + c] = gu[i * MO + c];
-}
-
-template <int MI, int MO>
-void launch_gather(const double *rho, const double *gu, const int32_t *perm, int64_t N, double *pl, double *rec,
-                   hipStream_t s)
-{
-    const dim3 grid((unsigned)((N + 255) / 256));
-    if constexpr (MO == 0) {
-        hipLaunchKernelGGL((k_gather_payload<MI>), grid, dim3(256), 0, s, rho, perm, N, pl);
-    } else {
-        hipLaunchKernelGGL((k_interleave<MI, MO>), grid, dim3(256), 0, s, rho, gu, N, rec);
-        hipLaunchKernelGGL((k_gather_payload<MI + MO>), grid, dim3(256), 0, s, (const double *)rec, perm, N, pl);
-    }
-}
-
-// sorted SoA payload of the call: strengths, then the cotangent (adjoint);
-// rec = scratch of (m_in + m_out) N doubles for the adjoint's records
-void gather_payload(int kernel, bool bwd, const double *rho, const double *gu, const int32_t *perm, int64_t N,
-                    double *pl, double *rec, hipStream_t s)
-{
-    switch (kernel) {
-    case 0: bwd ? launch_gather<1, 1>(rho, gu, perm, N, pl, rec, s) : launch_gather<1, 0>(rho, gu, perm, N, pl, rec, s); break;
-    case 1: bwd ? launch_gather<3, 3>(rho, gu, perm, N, pl, rec, s) : launch_gather<3, 0>(rho, gu, perm, N, pl, rec, s); break;
-    case 2: bwd ? launch_gather<9, 3>(rho, gu, perm, N, pl, rec, s) : launch_gather<9, 0>(rho, gu, perm, N, pl, rec, s); break;
-    default: bwd ? launch_gather<3, 3>(rho, gu, perm, N, pl, rec, s) : launch_gather<3, 0>(rho, gu, perm, N, pl, rec, s); break;
-    }
+    for (int c = 0; c < M; ++c) dst[c * N + j] = v[c];
 }
 
 }  // namespace dmk
@@ -1043,6 +976,25 @@ namespace {
 
 int m_in_of(int k) { return k == 0 ? 1 : (k == 2 ? 9 : 3); }
 int m_out_of(int k) { return k == 0 ? 1 : 3; }
+
+// sorted SoA copy of m components (1 <= m <= DMK_GATHER_MMAX)
+int gather_m(int m, const double *src, const int32_t *perm, int64_t N, double *dst, hipStream_t s)
+{
+    if (N <= 0) return DMK_OK;
+    if (N > (int64_t)0x3fffffff) return DMK_ESIZE;
+    // one launch of 256-thread workgroups: below 2^32 work-items for the
+    // at most 2^30 - 1 points a binning holds
+    const dim3 grid((unsigned)((N + 255) / 256)), blk(256);
+    switch (m) {
+#define DMK_G(M) \
+    case M: hipLaunchKernelGGL((k_gather_sorted<M>), grid, blk, 0, s, src, perm, N, dst); break;
+        DMK_G(1) DMK_G(2) DMK_G(3) DMK_G(4) DMK_G(5) DMK_G(6) DMK_G(7) DMK_G(8) DMK_G(9) DMK_G(10) DMK_G(11)
+        DMK_G(12)
+#undef DMK_G
+    default: return DMK_EINVAL;
+    }
+    return hipGetLastError() == hipSuccess ? DMK_OK : DMK_EHIP;
+}
 
 int check_call(const dmk_grid *g, const dmk_bins *b, int kernel, int prec, double sigma, double rc)
 {
@@ -1063,12 +1015,34 @@ int check_call(const dmk_grid *g, const dmk_bins *b, int kernel, int prec, doubl
     return DMK_OK;
 }
 
-// workspace: the sorted payload, and for the adjoint the interleaved records
+int check_window(const dmk_pswf *w)
+{
+    if (!w) return DMK_EINVAL;
+    if (!(w->c > 0.0) || !(w->c <= DMK_PSWF_CMAX) || w->nterms64 < 1 || w->nterms64 > DMK_PSWF_MAXTERMS ||
+        w->nterms32 < 1 || w->nterms32 > DMK_PSWF_MAXTERMS32)
+        return DMK_EUNSUPPORTED;
+    return DMK_OK;
+}
+
+// split arguments of a call: the Gaussian of width sigma with cutoff rc
+// (w null), or the PSWF window w of support rc (sigma unused)
+int check_split(const dmk_grid *g, const dmk_bins *b, int kernel, int prec, double sigma, double rc,
+                const dmk_pswf *w)
+{
+    if (w) {
+        const int st = check_window(w);
+        if (st != DMK_OK) return st;
+        sigma = rc;
+    }
+    return check_call(g, b, kernel, prec, sigma, rc);
+}
+
+// workspace of dmk_residual_eval / _backward: the sorted strengths, and for
+// the adjoint the sorted cotangent after them (256-byte aligned)
+size_t ws_part(int64_t N, int m) { return ((size_t)sizeof(double) * m * (size_t)(N > 0 ? N : 1) + 255) & ~(size_t)255; }
 size_t ws_need(int64_t N, int kernel, int backward)
 {
-    const int64_t ncomp = m_in_of(kernel) + (backward ? m_out_of(kernel) : 0);
-    const size_t one = (size_t)(sizeof(double) * ncomp * (N > 0 ? N : 1));
-    return (backward ? 2 * one : one) + 512;
+    return ws_part(N, m_in_of(kernel)) + (backward ? ws_part(N, m_out_of(kernel)) : 0) + 256;
 }
 
 template <int KERN, typename FP, bool BWD, int WIN>
@@ -1116,7 +1090,7 @@ int dispatch(int kernel, int prec, const ResParams &P, const dmk_pswf *w, hipStr
     return hipGetLastError() == hipSuccess ? DMK_OK : DMK_EHIP;
 }
 
-ResParams make_params(const dmk_grid *g, const dmk_bins *b, double sigma, double rc, const double *pl)
+ResParams make_params(const dmk_grid *g, const dmk_bins *b, double sigma, double rc)
 {
     ResParams P{};
     for (int i = 0; i < 3; ++i) {
@@ -1136,48 +1110,85 @@ ResParams make_params(const dmk_grid *g, const dmk_bins *b, double sigma, double
     P.nbr = b->axis_nbr;
     P.img = b->axis_img;
     P.tiles = (const int4 *)b->tiles;
-    P.pl = pl;
     return P;
 }
 
-}  // namespace
-
-// timing events recorded around the pair kernel (see dmk_residual_set_kernel_events)
-static hipEvent_t g_kernel_ev_start = nullptr, g_kernel_ev_stop = nullptr;
-
-extern "C" int dmk_residual_set_kernel_events(hipEvent_t start, hipEvent_t stop)
-{
-    if ((start == nullptr) != (stop == nullptr)) return DMK_EINVAL;
-    g_kernel_ev_start = start;
-    g_kernel_ev_stop = stop;
-    return DMK_OK;
-}
-
-namespace {
-// launch the pair kernel between the optional timing events; w selects the
-// PSWF window (null: Gaussian)
+// the pair kernel alone; w selects the PSWF window (null: Gaussian)
 template <bool BWD>
-int launch_timed(int kernel, int prec, const ResParams &P, const dmk_pswf *w, hipStream_t s)
+int launch_pairs(int kernel, int prec, const ResParams &P, const dmk_pswf *w, hipStream_t s)
 {
-    if (g_kernel_ev_start && hipEventRecord(g_kernel_ev_start, s) != hipSuccess) return DMK_EHIP;
-    int st = DMK_OK;
-    if (P.ntiles > 0) {
-        if (!w) {
-            st = dispatch<BWD, WIN_GAUSS>(kernel, prec, P, w, s);
-        } else {
-            // PSWF: Chebyshev series of 16 / 24 terms (FP32) or 24 / 32 (FP64),
-            // the shortest that holds the window's terms; WIN = terms + 1
-            const bool f32 = prec == DMK_FP32C;
-            const int nt = f32 ? w->nterms32 : w->nterms64;
-            if (f32)
-                st = nt <= 16 ? dispatch<BWD, 17>(kernel, prec, P, w, s) : dispatch<BWD, 25>(kernel, prec, P, w, s);
-            else
-                st = nt <= 24 ? dispatch<BWD, 25>(kernel, prec, P, w, s) : dispatch<BWD, 33>(kernel, prec, P, w, s);
-        }
-    }
-    if (st == DMK_OK && g_kernel_ev_stop && hipEventRecord(g_kernel_ev_stop, s) != hipSuccess) return DMK_EHIP;
-    return st;
+    if (P.ntiles <= 0) return DMK_OK;
+    if (!w) return dispatch<BWD, WIN_GAUSS>(kernel, prec, P, w, s);
+    // PSWF: Chebyshev series of 16 / 24 terms (FP32) or 24 / 32 (FP64), the
+    // shortest that holds the window's terms; WIN = terms + 1
+    if (prec == DMK_FP32C)
+        return w->nterms32 <= 16 ? dispatch<BWD, 17>(kernel, prec, P, w, s) : dispatch<BWD, 25>(kernel, prec, P, w, s);
+    return w->nterms64 <= 24 ? dispatch<BWD, 25>(kernel, prec, P, w, s) : dispatch<BWD, 33>(kernel, prec, P, w, s);
 }
+
+int eval_sorted_impl(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma, double rc,
+                     const dmk_pswf *w, const double *rho_s, double *u, hipStream_t stream)
+{
+    const int st = check_split(grid, bins, kernel, prec, sigma, rc, w);
+    if (st != DMK_OK) return st;
+    if (bins->N == 0) return DMK_OK;
+    if (!rho_s || !u) return DMK_EINVAL;
+    ResParams P = make_params(grid, bins, w ? rc : sigma, rc);
+    P.pl = rho_s;
+    P.out0 = u;
+    return launch_pairs<false>(kernel, prec, P, w, stream);
+}
+
+int backward_sorted_impl(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma, double rc,
+                         const dmk_pswf *w, const double *rho_s, const double *gu_s, double *grad_rho,
+                         double *grad_x, hipStream_t stream)
+{
+    const int st = check_split(grid, bins, kernel, prec, sigma, rc, w);
+    if (st != DMK_OK) return st;
+    if (bins->N == 0) return DMK_OK;
+    if (!rho_s || !gu_s || !grad_rho || !grad_x) return DMK_EINVAL;
+    ResParams P = make_params(grid, bins, w ? rc : sigma, rc);
+    P.pl = rho_s;
+    P.pg = gu_s;
+    P.out0 = grad_rho;
+    P.out1 = grad_x;
+    return launch_pairs<true>(kernel, prec, P, w, stream);
+}
+
+// gather + pair kernel, the workspace holding the sorted payload
+int eval_impl(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma, double rc,
+              const dmk_pswf *w, const double *rho, double *u, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    const int st = check_split(grid, bins, kernel, prec, sigma, rc, w);
+    if (st != DMK_OK) return st;
+    const int64_t N = bins->N;
+    if (N == 0) return DMK_OK;
+    if (!rho || !u || !ws) return DMK_EINVAL;
+    if (ws_bytes < ws_need(N, kernel, 0)) return DMK_ESIZE;
+    double *pl = (double *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    const int g = gather_m(m_in_of(kernel), rho, bins->perm, N, pl, stream);
+    if (g != DMK_OK) return g;
+    return eval_sorted_impl(grid, bins, kernel, prec, sigma, rc, w, pl, u, stream);
+}
+
+int backward_impl(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma, double rc,
+                  const dmk_pswf *w, const double *rho, const double *gu, double *grad_rho, double *grad_x,
+                  void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    const int st = check_split(grid, bins, kernel, prec, sigma, rc, w);
+    if (st != DMK_OK) return st;
+    const int64_t N = bins->N;
+    if (N == 0) return DMK_OK;
+    if (!rho || !gu || !grad_rho || !grad_x || !ws) return DMK_EINVAL;
+    if (ws_bytes < ws_need(N, kernel, 1)) return DMK_ESIZE;
+    double *pl = (double *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    double *pg = (double *)((char *)pl + ws_part(N, m_in_of(kernel)));
+    int g = gather_m(m_in_of(kernel), rho, bins->perm, N, pl, stream);
+    if (g == DMK_OK) g = gather_m(m_out_of(kernel), gu, bins->perm, N, pg, stream);
+    if (g != DMK_OK) return g;
+    return backward_sorted_impl(grid, bins, kernel, prec, sigma, rc, w, pl, pg, grad_rho, grad_x, stream);
+}
+
 }  // namespace
 
 extern "C" size_t dmk_residual_ws_bytes(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec,
@@ -1189,59 +1200,13 @@ extern "C" size_t dmk_residual_ws_bytes(const dmk_grid *grid, const dmk_bins *bi
     return ws_need(bins->N, kernel, backward);
 }
 
-namespace {
-
-// shared by the Gaussian and PSWF entry points (w null: Gaussian split of
-// width sigma with cutoff rc; else the PSWF split, sigma = rc = nu)
-int eval_impl(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma, double rc,
-              const dmk_pswf *w, const double *rho, double *u, void *ws, size_t ws_bytes, hipStream_t stream)
+extern "C" int dmk_gather_sorted(const dmk_bins *bins, int m, const double *src, double *dst, hipStream_t stream)
 {
-    int rc_ = check_call(grid, bins, kernel, prec, sigma, rc);
-    if (rc_ != DMK_OK) return rc_;
-    const int64_t N = bins->N;
-    if (N == 0) return DMK_OK;
-    if (!rho || !u || !ws) return DMK_EINVAL;
-    if (ws_bytes < ws_need(N, kernel, 0)) return DMK_ESIZE;
-    double *pl = (double *)ws;
-    gather_payload(kernel, false, rho, nullptr, bins->perm, N, pl, nullptr, stream);
-    if (hipGetLastError() != hipSuccess) return DMK_EHIP;
-    ResParams P = make_params(grid, bins, sigma, rc, pl);
-    P.out0 = u;
-    return launch_timed<false>(kernel, prec, P, w, stream);
+    if (!bins || m < 1 || m > DMK_GATHER_MMAX) return DMK_EINVAL;
+    if (bins->N == 0) return DMK_OK;
+    if (!bins->perm || !src || !dst) return DMK_EINVAL;
+    return gather_m(m, src, bins->perm, bins->N, dst, stream);
 }
-
-int backward_impl(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma, double rc,
-                  const dmk_pswf *w, const double *rho, const double *gu, double *grad_rho, double *grad_x,
-                  void *ws, size_t ws_bytes, hipStream_t stream)
-{
-    int rc_ = check_call(grid, bins, kernel, prec, sigma, rc);
-    if (rc_ != DMK_OK) return rc_;
-    const int64_t N = bins->N;
-    if (N == 0) return DMK_OK;
-    if (!rho || !gu || !grad_rho || !grad_x || !ws) return DMK_EINVAL;
-    if (ws_bytes < ws_need(N, kernel, 1)) return DMK_ESIZE;
-    double *pl = (double *)ws;
-    // records after the payload, 256-byte aligned
-    const size_t one = sizeof(double) * (size_t)(m_in_of(kernel) + m_out_of(kernel)) * (size_t)N;
-    double *rec = (double *)(((uintptr_t)ws + one + 255) & ~(uintptr_t)255);
-    gather_payload(kernel, true, rho, gu, bins->perm, N, pl, rec, stream);
-    if (hipGetLastError() != hipSuccess) return DMK_EHIP;
-    ResParams P = make_params(grid, bins, sigma, rc, pl);
-    P.out0 = grad_rho;
-    P.out1 = grad_x;
-    return launch_timed<true>(kernel, prec, P, w, stream);
-}
-
-int check_window(const dmk_pswf *w)
-{
-    if (!w) return DMK_EINVAL;
-    if (!(w->c > 0.0) || !(w->c <= DMK_PSWF_CMAX) || w->nterms64 < 1 || w->nterms64 > DMK_PSWF_MAXTERMS ||
-        w->nterms32 < 1 || w->nterms32 > DMK_PSWF_MAXTERMS32)
-        return DMK_EUNSUPPORTED;
-    return DMK_OK;
-}
-
-}  // namespace
 
 extern "C" int dmk_residual_eval(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma,
                                  double rc, const double *rho, double *u, void *ws, size_t ws_bytes,
@@ -1262,8 +1227,7 @@ extern "C" int dmk_residual_eval_pswf(const dmk_grid *grid, const dmk_bins *bins
                                       const dmk_pswf *w, double nu, const double *rho, double *u, void *ws,
                                       size_t ws_bytes, hipStream_t stream)
 {
-    const int st = check_window(w);
-    if (st != DMK_OK) return st;
+    if (!w) return DMK_EINVAL;
     return eval_impl(grid, bins, kernel, prec, nu, nu, w, rho, u, ws, ws_bytes, stream);
 }
 
@@ -1272,7 +1236,22 @@ extern "C" int dmk_residual_backward_pswf(const dmk_grid *grid, const dmk_bins *
                                           double *grad_rho, double *grad_x, void *ws, size_t ws_bytes,
                                           hipStream_t stream)
 {
-    const int st = check_window(w);
-    if (st != DMK_OK) return st;
+    if (!w) return DMK_EINVAL;
     return backward_impl(grid, bins, kernel, prec, nu, nu, w, rho, gu, grad_rho, grad_x, ws, ws_bytes, stream);
+}
+
+extern "C" int dmk_residual_eval_sorted(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec,
+                                        double sigma, double rc, const dmk_pswf *w, const double *rho_sorted,
+                                        double *u, hipStream_t stream)
+{
+    return eval_sorted_impl(grid, bins, kernel, prec, sigma, rc, w, rho_sorted, u, stream);
+}
+
+extern "C" int dmk_residual_backward_sorted(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec,
+                                            double sigma, double rc, const dmk_pswf *w, const double *rho_sorted,
+                                            const double *gu_sorted, double *grad_rho, double *grad_x,
+                                            hipStream_t stream)
+{
+    return backward_sorted_impl(grid, bins, kernel, prec, sigma, rc, w, rho_sorted, gu_sorted, grad_rho, grad_x,
+                                stream);
 }

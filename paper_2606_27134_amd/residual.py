@@ -169,6 +169,56 @@ def residual_backward(bins: Bins, kernel, prec, sigma: float, rc: float, rho: to
     return grho, gx
 
 
+def gather_sorted(bins: Bins, src: torch.Tensor, out=None) -> torch.Tensor:
+    """Sorted SoA copy dst[m, N] (dst[c][j] = src[perm[j]][c]) of src[N, m]."""
+    if src.dim() != 2 or src.shape[0] != bins.N:
+        raise ValueError("src must be [N, m] with N = %d" % bins.N)
+    _require_dev_f64(src, "src")
+    m = int(src.shape[1])
+    dst = out if out is not None else torch.empty((m, bins.N), dtype=torch.float64, device=src.device)
+    _require_dev_f64(dst, "dst", (m, bins.N))
+    code = L.dmk_gather_sorted(bins.c, m, src.data_ptr(), dst.data_ptr(), _stream())
+    if code != L.DMK_OK:
+        raise L.DmkError(code, "dmk_gather_sorted")
+    return dst
+
+
+def residual_eval_sorted(bins: Bins, kernel, prec, sigma: float, rc: float, rho_sorted: torch.Tensor, out=None,
+                         pswf_c: float = None):
+    """Pair kernel alone on sorted strengths rho_sorted[m_in, N]; u[N, m_out]
+    in the original order."""
+    k, p = _kid(kernel), _pid(prec)
+    _require_dev_f64(rho_sorted, "rho_sorted", (L.M_IN[k], bins.N))
+    u = out if out is not None else torch.empty((bins.N, L.M_OUT[k]), dtype=torch.float64,
+                                                device=rho_sorted.device)
+    _require_dev_f64(u, "u", (bins.N, L.M_OUT[k]))
+    w = pswf_window(pswf_c) if pswf_c is not None else None
+    code = L.dmk_residual_eval_sorted(bins.grid, bins.c, k, p, sigma, rc, w, rho_sorted.data_ptr(), u.data_ptr(),
+                                      _stream())
+    if code != L.DMK_OK:
+        raise L.DmkError(code, "dmk_residual_eval_sorted")
+    return u
+
+
+def residual_backward_sorted(bins: Bins, kernel, prec, sigma: float, rc: float, rho_sorted: torch.Tensor,
+                             gu_sorted: torch.Tensor, out=None, pswf_c: float = None):
+    """Adjoint pair kernel alone on sorted strengths and cotangent."""
+    k, p = _kid(kernel), _pid(prec)
+    _require_dev_f64(rho_sorted, "rho_sorted", (L.M_IN[k], bins.N))
+    _require_dev_f64(gu_sorted, "gu_sorted", (L.M_OUT[k], bins.N))
+    if out is None:
+        grho = torch.empty((bins.N, L.M_IN[k]), dtype=torch.float64, device=rho_sorted.device)
+        gx = torch.empty((bins.N, 3), dtype=torch.float64, device=rho_sorted.device)
+    else:
+        grho, gx = out
+    w = pswf_window(pswf_c) if pswf_c is not None else None
+    code = L.dmk_residual_backward_sorted(bins.grid, bins.c, k, p, sigma, rc, w, rho_sorted.data_ptr(),
+                                          gu_sorted.data_ptr(), grho.data_ptr(), gx.data_ptr(), _stream())
+    if code != L.DMK_OK:
+        raise L.DmkError(code, "dmk_residual_backward_sorted")
+    return grho, gx
+
+
 @dataclass
 class ResidualSpec:
     """Problem description for :class:`DmkResidual`."""
@@ -188,7 +238,9 @@ class DmkResidual(torch.autograd.Function):
     forward(x[N,3], rho[N,m_in], spec, bins=None) -> u[N,m_out]; backward
     gives (grad_x, grad_rho) from the library's adjoint kernel.  The points
     are binned on every forward call unless a Bins built from these exact
-    positions is passed in (then the caller vouches that it matches x).
+    positions is passed in (then the caller vouches that it matches x).  The
+    forward keeps the strengths in the sorted order, so the backward gathers
+    only the cotangent.
     """
 
     @staticmethod
@@ -199,18 +251,20 @@ class DmkResidual(torch.autograd.Function):
             bins = tree_bin(spec.L, spec.D, spec.n, x_)
         elif bins.N != x_.shape[0]:
             raise ValueError("bins were built for %d points, x has %d" % (bins.N, x_.shape[0]))
-        u = residual_eval(bins, spec.kernel, spec.prec, spec.sigma, spec.rc, rho_, pswf_c=spec.pswf_c)
+        rho_s = gather_sorted(bins, rho_)
+        u = residual_eval_sorted(bins, spec.kernel, spec.prec, spec.sigma, spec.rc, rho_s, pswf_c=spec.pswf_c)
         ctx.spec = spec
         ctx.bins = bins
-        ctx.save_for_backward(rho_)
+        ctx.save_for_backward(rho_s)
         return u
 
     @staticmethod
     def backward(ctx, gu):
-        (rho_,) = ctx.saved_tensors
+        (rho_s,) = ctx.saved_tensors
         s = ctx.spec
-        grho, gx = residual_backward(ctx.bins, s.kernel, s.prec, s.sigma, s.rc, rho_, gu.contiguous(),
-                                     pswf_c=s.pswf_c)
+        gu_s = gather_sorted(ctx.bins, gu.contiguous())
+        grho, gx = residual_backward_sorted(ctx.bins, s.kernel, s.prec, s.sigma, s.rc, rho_s, gu_s,
+                                            pswf_c=s.pswf_c)
         return gx, grho, None, None
 
 

@@ -98,11 +98,36 @@ def test_workspace_sizes_grow_with_components():
     assert L.dmk_residual_ws_bytes(g, b, 2, 0, 1) > L.dmk_residual_ws_bytes(g, b, 0, 0, 0)
 
 
-def test_kernel_events_argument_check():
-    # one event without the other is rejected; two null events clear the hook
-    assert L.dmk_residual_set_kernel_events(1 << 40, 0) == L.DMK_EINVAL
-    assert L.dmk_residual_set_kernel_events(0, 1 << 40) == L.DMK_EINVAL
-    assert L.dmk_residual_set_kernel_events(0, 0) == L.DMK_OK
+def test_library_keeps_no_timing_hook():
+    # the library records no events of its own: a caller times a pair kernel
+    # with its own events around dmk_residual_eval_sorted / _backward_sorted
+    assert not hasattr(L.load(), "dmk_residual_set_kernel_events")
+
+
+def test_sorted_entry_points_argument_errors_before_launch():
+    g, b = _carved()
+    P = 1 << 41
+    assert L.dmk_gather_sorted(b, 0, P, P, 0) == L.DMK_EINVAL
+    assert L.dmk_gather_sorted(b, L.GATHER_MMAX + 1, P, P, 0) == L.DMK_EINVAL
+    assert L.dmk_gather_sorted(b, 3, 0, P, 0) == L.DMK_EINVAL
+    assert L.dmk_gather_sorted(b, 3, P, 0, 0) == L.DMK_EINVAL
+    big = L.dmk_bins()
+    big.N, big.perm = 1 << 30, P
+    assert L.dmk_gather_sorted(big, 1, P, P, 0) == L.DMK_ESIZE
+    # split arguments as in dmk_residual_eval
+    assert L.dmk_residual_eval_sorted(g, b, 0, 0, 0.05, 0.3, None, P, P, 0) == L.DMK_ECUTOFF
+    assert L.dmk_residual_eval_sorted(g, b, 0, 0, -1.0, 0.1, None, P, P, 0) == L.DMK_ECUTOFF
+    assert L.dmk_residual_eval_sorted(g, b, 7, 0, 0.05, 0.1, None, P, P, 0) == L.DMK_EUNSUPPORTED
+    assert L.dmk_residual_eval_sorted(g, b, 0, 0, 0.05, 0.1, None, 0, P, 0) == L.DMK_EINVAL
+    assert L.dmk_residual_eval_sorted(g, b, 0, 0, 0.05, 0.1, None, P, 0, 0) == L.DMK_EINVAL
+    assert L.dmk_residual_backward_sorted(g, b, 1, 1, 0.05, 0.1, None, P, 0, P, P, 0) == L.DMK_EINVAL
+    assert L.dmk_residual_backward_sorted(g, b, 1, 1, 0.05, 0.1, None, P, P, 0, P, 0) == L.DMK_EINVAL
+    # with a PSWF window sigma is not used, the support rc still is
+    w = L.dmk_pswf()
+    assert L.dmk_pswf_window(14.5, w) == L.DMK_OK
+    assert L.dmk_residual_eval_sorted(g, b, 0, 0, -1.0, 0.1, w, 0, P, 0) == L.DMK_EINVAL
+    assert L.dmk_residual_eval_sorted(g, b, 0, 0, -1.0, 0.3, w, P, P, 0) == L.DMK_ECUTOFF
+    assert L.dmk_residual_eval_sorted(g, b, 0, 0, 0.05, 0.1, L.dmk_pswf(), P, P, 0) == L.DMK_EUNSUPPORTED
 
 
 def test_pswf_window_host_matches_oracle_window():
