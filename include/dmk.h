@@ -32,7 +32,8 @@
  *  - All pointers named "dev" are device pointers on the current HIP device.
  *    The caller owns every byte: the library allocates nothing and keeps no
  *    global state, so calls on different streams with different arenas are
- *    independent.
+ *    independent.  The one exception is dmk_residual_eval_noalloc (below),
+ *    whose workspace is a device array of the library itself.
  *  - User-facing arrays are row-major in the ORIGINAL point order and FP64:
  *      x[N][3], rho[N][m_in], u[N][m_out], grad_rho[N][m_in], grad_x[N][3]
  *    with (m_in, m_out) = (1,1) Laplace, (3,3) Stokeslet, (9,3) stresslet
@@ -221,6 +222,25 @@ int dmk_residual_eval_sorted(const dmk_grid *grid, const dmk_bins *bins, int ker
 int dmk_residual_backward_sorted(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma,
                                  double rc, const dmk_pswf *w, const double *rho_sorted, const double *gu_sorted,
                                  double *grad_rho, double *grad_x, hipStream_t stream);
+
+/*
+ * dmk_residual_eval for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments and results as dmk_residual_eval (the same
+ * kernels, bit-identical u), without a workspace argument.  The sorted
+ * strengths go to a device array of the library, DMK_NOALLOC_WS_BYTES bytes
+ * that each GPU the library runs on holds from its first such call (the
+ * array's address is looked up then, once per device) until the process
+ * ends.  The call allocates nothing.  Errors: those of dmk_residual_eval, and
+ * DMK_ESIZE when dmk_residual_ws_bytes(.., 0) exceeds the array, i.e. for
+ * N > 8,388,576 Laplace, > 2,796,192 Stokeslet or rotlet, > 932,064 stresslet
+ * points.  All calls on one GPU share its array: calls that overlap
+ * on one GPU (other streams, other host threads) race and must not be issued.
+ * Asynchronous on `stream`.
+ */
+#define DMK_NOALLOC_WS_BYTES (64 << 20)
+int dmk_residual_eval_noalloc(const dmk_grid *grid, const dmk_bins *bins, int kernel, int prec, double sigma,
+                              double rc, const double *rho, double *u, hipStream_t stream);
 
 /* Static description of a status code. */
 const char *dmk_strerror(int status);

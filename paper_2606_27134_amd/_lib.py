@@ -51,6 +51,7 @@ FAR_PMAX = 64
 FAR_MMAX = 4096
 FAR_KMAX = 1024
 GATHER_MMAX = 12
+NOALLOC_WS_BYTES = 64 << 20
 
 
 class DmkError(RuntimeError):
@@ -113,6 +114,9 @@ def load():
     lib.dmk_residual_backward_sorted.argtypes = [G, B, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                                  ctypes.c_double, W, P, P, P, P, P]
     lib.dmk_residual_backward_sorted.restype = ctypes.c_int
+    lib.dmk_residual_eval_noalloc.argtypes = [G, B, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                              P, P, P]
+    lib.dmk_residual_eval_noalloc.restype = ctypes.c_int
     F = ctypes.POINTER(dmk_far_grid)
     lib.dmk_far3p_ws_bytes.argtypes = [F, ctypes.c_int]
     lib.dmk_far3p_ws_bytes.restype = ctypes.c_size_t
@@ -228,6 +232,12 @@ def dmk_residual_backward_sorted(grid, bins, kernel, prec, sigma, rc, w, rho_s_p
                                                    ctypes.c_void_p(rho_s_ptr), ctypes.c_void_p(gu_s_ptr),
                                                    ctypes.c_void_p(grho_ptr), ctypes.c_void_p(gx_ptr),
                                                    ctypes.c_void_p(stream)))
+
+
+def dmk_residual_eval_noalloc(grid, bins, kernel, prec, sigma, rc, rho_ptr, u_ptr, stream) -> int:
+    return int(load().dmk_residual_eval_noalloc(ctypes.byref(grid), ctypes.byref(bins), int(kernel), int(prec),
+                                                float(sigma), float(rc), ctypes.c_void_p(rho_ptr),
+                                                ctypes.c_void_p(u_ptr), ctypes.c_void_p(stream)))
 
 
 def make_far_grid(L, M, p, K) -> dmk_far_grid:

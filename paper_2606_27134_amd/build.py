@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdmkloc.so")
-SOURCES = ["dmk_bin.hip", "dmk_residual.hip", "dmk_far.hip", "dmk_cheb.hip", "dmk_pswf.cpp"]
+SOURCES = ["dmk_bin.hip", "dmk_residual.hip", "dmk_far.hip", "dmk_cheb.hip", "dmk_pswf.cpp", "dmk_noalloc.hip"]
 ARCH = os.environ.get("DMK_OFFLOAD_ARCH", "gfx950")
 
 
