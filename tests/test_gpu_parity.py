@@ -218,7 +218,7 @@ def test_full_size_sampled(name, kernel, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
-@pytest.mark.parametrize("name,kernel", [("laplace_n1m", "laplace"), ("stokeslet_n500k_clustered", "stokeslet")])
+@pytest.mark.parametrize("name,kernel", FULL)
 def test_full_size_backward_sampled(name, kernel, prec):
     w = W.make(name, kernel=kernel)
     print("full bwd", name, kernel, prec, flush=True)
