@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -344,20 +345,24 @@ def autograd_step(w, prec, steps, warmup):
 def _far_flops(M, p, K):
     """Algorithmic flops of one root-level far field on an exact tiling of
     M_i cubes, counting the form the library runs on each axis: the direct
-    contraction over the grid index, or (8 or more cubes, when it at least
-    halves the terms) the DFT over the cube index plus the fold over the
-    Chebyshev index.  Complex multiply-add 8, real by complex or real part
-    only 4."""
+    contraction over the grid index, or (8 or more cubes) the DFT over the
+    cube index plus the fold over the Chebyshev index, the DFT as a dense
+    product below 65 cubes (when it at least halves the terms) and as an FFT
+    (5 M log2 M per transform) from 65 on.  Complex multiply-add 8, real by
+    complex or real part only 4."""
     G = [m * p for m in M]
     Wn = [2 * k + 1 for k in K]
-    fac = [8 <= m <= 512 and 2 * (m * m + w) <= w * m for m, w in zip(M, Wn)]
+    fft = [m >= 65 for m in M]
+    fac = [f or (8 <= m and 2 * (m * m + w) <= w * m) for f, m, w in zip(fft, M, Wn)]
     # (A, C) around each axis: axis 2 on [g0][g1][.], axis 1 on [g0][.][n2], axis 0 on [.][n1][n2]
     cols = {2: (G[0] * G[1], 1), 1: (G[0], Wn[2]), 0: (1, Wn[1] * Wn[2])}
     fl = 0.0
     for ax, first_or_last in ((2, True), (1, False), (0, False)):
         A, C = cols[ax]
         half = 4.0 if first_or_last else 8.0  # real input (forward) / real part (evaluation)
-        if fac[ax]:
+        if fft[ax]:
+            fl += 2 * (5.0 * M[ax] * math.log2(M[ax]) * A * p * C + 8.0 * A * Wn[ax] * p * C)
+        elif fac[ax]:
             fl += 2 * (half * A * M[ax] * M[ax] * p * C + 8.0 * A * Wn[ax] * p * C)
         else:
             fl += 2 * half * A * G[ax] * Wn[ax] * C
@@ -378,7 +383,11 @@ def far_leaf_leg(args):
     rng = np.random.default_rng(2026)
     for name, Lv, M in (("cube", (1.0, 1.0, 1.0), (1, 1, 1)), ("cuboid_32x1x1", (32.0, 1.0, 1.0), (32, 1, 1)),
                         ("cuboid_1x1x32", (1.0, 1.0, 32.0), (1, 1, 32)),
-                        ("cuboid_128x1x1", (128.0, 1.0, 1.0), (128, 1, 1))):
+                        ("cuboid_128x1x1", (128.0, 1.0, 1.0), (128, 1, 1)),
+                        ("cuboid_256x1x1", (256.0, 1.0, 1.0), (256, 1, 1)),
+                        ("cuboid_1024x1x1", (1024.0, 1.0, 1.0), (1024, 1, 1)),
+                        ("cuboid_4096x1x1", (4096.0, 1.0, 1.0), (4096, 1, 1)),
+                        ("cuboid_1x1x256", (1.0, 1.0, 256.0), (1, 1, 256))):
         p, c = 38, 29.0
         K = F.table_modes(c, Lv, 1.0)
         G = [m * p for m in M]
@@ -386,10 +395,14 @@ def far_leaf_leg(args):
         u = torch.empty_like(rho)
         nb = L.dmk_far3p_ws_bytes(L.make_far_grid(Lv, M, p, K), 0)
         ws = torch.empty(nb // 8 + 32, dtype=torch.float64, device="cuda")
-        ms = _time_ms(lambda: F.far3p_eval(Lv, M, p, K, "laplace", 1.0, rho, pswf_c=c, out=u, ws=ws), 20)
+        ms = _time_ms(lambda: F.far3p_eval(Lv, M, p, K, "laplace", 1.0, rho, pswf_c=c, out=u, ws=ws),
+                      20 if max(M) <= 256 else 5)
         fl = _far_flops(M, p, K)
         out["far3p_" + name] = {"L": list(Lv), "cubes": list(M), "p": p, "c": c, "K": list(K), "ms": ms,
+                                "ms_per_cube": ms / (M[0] * M[1] * M[2]),
                                 "gflops": fl / (ms * 1e-3) / 1e9, "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / 78.6}
+        del rho, u, ws
+        torch.cuda.empty_cache()
     # leaf grids: 100k uniform points on an 8^3 tiling, p = 20 (the 1e-6 order)
     N, n, p = 100_000, (8, 8, 8), 20
     x = torch.as_tensor(rng.random((N, 3))).cuda()

@@ -278,6 +278,14 @@ const char *dmk_version(void);
  * sigma0 (win from dmk_pswf_window).  The stresslet's extra k = 0
  * compensation term is not included.
  *
+ * Both sums factor over the axes (sum factorization).  On an exact tiling,
+ * an axis of 8 or more cubes factors further through a DFT over the cube
+ * index (Sec. 4, large aspect ratios): a dense product up to 64 cubes, an
+ * FFT (O(M_i log M_i) per column) from 65 cubes on, for any M_i up to
+ * DMK_FAR_MMAX (Bluestein's convolution when M_i has a prime factor above
+ * 8).  Such an axis needs only the first cube's phase table, so the
+ * workspace grows linearly in M_i.
+ *
  * Layout (dev, FP64): rho_grid[m_in][G0][G1][G2], u_grid[m_out][G0][G1][G2]
  * (last index fastest).  `ws` is a device workspace of >= dmk_far3p_ws_bytes
  * bytes.  Asynchronous on `stream`; u_grid is fully overwritten.  Errors:
@@ -291,7 +299,7 @@ const char *dmk_version(void);
  */
 #define DMK_FAR_PMAX 64
 #define DMK_FAR_MMAX 4096
-#define DMK_FAR_KMAX 1024
+#define DMK_FAR_KMAX 65536
 
 typedef struct {
     double L[3];

@@ -566,7 +566,7 @@ int oracle_far_3p(int kern, const double L[3], double sigma, const int32_t K[3],
 {
     if (kern < 0 || kern > 3 || !(sigma > 0.0) || ns < 0 || nt < 0) return 1;
     for (int i = 0; i < 3; i++)
-        if (!(L[i] > 0.0) || K[i] < 0 || K[i] > 4096) return 1;
+        if (!(L[i] > 0.0) || K[i] < 0 || K[i] > 65536) return 1;
     const int mi = m_in_of(kern), mo = m_out_of(kern);
     const long double V = (long double)L[0] * L[1] * L[2];
     const int64_t w0 = 2 * K[0] + 1, w1 = 2 * K[1] + 1, w2 = 2 * K[2] + 1;

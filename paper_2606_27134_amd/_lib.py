@@ -49,7 +49,7 @@ class dmk_far_grid(ctypes.Structure):
 
 FAR_PMAX = 64
 FAR_MMAX = 4096
-FAR_KMAX = 1024
+FAR_KMAX = 65536
 GATHER_MMAX = 12
 NOALLOC_WS_BYTES = 64 << 20
 

@@ -17,10 +17,12 @@
 //
 //   Y[a][o][c] = s * sum_i coef(i, o) X[a][i][c]
 //
-// with coef a view of one of the E_i tables.  Summing over the cubes of an
-// axis directly costs O(M_i^2) instead of the O(M_i log M_i) of a DFT over the
-// cube index; at the cube counts of elongated cells (tens) the direct form is
-// a few tens of microseconds on the GPU.
+// with coef a view of one of the E_i tables.  On a cover of the cell by cut
+// cubes every contraction is such a direct sum.  On an exact tiling, an axis
+// of 8 or more cubes factors through a DFT over the cube index (Sec. 4, large
+// aspect ratios): a dense product on the matrix cores up to 64 cubes, an FFT
+// (mixed-radix Stockham stages, or Bluestein's chirp convolution for lengths
+// with a prime factor above 8) beyond, O(M_i log M_i) per column.
 //
 // The mollified kernels in Fourier space (App. A convention) are
 //   harmonic   Hhat = phihat(|k| sigma) / k^2                 eq. (Hhatsplit_wfunc)
@@ -46,16 +48,34 @@ namespace {
 
 constexpr int GL_N = 16;  // Gauss-Legendre nodes per quadrature panel
 
+constexpr int FFT_MAXST = 24;   // radix stages of one FFT (lengths up to 2^24)
+constexpr int FFT_MIN = 65;     // cube-index DFTs of this length or more run as FFTs
+
+// A length-N FFT as Stockham stages of radix 2 .. 8, or (N with a prime
+// factor above 8) Bluestein's convolution through FFTs of length N2, the
+// power of two >= 2 N - 1.
+struct FftPlan {
+    int n;                  // transform length (the axis' cube count)
+    int n2;                 // Bluestein: padded length (0: plain Stockham)
+    int nst, rad[FFT_MAXST];  // stages of the length-n (or n2) FFT
+    int64_t twoff;          // w^k = exp(2 pi i k / len), k < len (len = n, or n2)
+    int64_t choff, hoff;    // Bluestein: chirp c_k = exp(-pi i k^2 / n), k < n; H = FFT(h), n2 entries
+};
+
 struct FarGeom {
     int G[3], W[3], K[3], M[3], p;
     double L[3];
     int cover;        // 1: cubes of side h0 = min L_i cover the cell, the last cut by a face
     double hr[3];     // h0 / L_i (cover)
+    int rows[3];      // grid points with phase-table rows: G_i, or p (the first cube, fac)
     int64_t eoff[3];  // offset of E_i in the table array (double2 entries)
     int fac[3];       // 1: the sums along axis i factor through a length-M_i DFT over the cube index
-    int64_t doff[3];  // offset of D_i[b][r] = exp(2 pi i r b / M_i) in the table array (fac)
+    int fft[3];       // 1: that DFT runs as an FFT (M_i >= FFT_MIN), else as a dense product
+    int64_t doff[3];  // offset of D_i[b][r] = exp(2 pi i r b / M_i) in the table array (dense DFT)
     int64_t foff[3];  // offset of FT_i[n][j] = E_i[j][n], j < p: the first cube's rows transposed (fac)
-    int64_t nE, nD;   // set-up entries of the phase tables (one per n >= 0) and of the D_i
+    FftPlan pl[3];    // FFT of the cube index (fft)
+    int64_t nE, nD;   // set-up entries of the phase tables (one per n >= 0) and of the other tables
+    int64_t ntab;     // double2 entries of all tables
 };
 
 struct FarWin {
@@ -74,26 +94,53 @@ struct FarWin {
 __device__ inline void far_table_entry(const FarGeom &g, double2 *__restrict__ E, int64_t t)
 {
     if (t >= g.nE) {
-        // DFT tables of the factored axes, the phase reduced mod M_i exactly
+        // tables of the factored axes: D (dense DFT) or the FFT's twiddles,
+        // and for Bluestein the chirp and h (transformed into H after set-up);
+        // every phase is reduced mod its period exactly in integers
         int64_t r = t - g.nE;
         for (int ax = 0; ax < 3; ++ax) {
             if (!g.fac[ax]) continue;
             const int64_t m = g.M[ax];
-            if (r < m * m) {
-                const int64_t q = ((r / m) * (r % m)) % m;
+            if (!g.fft[ax]) {
+                if (r < m * m) {
+                    const int64_t q = ((r / m) * (r % m)) % m;
+                    double s, c;
+                    sincospi(2.0 * (double)q / (double)m, &s, &c);
+                    E[g.doff[ax] + r] = make_double2(c, s);
+                    return;
+                }
+                r -= m * m;
+                continue;
+            }
+            const FftPlan &pl = g.pl[ax];
+            const int64_t len = pl.n2 ? pl.n2 : pl.n;
+            if (r < len) {  // w^r = exp(2 pi i r / len)
                 double s, c;
-                sincospi(2.0 * (double)q / (double)m, &s, &c);
-                E[g.doff[ax] + r] = make_double2(c, s);
+                sincospi(2.0 * (double)r / (double)len, &s, &c);
+                E[pl.twoff + r] = make_double2(c, s);
                 return;
             }
-            r -= m * m;
+            r -= len;
+            if (!pl.n2) continue;
+            if (r < pl.n2) {
+                // chirp c_k = exp(-pi i k^2 / n) (k < n) and h_k = conj(c_|k|) on
+                // the circle of length n2 (zero between n and n2 - n)
+                const int64_t k = r;
+                const int64_t kk = k < pl.n ? k : (pl.n2 - k < pl.n ? pl.n2 - k : -1);
+                double s = 0.0, c = 0.0;
+                if (kk >= 0) sincospi((double)((kk * kk) % (2 * m)) / (double)m, &s, &c);
+                if (k < pl.n) E[pl.choff + k] = make_double2(c, -s);
+                E[pl.hoff + k] = kk >= 0 ? make_double2(c, s) : make_double2(0.0, 0.0);
+                return;
+            }
+            r -= pl.n2;
         }
         return;
     }
     int ax = 0;
     int64_t r = t;
-    while (ax < 3 && r >= (int64_t)g.G[ax] * (g.K[ax] + 1)) {
-        r -= (int64_t)g.G[ax] * (g.K[ax] + 1);
+    while (ax < 3 && r >= (int64_t)g.rows[ax] * (g.K[ax] + 1)) {
+        r -= (int64_t)g.rows[ax] * (g.K[ax] + 1);
         ++ax;
     }
     if (ax >= 3) return;
@@ -440,6 +487,124 @@ __global__ void k_unfold(const double2 *__restrict__ X, const double2 *__restric
     U[t] = make_double2(re, im);
 }
 
+// ---- FFT over the cube index (Sec. 4, large aspect ratios): data [A][N][ncol],
+// the transform along the middle index.
+
+// One radix-R Stockham stage.  With S the product of the radices of the
+// stages before, the sub-transforms have length n = N / S; a thread takes the
+// butterfly (s, b2) of one (a, column), s < S, b2 < m = n / R:
+//   x_b1 = in[a][(m b1 + b2) S + s],  b1 < R,
+//   out[a][b2 S R + s + S r1] = w_n^(sg r1 b2) sum_b1 w_R^(sg r1 b1) x_b1,
+// with w_len = exp(2 pi i / len) from the twiddle table tw of the length-N
+// transform (w_n = w_N^S, w_R = w_N^(N/R)) and sg = -1 or +1.  After the
+// last stage (S R = N) the outputs are in natural order.  INM: real input;
+// OUTM: only the real part is stored; the output is scaled by `scale`.
+template <int R, bool INM, bool OUTM>
+__global__ void k_fft_stage(const void *__restrict__ in, void *__restrict__ out, int64_t A, int N, int ncol, int S,
+                            int sg, const double2 *__restrict__ tw, double scale)
+{
+    const int nbf = N / R;
+    const int64_t per = (int64_t)nbf * ncol;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= A * per) return;
+    const int col = (int)(t % ncol);
+    const int u = (int)((t / ncol) % nbf);
+    const int64_t a = t / per;
+    const int m = nbf / S;
+    const int sb = u % S, b2 = u / S;
+    const int64_t base = a * N;
+    double2 x[R];
+#pragma unroll
+    for (int b1 = 0; b1 < R; ++b1) {
+        const int64_t idx = (base + (int64_t)(m * b1 + b2) * S + sb) * ncol + col;
+        if constexpr (INM)
+            x[b1] = make_double2(((const double *)in)[idx], 0.0);
+        else
+            x[b1] = ((const double2 *)in)[idx];
+    }
+    const double sgn = sg < 0 ? -1.0 : 1.0;
+    double2 wr[R];  // w_R^k with the transform's sign
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const double2 w = tw[(int64_t)k * nbf];
+        wr[k] = make_double2(w.x, sgn * w.y);
+    }
+#pragma unroll
+    for (int r1 = 0; r1 < R; ++r1) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int b1 = 0; b1 < R; ++b1) {
+            const double2 w = wr[(r1 * b1) % R];
+            re = fma(w.x, x[b1].x, fma(-w.y, x[b1].y, re));
+            im = fma(w.x, x[b1].y, fma(w.y, x[b1].x, im));
+        }
+        const double2 tv = tw[(int64_t)S * r1 * b2];  // w_n^(r1 b2), S r1 b2 < N
+        const double ti = sgn * tv.y;
+        const double yr = scale * (tv.x * re - ti * im), yi = scale * (tv.x * im + ti * re);
+        const int64_t o = (base + (int64_t)b2 * S * R + sb + (int64_t)S * r1) * ncol + col;
+        if constexpr (OUTM)
+            ((double *)out)[o] = yr;
+        else
+            ((double2 *)out)[o] = make_double2(yr, yi);
+    }
+}
+
+// Bluestein: sum_b w^(sg r b) X_b = c_r sum_b (X_b c_b) conj(c_(r-b)), c_k =
+// exp(sg pi i k^2 / n); the sum is a circular convolution of length n2 >=
+// 2n - 1 with h_k = conj(c_|k|), done as IFFT(FFT(a) H), H = FFT(h).  The
+// tables hold the sg = -1 chirp; sg = +1 runs the same steps on conj(X) and
+// conjugates the result.
+template <bool RIN>
+__global__ void k_blue_in(const void *__restrict__ in, double2 *__restrict__ P, int64_t A, int n, int n2, int ncol,
+                          int sg, const double2 *__restrict__ ch)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= A * n2 * (int64_t)ncol) return;
+    const int col = (int)(t % ncol);
+    const int k = (int)((t / ncol) % n2);
+    const int64_t a = t / ((int64_t)ncol * n2);
+    double2 v = make_double2(0.0, 0.0);
+    if (k < n) {
+        const int64_t idx = (a * n + k) * ncol + col;
+        double2 x;
+        if constexpr (RIN)
+            x = make_double2(((const double *)in)[idx], 0.0);
+        else
+            x = ((const double2 *)in)[idx];
+        if (sg > 0) x.y = -x.y;
+        const double2 c = ch[k];
+        v = make_double2(x.x * c.x - x.y * c.y, x.x * c.y + x.y * c.x);
+    }
+    P[t] = v;
+}
+
+__global__ void k_blue_mul(double2 *__restrict__ P, int64_t A, int n2, int ncol, const double2 *__restrict__ H)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= A * n2 * (int64_t)ncol) return;
+    const int k = (int)((t / ncol) % n2);
+    const double2 h = H[k], x = P[t];
+    P[t] = make_double2(x.x * h.x - x.y * h.y, x.x * h.y + x.y * h.x);
+}
+
+template <bool ROUT>
+__global__ void k_blue_out(const double2 *__restrict__ P, void *__restrict__ out, int64_t A, int n, int n2, int ncol,
+                           int sg, const double2 *__restrict__ ch, double scale)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= A * n * (int64_t)ncol) return;
+    const int col = (int)(t % ncol);
+    const int r = (int)((t / ncol) % n);
+    const int64_t a = t / ((int64_t)ncol * n);
+    const double2 x = P[(a * n2 + r) * ncol + col], c = ch[r];
+    double yr = scale * (x.x * c.x - x.y * c.y), yi = scale * (x.x * c.y + x.y * c.x);
+    if (sg > 0) yi = -yi;
+    if constexpr (ROUT)
+        ((double *)out)[t] = yr;
+    else
+        ((double2 *)out)[t] = make_double2(yr, yi);
+}
+
 // a Chebyshev series of the PSWF window in u = 2 t^2 - 1 (Clenshaw), over
 // all DMK_PSWF_MAXTERMS coefficients (zero past the window's nterms64, where
 // the recurrence stays exactly zero): a fixed length lets the coefficient
@@ -625,6 +790,17 @@ __global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, double sigma, c
 int m_in_k(int k) { return k == 0 ? 1 : (k == 2 ? 9 : 3); }
 int m_out_k(int k) { return k == 0 ? 1 : 3; }
 
+// radices 8, 4, 2, 3, 5, 7 of n into the plan's stages; n keeps the rest
+void fft_factor(int &n, FftPlan &pl)
+{
+    static const int rads[6] = {8, 4, 2, 3, 5, 7};
+    for (int k = 0; k < 6; ++k)
+        while (n % rads[k] == 0 && n > 1 && pl.nst < FFT_MAXST) {
+            pl.rad[pl.nst++] = rads[k];
+            n /= rads[k];
+        }
+}
+
 int far_geom(const dmk_far_grid *fg, FarGeom &g)
 {
     if (!fg) return DMK_EINVAL;
@@ -648,6 +824,17 @@ int far_geom(const dmk_far_grid *fg, FarGeom &g)
     g.cover = tiles ? 0 : 1;
     for (int i = 0; i < 3; ++i) g.hr[i] = h0 / fg->L[i];
     g.p = fg->p;
+    // The cube-index DFT on the cube grid of an exact tiling (the cubes'
+    // centres at multiples of L_i / M_i), for 8 or more cubes: as an FFT from
+    // FFT_MIN cubes on, below that as a dense product where it at least
+    // halves the terms of the direct sums ((M^2 + W) p against W M p per
+    // output column).  A factored axis keeps the phase-table rows of the first
+    // cube only.
+    for (int i = 0; i < 3; ++i) {
+        const int64_t m = fg->M[i], w = 2 * (int64_t)fg->K[i] + 1;
+        g.fac[i] = !g.cover && m >= 8 && (m >= FFT_MIN || 2 * (m * m + w) <= w * m);
+        g.fft[i] = g.fac[i] && m >= FFT_MIN;
+    }
     int64_t off = 0;
     for (int i = 0; i < 3; ++i) {
         g.L[i] = fg->L[i];
@@ -655,20 +842,41 @@ int far_geom(const dmk_far_grid *fg, FarGeom &g)
         g.K[i] = fg->K[i];
         g.G[i] = fg->M[i] * fg->p;
         g.W[i] = 2 * fg->K[i] + 1;
+        g.rows[i] = g.fac[i] ? g.p : g.G[i];
         g.eoff[i] = off;
-        off += (int64_t)g.G[i] * g.W[i];
-        g.nE += (int64_t)g.G[i] * (g.K[i] + 1);
+        off += (int64_t)g.rows[i] * g.W[i];
+        g.nE += (int64_t)g.rows[i] * (g.K[i] + 1);
     }
-    // the cube-index DFT where it at least halves the terms of the direct
-    // sums, (M^2 + W) p against W M p per output column, on the cube grid of
-    // an exact tiling (the cubes' centres at multiples of L_i / M_i)
     for (int i = 0; i < 3; ++i) {
-        const int64_t m = g.M[i], w = g.W[i];
-        g.fac[i] = !g.cover && m >= 8 && m <= 512 && 2 * (m * m + w) <= w * m;
-        if (g.fac[i]) {
+        if (!g.fac[i]) continue;
+        const int64_t m = g.M[i];
+        if (!g.fft[i]) {
             g.doff[i] = off;
             off += m * m;
             g.nD += m * m;
+            continue;
+        }
+        FftPlan &pl = g.pl[i];
+        pl.n = (int)m;
+        int rest = (int)m;
+        fft_factor(rest, pl);
+        if (rest > 1) {  // a prime factor above 8: Bluestein with a power-of-two length
+            pl.n2 = 1;
+            while (pl.n2 < 2 * pl.n - 1) pl.n2 *= 2;
+            pl.nst = 0;
+            int r2 = pl.n2;
+            fft_factor(r2, pl);
+        }
+        const int64_t len = pl.n2 ? pl.n2 : pl.n;
+        pl.twoff = off;
+        off += len;
+        g.nD += len;
+        if (pl.n2) {
+            pl.choff = off;
+            off += pl.n;
+            pl.hoff = off;  // h, then H = FFT(h) after it
+            off += 2 * (int64_t)pl.n2;
+            g.nD += pl.n2;
         }
     }
     for (int i = 0; i < 3; ++i)
@@ -676,6 +884,7 @@ int far_geom(const dmk_far_grid *fg, FarGeom &g)
             g.foff[i] = off;
             off += (int64_t)g.p * g.W[i];
         }
+    g.ntab = off;
     return DMK_OK;
 }
 
@@ -818,6 +1027,97 @@ int mode(const void *X, const double2 *E, int64_t A, int I, int O, int C, int64_
     return 1;
 }
 
+// ---- FFT launches
+template <bool INM, bool OUTM>
+void fft_stage_launch(int R, const void *in, void *out, int64_t A, int N, int ncol, int S, int sg,
+                      const double2 *tw, double scale, hipStream_t st)
+{
+    const dim3 grid((unsigned)nblk(A * (N / R) * (int64_t)ncol, 256)), blk(256);
+    switch (R) {
+    case 2: hipLaunchKernelGGL((k_fft_stage<2, INM, OUTM>), grid, blk, 0, st, in, out, A, N, ncol, S, sg, tw, scale); break;
+    case 3: hipLaunchKernelGGL((k_fft_stage<3, INM, OUTM>), grid, blk, 0, st, in, out, A, N, ncol, S, sg, tw, scale); break;
+    case 4: hipLaunchKernelGGL((k_fft_stage<4, INM, OUTM>), grid, blk, 0, st, in, out, A, N, ncol, S, sg, tw, scale); break;
+    case 5: hipLaunchKernelGGL((k_fft_stage<5, INM, OUTM>), grid, blk, 0, st, in, out, A, N, ncol, S, sg, tw, scale); break;
+    case 7: hipLaunchKernelGGL((k_fft_stage<7, INM, OUTM>), grid, blk, 0, st, in, out, A, N, ncol, S, sg, tw, scale); break;
+    default: hipLaunchKernelGGL((k_fft_stage<8, INM, OUTM>), grid, blk, 0, st, in, out, A, N, ncol, S, sg, tw, scale); break;
+    }
+}
+
+// The stages of a length-N transform (stages rad[0 .. nst)) on [A][N][ncol]:
+// stage 0 reads `in` (real if rin), the last writes `out` (real part if rout;
+// when out is null, the result stays in a scratch buffer), the ones between
+// alternate between bufA and bufB (never the buffer they read).  Returns the
+// buffer that holds the result.
+void *fft_stages(const FftPlan &pl, int N, const double2 *tw, const void *in, bool rin, void *out, bool rout,
+                 int64_t A, int ncol, int sg, double scale, double2 *bufA, double2 *bufB, hipStream_t st)
+{
+    const void *cur = in;
+    int S = 1;
+    for (int k = 0; k < pl.nst; ++k) {
+        const bool last = k == pl.nst - 1;
+        void *dst = (last && out) ? out : (cur == (const void *)bufA ? (void *)bufB : (void *)bufA);
+        const bool ri = k == 0 && rin, ro = last && rout && out;
+        const double sc = last ? scale : 1.0;
+        if (ri && ro) fft_stage_launch<true, true>(pl.rad[k], cur, dst, A, N, ncol, S, sg, tw, sc, st);
+        else if (ri) fft_stage_launch<true, false>(pl.rad[k], cur, dst, A, N, ncol, S, sg, tw, sc, st);
+        else if (ro) fft_stage_launch<false, true>(pl.rad[k], cur, dst, A, N, ncol, S, sg, tw, sc, st);
+        else fft_stage_launch<false, false>(pl.rad[k], cur, dst, A, N, ncol, S, sg, tw, sc, st);
+        S *= pl.rad[k];
+        cur = dst;
+    }
+    return (void *)cur;
+}
+
+// Y[a][r][c] = sum_b exp(sg 2 pi i r b / M) X[a][b][c] over the cube index of
+// axis ax (X real if RIN; only Re(Y) stored if ROUT), via the axis' plan
+template <bool RIN, bool ROUT>
+void fft_cube(const FarGeom &g, int ax, const double2 *E, const void *X, void *Y, int64_t A, int ncol, int sg,
+              double2 *bufA, double2 *bufB, hipStream_t st)
+{
+    const FftPlan &pl = g.pl[ax];
+    const double2 *tw = E + pl.twoff;
+    if (!pl.n2) {
+        fft_stages(pl, pl.n, tw, X, RIN, Y, ROUT, A, ncol, sg, 1.0, bufA, bufB, st);
+        return;
+    }
+    const double2 *ch = E + pl.choff, *H = E + pl.hoff + pl.n2;
+    const int64_t n2c = A * pl.n2 * (int64_t)ncol;
+    hipLaunchKernelGGL((k_blue_in<RIN>), dim3((unsigned)nblk(n2c, 256)), dim3(256), 0, st, X, bufA, A, pl.n, pl.n2,
+                       ncol, sg, ch);
+    double2 *P = (double2 *)fft_stages(pl, pl.n2, tw, bufA, false, nullptr, false, A, ncol, -1, 1.0, bufA, bufB, st);
+    hipLaunchKernelGGL(k_blue_mul, dim3((unsigned)nblk(n2c, 256)), dim3(256), 0, st, P, A, pl.n2, ncol, H);
+    double2 *Q = (double2 *)fft_stages(pl, pl.n2, tw, P, false, nullptr, false, A, ncol, 1, 1.0, bufA, bufB, st);
+    hipLaunchKernelGGL((k_blue_out<ROUT>), dim3((unsigned)nblk(A * pl.n * (int64_t)ncol, 256)), dim3(256), 0, st, Q,
+                       Y, A, pl.n, pl.n2, ncol, sg, ch, 1.0 / pl.n2);
+}
+
+// H = FFT(h) (sign -1) of every Bluestein axis, after the set-up kernel
+void fft_bluestein_tables(const FarGeom &g, double2 *E, double2 *bufA, double2 *bufB, hipStream_t st)
+{
+    for (int ax = 0; ax < 3; ++ax) {
+        if (!g.fft[ax] || !g.pl[ax].n2) continue;
+        const FftPlan &pl = g.pl[ax];
+        fft_stages(pl, pl.n2, E + pl.twoff, E + pl.hoff, false, E + pl.hoff + pl.n2, false, 1, 1, -1, 1.0, bufA, bufB,
+                   st);
+    }
+}
+
+// launch sizes of the FFT of axis ax on [A][M][ncol]
+inline bool fft_fits(const FarGeom &g, int ax, int64_t A, int64_t ncol)
+{
+    const FftPlan &pl = g.pl[ax];
+    const int64_t len = pl.n2 ? pl.n2 : pl.n;
+    return grid_fits(nblk(A * len * ncol, 256), 256);
+}
+
+// complex scratch of the FFT of axis ax on [A][M][ncol] (each of two buffers)
+inline int64_t fft_scratch(const FarGeom &g, int ax, int64_t A, int64_t ncol)
+{
+    if (!g.fft[ax]) return 0;
+    const FftPlan &pl = g.pl[ax];
+    return A * (int64_t)(pl.n2 ? pl.n2 : pl.n) * ncol;
+}
+
 // The three contractions of each side, axis ax: A leading and C trailing
 // columns around the contracted index, input Q (forward) or J (evaluation)
 // components.
@@ -845,8 +1145,8 @@ inline bool axis_fits(const FarGeom &g, int ax, int64_t comps, bool fwd)
     if (!g.fac[ax]) return fwd ? mode_fits(ac.A, G, W, ac.C) : mode_fits(ac.A, W, G, ac.C);
     const int64_t pc = (int64_t)g.p * ac.C;
     if (pc > INT32_MAX) return false;
-    return mode_fits(ac.A, M, M, (int)pc) && grid_fits(nblk(ac.A * W * ac.C, 256), 256) &&
-           grid_fits(nblk(ac.A * G * ac.C, 256), 256);
+    const bool dft = g.fft[ax] ? fft_fits(g, ax, ac.A, pc) : mode_fits(ac.A, M, M, (int)pc);
+    return dft && grid_fits(nblk(ac.A * W * ac.C, 256), 256) && grid_fits(nblk(ac.A * G * ac.C, 256), 256);
 }
 
 // doubles2 of split partials and of the DFT's output a contraction needs
@@ -854,6 +1154,7 @@ inline int64_t axis_part(const FarGeom &g, int ax, int64_t comps, bool fwd)
 {
     const AxisCols ac = axis_cols(g, ax, comps);
     if (!g.fac[ax]) return fwd ? mode_part(ac.A, g.G[ax], g.W[ax], ac.C) : mode_part(ac.A, g.W[ax], g.G[ax], ac.C);
+    if (g.fft[ax]) return 0;
     return mode_part(ac.A, g.M[ax], g.M[ax], g.p * ac.C);
 }
 
@@ -873,14 +1174,17 @@ inline bool fold_on_lds(const FarGeom &g, int ax, const AxisCols &ac)
 // Returns mode()'s count of deferred partial results (1 when written to Y).
 template <bool RIN>
 int contract_fwd(const FarGeom &g, int ax, int64_t comps, const void *X, const double2 *E, double s, double2 *Y,
-                 double2 *Z, double2 *part, hipStream_t st, bool defer_sum = false)
+                 double2 *Z, double2 *part, double2 *fa, double2 *fb, hipStream_t st, bool defer_sum = false)
 {
     const AxisCols ac = axis_cols(g, ax, comps);
     const int W = g.W[ax];
     if (!g.fac[ax])
         return mode<RIN, false, true>(X, E + g.eoff[ax], ac.A, g.G[ax], W, ac.C, W, 1, s, Y, part, st, defer_sum);
     const int M = g.M[ax];
-    mode<RIN, false, true>(X, E + g.doff[ax], ac.A, M, M, g.p * ac.C, M, 1, 1.0, Z, part, st);
+    if (g.fft[ax])
+        fft_cube<RIN, false>(g, ax, E, X, Z, ac.A, g.p * ac.C, -1, fa, fb, st);
+    else
+        mode<RIN, false, true>(X, E + g.doff[ax], ac.A, M, M, g.p * ac.C, M, 1, 1.0, Z, part, st);
     if (fold_on_lds(g, ax, ac))
         hipLaunchKernelGGL(k_fold_lds<true>, dim3((unsigned)ac.A), dim3(FL_T), (size_t)M * g.p * sizeof(double2), st, Z,
                            E + g.eoff[ax], M, g.p, W, g.K[ax], s, Y);
@@ -893,7 +1197,7 @@ int contract_fwd(const FarGeom &g, int ax, int64_t comps, const void *X, const d
 // One contraction of the evaluation along axis ax (E); ROUT: real part only
 template <bool ROUT>
 void contract_eval(const FarGeom &g, int ax, int64_t comps, const double2 *X, const double2 *E, void *Y, double2 *Z,
-                   double2 *part, hipStream_t st)
+                   double2 *part, double2 *fa, double2 *fb, hipStream_t st)
 {
     const AxisCols ac = axis_cols(g, ax, comps);
     const int W = g.W[ax];
@@ -904,11 +1208,14 @@ void contract_eval(const FarGeom &g, int ax, int64_t comps, const double2 *X, co
     const int M = g.M[ax];
     hipLaunchKernelGGL(k_unfold, dim3((unsigned)nblk(ac.A * g.G[ax] * ac.C, 256)), dim3(256), 0, st, X,
                        E + g.foff[ax], ac.A, M, g.p, W, g.K[ax], ac.C, Z);
-    mode<false, ROUT, false>(Z, E + g.doff[ax], ac.A, M, M, g.p * ac.C, M, 1, 1.0, Y, part, st);
+    if (g.fft[ax])
+        fft_cube<false, ROUT>(g, ax, E, Z, Y, ac.A, g.p * ac.C, 1, fa, fb, st);
+    else
+        mode<false, ROUT, false>(Z, E + g.doff[ax], ac.A, M, M, g.p * ac.C, M, 1, 1.0, Y, part, st);
 }
 
 struct FarLayout {
-    int64_t E, T1, T2, CHI, WT, V1, V2, PH, PART, Z, total;  // byte offsets
+    int64_t E, T1, T2, CHI, WT, V1, V2, PH, PART, Z, FA, FB, total;  // byte offsets
 };
 
 FarLayout far_layout(const FarGeom &g, int kernel)
@@ -920,10 +1227,8 @@ FarLayout far_layout(const FarGeom &g, int kernel)
     int64_t off = 0;
     const int64_t z = (int64_t)sizeof(double2);
     l.E = off;
-    int64_t nft = 0;
-    for (int i = 0; i < 3; ++i)
-        if (g.fac[i]) nft += (int64_t)g.p * g.W[i];
-    off = al(off + z * ((int64_t)g.G[0] * W0 + (int64_t)g.G[1] * W1 + (int64_t)g.G[2] * W2 + g.nD + nft));
+    // phase tables, DFT / FFT tables (Bluestein's H included), transposed first-cube rows
+    off = al(off + z * g.ntab);
     l.T1 = off;
     off = al(off + z * Q * G0 * G1 * W2);
     l.T2 = off;
@@ -940,15 +1245,24 @@ FarLayout far_layout(const FarGeom &g, int kernel)
     off = al(off + z * (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1));
     // partial results of the split contractions (the six of dmk_far3p_eval)
     // and the cube-index DFTs' outputs
-    int64_t np = 0, nz = 0;
+    int64_t np = 0, nz = 0, nf = 0;
     for (int ax = 0; ax < 3; ++ax) {
         np = std::max({np, axis_part(g, ax, Q, true), axis_part(g, ax, J, false)});
         nz = std::max({nz, axis_z(g, ax, Q), axis_z(g, ax, J)});
+        if (g.fft[ax]) {
+            const AxisCols aq = axis_cols(g, ax, Q), aj = axis_cols(g, ax, J);
+            nf = std::max({nf, fft_scratch(g, ax, aq.A, (int64_t)g.p * aq.C), fft_scratch(g, ax, aj.A, (int64_t)g.p * aj.C)});
+            if (g.pl[ax].n2) nf = std::max<int64_t>(nf, g.pl[ax].n2);
+        }
     }
     l.PART = off;
     off = al(off + z * np);
     l.Z = off;
     off = al(off + z * nz);
+    l.FA = off;
+    off = al(off + z * nf);
+    l.FB = off;
+    off = al(off + z * nf);
     l.total = off;
     return l;
 }
@@ -1019,6 +1333,7 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     double2 *T1 = (double2 *)(b + l.T1), *T2 = (double2 *)(b + l.T2), *CHI = (double2 *)(b + l.CHI);
     double2 *WT = (double2 *)(b + l.WT), *V1 = (double2 *)(b + l.V1), *V2 = (double2 *)(b + l.V2);
     double2 *PH = (double2 *)(b + l.PH), *PART = (double2 *)(b + l.PART), *Z = (double2 *)(b + l.Z);
+    double2 *FA = (double2 *)(b + l.FA), *FB = (double2 *)(b + l.FB);
     const int64_t Q = m_in_k(kernel), J = m_out_k(kernel);
     const int W0 = g.W[0], W1 = g.W[1], W2 = g.W[2];
     const double invV = 1.0 / (g.L[0] * g.L[1] * g.L[2]);
@@ -1027,10 +1342,11 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     const int64_t no = (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1);
     const unsigned nbt = (unsigned)nblk(ne, PREP_T);
     hipLaunchKernelGGL(k_far_prep, dim3(nbt + (unsigned)nblk(no, PREP_T / WAVE)), dim3(PREP_T), 0, stream, g, w, E, PH, nbt);
+    fft_bluestein_tables(g, E, FA, FB, stream);
     // structure factor (eq. (structurefac)): contract g2, g1, g0 with conj(E)
-    contract_fwd<true>(g, 2, Q, rho_grid, E, 1.0, T1, Z, PART, stream);
-    contract_fwd<false>(g, 1, Q, T1, E, 1.0, T2, Z, PART, stream);
-    const int ns_chi = contract_fwd<false>(g, 0, Q, T2, E, invV, CHI, Z, PART, stream, true);
+    contract_fwd<true>(g, 2, Q, rho_grid, E, 1.0, T1, Z, PART, FA, FB, stream);
+    contract_fwd<false>(g, 1, Q, T1, E, 1.0, T2, Z, PART, FA, FB, stream);
+    const int ns_chi = contract_fwd<false>(g, 0, Q, T2, E, invV, CHI, Z, PART, FA, FB, stream, true);
     // mode weights (with the window's transform per octant mode from k_far_prep)
     const int64_t nm = (int64_t)W0 * W1 * W2;
     const dim3 gw((unsigned)nblk(nm, FW_T));
@@ -1041,9 +1357,9 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     default: hipLaunchKernelGGL(k_far_weights<3>, gw, dim3(FW_T), 0, stream, g, sigma0, PH, CHI, PART, ns_chi, invV, WT); break;
     }
     // evaluation on the grids (eq. (eval_tensor)): contract n0, n1, n2 with E
-    contract_eval<false>(g, 0, J, WT, E, V1, Z, PART, stream);
-    contract_eval<false>(g, 1, J, V1, E, V2, Z, PART, stream);
-    contract_eval<true>(g, 2, J, V2, E, u_grid, Z, PART, stream);
+    contract_eval<false>(g, 0, J, WT, E, V1, Z, PART, FA, FB, stream);
+    contract_eval<false>(g, 1, J, V1, E, V2, Z, PART, FA, FB, stream);
+    contract_eval<true>(g, 2, J, V2, E, u_grid, Z, PART, FA, FB, stream);
     DMK_HIP_CHECK(hipGetLastError());
     return DMK_OK;
 }

@@ -1,11 +1,14 @@
 """Root-level far field of the triply periodic split (D = 3) on the
 top-level Chebyshev grids: wrapper of ``dmk_far3p_eval``.
 
-The cell is tiled exactly by M0 x M1 x M2 cubes; every cube carries p^3
-first-kind Chebyshev points and the far field of proxy strengths on those
-points is evaluated on the same points (Sec. 4, evaluation of the far-field
-contribution, eqs. (structurefac), (eval_tensor)).  All arithmetic is in the
-library's kernels.
+The cell is tiled exactly by M0 x M1 x M2 cubes (or covered by cubes of its
+shortest side, the last along an axis cut by the face); every cube carries
+p^3 first-kind Chebyshev points and the far field of proxy strengths on
+those points is evaluated on the same points (Sec. 4, evaluation of the
+far-field contribution, eqs. (structurefac), (eval_tensor)).  Long axes of an
+exact tiling factor through a DFT over the cube index, an FFT from 65 cubes
+on (Sec. 4, large aspect ratios).  All arithmetic is in the library's
+kernels.
 """
 from __future__ import annotations
 

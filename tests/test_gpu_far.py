@@ -199,3 +199,49 @@ def test_far_deterministic():
         b = F.far3p_eval(Lv, M, 38, K, "laplace", 1.0, rho, pswf_c=29.0)
         torch.cuda.synchronize()
         assert torch.equal(a, b), Lv
+
+
+# Long axes of 65 or more cubes: the sums over the cube index run as FFTs
+# (Stockham stages of radix 2..8, or Bluestein's chirp convolution for
+# lengths with a prime factor above 8; Sec. 4, large aspect ratios).
+FFT_CASES = [
+    # (L, M, p, K, kernel): radix mixes along each axis, a prime length, a
+    # length with a large prime factor, two long axes at once
+    ((72.0, 1.0, 1.0), (72, 1, 1), 3, (150, 1, 1), "laplace"),      # 8 * 3 * 3
+    ((1.0, 97.0, 1.0), (1, 97, 1), 3, (1, 160, 1), "stokeslet"),    # prime: Bluestein
+    ((1.0, 1.0, 130.0), (1, 1, 130), 3, (1, 1, 200), "rotlet"),     # 2 * 5 * 13: Bluestein
+    ((1.0, 1.0, 210.0), (1, 1, 210), 2, (1, 1, 300), "stresslet"),  # 2 * 3 * 5 * 7
+    ((66.0, 1.0, 70.0), (66, 1, 70), 1, (60, 1, 60), "laplace"),    # two long axes, 66 = 2 * 3 * 11
+]
+
+
+@pytest.mark.parametrize("case", range(len(FFT_CASES)))
+@pytest.mark.parametrize("win", ["gauss", "pswf"])
+def test_far_fft_lengths(case, win):
+    Lv, M, p, K, kernel = FFT_CASES[case]
+    print("far fft", case, M, kernel, win, flush=True)
+    k = oracle.KERNELS[kernel]
+    G = [m * p for m in M]
+    rng = np.random.default_rng(900 + case)
+    rho = rng.normal(size=(oracle.M_IN[k], *G))
+    c = None if win == "gauss" else 14.5
+    sigma0 = 0.6 if win == "gauss" else 1.0
+    ref = oracle.far_3p_grid(kernel, Lv, M, p, K, sigma0, rho, window=_w(c))
+    got = host(F.far3p_eval(Lv, M, p, K, kernel, sigma0, dev(rho), pswf_c=c))
+    assert_parity(got, ref, 1e-12, "far fft %d %s" % (case, win))
+
+
+@pytest.mark.parametrize("kernel,Lv,M,c,p,nnz", [
+    ("laplace", (256.0, 1.0, 1.0), (256, 1, 1), 29.0, 38, 400),
+    ("laplace", (1024.0, 1.0, 1.0), (1024, 1, 1), 29.0, 38, 300),
+    ("stokeslet", (1.0, 1.0, 256.0), (1, 1, 256), 32.46, 44, 200),
+    ("rotlet", (1.0, 251.0, 1.0), (1, 251, 1), 32.46, 44, 200),
+])
+def test_far_fft_long_cuboid_sampled(kernel, Lv, M, c, p, nnz):
+    # hundreds to a thousand cubes at the paper's 1e-12 parameters (251 is
+    # prime: Bluestein); sparse proxy strengths keep the oracle's direct sums
+    # over the ~1e5 - 8e5 wave numbers affordable
+    K = F.table_modes(c, Lv, 1.0)
+    print("far fft long cuboid", kernel, M, K, flush=True)
+    got, ref = _sampled(kernel, Lv, M, p, K, c, nnz, 64, 89)
+    assert_parity(got, ref, 1e-12, "far fft long cuboid %s %s" % (kernel, M))
