@@ -484,11 +484,38 @@ __global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *_
     if (!WRITE && lane == 0) counts[col] = cnt;
 }
 
-__global__ void k_gather_tiles(const int4 *__restrict__ tin, const int32_t *__restrict__ order, int64_t n,
-                               int4 *__restrict__ tout)
+// Final tile order.  Tiles are sorted heavy-first by cost bucket (skey,
+// stable, so within a bucket they keep the column-by-column walk order), and
+// workgroup i of the pair kernels runs on XCD i mod 8.  Within each bucket
+// [o, o + B) the positions k with k mod 8 = q (one XCD) take the q-th
+// contiguous run of the bucket's tiles: every XCD works on a spatially
+// compact share of every bucket, so tiles that stage the same neighbour
+// columns meet in one L2, and the heavy buckets stay spread over all XCDs.
+__device__ inline int64_t bound_of(const int32_t *__restrict__ a, int64_t n, int32_t v, bool upper)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (upper ? a[mid] <= v : a[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_gather_tiles(const int4 *__restrict__ tin, const int32_t *__restrict__ order,
+                               const int32_t *__restrict__ skey, int64_t n, int4 *__restrict__ tout)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) tout[i] = tin[order[i]];
+    if (i >= n) return;
+    const int32_t key = skey[i];
+    const int64_t o = bound_of(skey, n, key, false), B = bound_of(skey, n, key, true) - o;
+    const int64_t k = i - o;
+    const int q = (int)(k & (XCDS - 1));
+    int64_t start = 0;  // tiles of the groups before q
+    for (int qq = 0; qq < q; ++qq) start += qq < B ? (B - qq + XCDS - 1) / XCDS : 0;
+    tout[i] = tin[order[o + start + k / XCDS]];
 }
 
 __global__ void k_tile_total(const int32_t *__restrict__ counts, int ncol, const int32_t *__restrict__ last_raw,
@@ -704,8 +731,8 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
         scan_excl(thist, (int64_t)256 * tb, thist + 256 * tb, stream);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tb), dim3(RS_THREADS), 0, stream, tkey,
                            (const int32_t *)nullptr, nt, 0, thist, (int)tb, tkey2, torder);
-        hipLaunchKernelGGL(k_gather_tiles, dim3(nblocks(nt, 256)), dim3(256), 0, stream, tiles_u, torder, nt,
-                           (int4 *)bins->tiles);
+        hipLaunchKernelGGL(k_gather_tiles, dim3(nblocks(nt, 256)), dim3(256), 0, stream, tiles_u, torder,
+                           (const int32_t *)tkey2, nt, (int4 *)bins->tiles);
         DMK_HIP_CHECK(hipGetLastError());
     }
     bins->ntiles = st[1];

@@ -21,8 +21,12 @@ namespace dmk {
 #ifndef DMK_WAVES_PER_TILE
 #define DMK_WAVES_PER_TILE 4
 #endif
+#ifndef DMK_TILE_T
+#define DMK_TILE_T 64
+#endif
 constexpr int WAVE = 64;
-constexpr int TILE_T = 64;
+constexpr int XCDS = 8;  // accelerator complex dies: workgroup i runs on XCD i mod 8
+constexpr int TILE_T = DMK_TILE_T;
 constexpr int TILE_CAP = DMK_TILE_CAP;
 constexpr int TILE_NW = DMK_WAVES_PER_TILE;  // wavefronts per tile workgroup
 #ifndef DMK_TILE_ZMAX

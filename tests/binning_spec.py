@@ -82,7 +82,10 @@ def tiles_spec(box_start, D, n, T=64, CAP=512, ZMAX=46):
     reached through, and a slab beyond a free z face is empty.  The tiles,
     listed column by column, are then stably sorted by the key
     64 - bit_length(cost + 1), cost = sum over the tile's targets of the
-    sources in their 3 slabs.
+    sources in their 3 slabs.  Finally, within each bucket (run of equal
+    keys) of B tiles at offset o, the positions o + k with k = q (mod 8) take,
+    for q = 0, 1, ..., 7 in turn, the next ceil((B - q) / 8) tiles of the
+    bucket in order (one contiguous run per XCD of the pair kernels).
     """
     n0, n1, n2 = (int(v) for v in n)
     nbr, _ = axis_tables_spec(D, n)
@@ -136,5 +139,14 @@ def tiles_spec(box_start, D, n, T=64, CAP=512, ZMAX=46):
                 keys.append(64 - (cost + 1).bit_length())
                 z = z1 + 1
     tiles = np.asarray(tiles, dtype=np.int32).reshape(-1, 4)
-    order = np.argsort(np.asarray(keys, dtype=np.int64), kind="stable")
-    return tiles[order]
+    keys = np.asarray(keys, dtype=np.int64)
+    order = np.argsort(keys, kind="stable")
+    srt, sk = tiles[order], keys[order]
+    out = np.empty_like(srt)
+    o = 0
+    while o < len(srt):
+        B = int(np.searchsorted(sk, sk[o], side="right")) - o
+        pos = [k for q in range(8) for k in range(q, B, 8)]
+        out[o + np.asarray(pos, dtype=np.int64)] = srt[o:o + B]
+        o += B
+    return out
