@@ -76,7 +76,6 @@ struct Cfg {
     static constexpr int NW = (STAGE_B + TILE_NW * WAVE_B > 150 * 1024) ? 2
                               : (STAGE_B + TILE_NW * WAVE_B + 16 * 1024 > 80 * 1024) ? 8
                                                                                        : TILE_NW;
-    static constexpr int TPW = TILE_T / NW;              // targets per wavefront
 };
 
 struct ResParams {
@@ -858,11 +857,15 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
         __syncthreads();
 
         // ---- scan: one target at a time over its contiguous stencil range;
-        // wavefront w takes targets w, w + NW, ...  The target's coordinates
-        // and threshold are read from LDS at a uniform address (a broadcast).
-        const int nmine = ntgt > w ? min(C::TPW, (ntgt - w + C::NW - 1) / C::NW) : 0;
-        for (int i = 0; i < nmine; ++i) {
-            const int t = w + C::NW * i;
+        // wavefront w takes the consecutive targets [t0, t1) (an even share),
+        // so that consecutive targets mostly lie in one box and share their
+        // range: a one-step range already held in s0, s1 is not read again.
+        // The target's coordinates and threshold are read from LDS at a
+        // uniform address (a broadcast).
+        const int t0 = (w * ntgt) / C::NW, t1 = ((w + 1) * ntgt) / C::NW;
+        int pa = -1;  // first slot of the one-step window held in s0, s1 (-1: none)
+        float4 s0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), s1 = s0;
+        for (int t = t0; t < t1; ++t) {
             const float4 ts = S.tc[t];
             const float tx = ts.x, ty = ts.y, tz = ts.z, thr = ts.w;
             int a = 0, b = clen;
@@ -880,9 +883,13 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
             // is the compare's lane mask.  Hits are appended at queue[qn ..) in
             // lane order, those of the first half first; entry = (t << 16) |
             // source slot.
+            const bool one = b - a <= 2 * WAVE;
             for (int p = a; p < b; p += 2 * WAVE) {
-                const int i0 = min(p + lane, clen), i1 = min(p + WAVE + lane, clen);
-                const float4 s0 = S.sc[i0], s1 = S.sc[i1];
+                if (p != pa) {
+                    s0 = S.sc[min(p + lane, clen)];
+                    s1 = S.sc[min(p + WAVE + lane, clen)];
+                    pa = one ? p : -1;
+                }
                 // (|s|^2 - 2 s.t) / 2 against (rc2s - |t|^2) / 2
                 const float ra = fmaf(-s0.x, tx, fmaf(-s0.y, ty, fmaf(-s0.z, tz, s0.w)));
                 const float rb = fmaf(-s1.x, tx, fmaf(-s1.y, ty, fmaf(-s1.z, tz, s1.w)));
