@@ -325,23 +325,26 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval(ChebGeom g, const int32_t *_
 //   V[i][n] = sum_{j2} l2(s_i, j2) U[n][j2],   n = (j0, j1),
 // is a (16 x p) by (p x p^2) product, done with v_mfma_f64_16x16x4 (A: lane l
 // holds A[l % 16][l / 16], B: B[l / 16][l % 16], D: D[4 r + l / 16][l % 16]);
-// each D element is then weighted by l0(s_i, j0) l1(s_i, j1) (the block's
+// each D element is then weighted by l0(s_i, j0) l1(s_i, j1) (the blocks'
 // l0 and l1 rows staged in the wavefront's LDS) and the 16 lanes that hold a
 // point's row are summed with shuffles.  One workgroup per box; its
-// wavefronts take the box's 16-point blocks in turn.  Each lane takes the
-// contiguous run j2 = lk nkk .. lk nkk + nkk - 1 (nkk = ceil(p / 4)), and all
-// KM loads of a component's run (addresses clamped into the row, KM >= nkk a
-// compile-time bound) are issued before its products, so that they are in
-// flight together.
+// wavefronts take groups of NB consecutive 16-point blocks in turn, so that
+// every B fragment (4 x 16 values of the box's grid) feeds NB independent
+// products, and (one component) the fragments of the next column tile are
+// loaded before the products of the current one.  Each lane takes the contiguous run
+// j2 = lk nkk .. lk nkk + nkk - 1 (nkk = ceil(p / 4)); KM >= nkk is a
+// compile-time bound and loads are clamped into the row, so none is
+// conditional.
 constexpr int KMAX = DMK_FAR_PMAX / 4;
 
-template <int M, bool ACC, int KM>
+template <int M, bool ACC, int KM, int NB>
 __global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32_t *__restrict__ bs,
                                                          const int32_t *__restrict__ perm,
                                                          const double *__restrict__ lag,
                                                          const double *__restrict__ U, double *__restrict__ u)
 {
     extern __shared__ double sm[];
+    constexpr bool PF = M == 1;  // prefetch the next tile's B fragments
     const int p = g.p;
     const int64_t N = g.N;
     const int64_t box = g.wg0 + blockIdx.x;
@@ -351,96 +354,123 @@ __global__ __launch_bounds__(CB_T) void k_cheb_eval_mfma(ChebGeom g, const int32
     const int wv = threadIdx.x / WAVE;
     const int li = lane & 15, lk = lane >> 4;  // A row / B column, A column / B row
     const int sb = bs[box], se = bs[box + 1];
-    const int nblock = (se - sb + 15) / 16;
+    const int ngrp = (se - sb + 16 * NB - 1) / (16 * NB);
     const int pp = p * p;
     const int nkk = (p + 3) / 4;
     const int64_t g12 = g.G[1] * g.G[2];
     const int64_t rb = ((b0 * p) * g.G[1] + b1 * p) * g.G[2] + b2 * p;  // the box's first grid value
-    // this wavefront's copy of the block's l0 and l1: W0[j][i], W1[j][i]
-    double *W0 = sm + (size_t)wv * 32 * p, *W1 = W0 + 16 * p;
-    for (int blk = wv; blk < nblock; blk += CB_T / WAVE) {
-        const int s0 = sb + blk * 16;
-        const int nv = min(16, se - s0);
-        wave_barrier();  // the previous block's weights are no longer read
-        for (int e = lane; e < 16 * p; e += WAVE) {
-            const int j = e >> 4, i = e & 15;
+    // this wavefront's copy of the group's l0 and l1: W0[b][j][i], W1[b][j][i]
+    double *W0 = sm + (size_t)wv * 32 * NB * p, *W1 = W0 + 16 * NB * p;
+    // B fragments of the column (j0, j1): this lane's run of j2 of every component
+    auto load_b = [&](int j0, int j1, double (&bv)[M][KM]) {
+        const int64_t row = rb + (int64_t)j0 * g12 + (int64_t)j1 * g.G[2];
+#pragma unroll
+        for (int q = 0; q < M; ++q)
+#pragma unroll
+            for (int kk = 0; kk < KM; ++kk) bv[q][kk] = U[q * tot + row + min(lk * nkk + kk, p - 1)];
+    };
+    for (int grp = wv; grp < ngrp; grp += CB_T / WAVE) {
+        const int s0 = sb + grp * 16 * NB;
+        const int nv = min(16 * NB, se - s0);  // points of the group
+        wave_barrier();  // the previous group's weights are no longer read
+        for (int e = lane; e < 16 * NB * p; e += WAVE) {
+            const int b = e / (16 * p), r = e - b * (16 * p);
+            const int j = r >> 4, i = b * 16 + (r & 15);
             W0[e] = i < nv ? lag[(int64_t)j * N + s0 + i] : 0.0;
             W1[e] = i < nv ? lag[(int64_t)(p + j) * N + s0 + i] : 0.0;
         }
         wave_barrier();
-        // A fragments: l2 of point li at j2 = lk nkk + kk (each lane takes a
-        // contiguous run of j2, so that its values of U are adjacent in memory)
-        double afr[KM];
+        // A fragments: l2 of point li of block b at j2 = lk nkk + kk
+        double afr[NB][KM];
 #pragma unroll
-        for (int kk = 0; kk < KM; ++kk) {
-            const int k = lk * nkk + kk;
-            afr[kk] = (kk < nkk && k < p && li < nv) ? lag[(int64_t)(2 * p + k) * N + s0 + li] : 0.0;
-        }
-        double part[M][4];
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int q = 0; q < M; ++q)
+            for (int kk = 0; kk < KM; ++kk) {
+                const int k = lk * nkk + kk, i = b * 16 + li;
+                afr[b][kk] = (kk < nkk && k < p && i < nv) ? lag[(int64_t)(2 * p + k) * N + s0 + i] : 0.0;
+            }
+        double part[NB][M][4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) part[q][r] = 0.0;
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) part[b][q][r] = 0.0;
         // this lane's B / D column n = n0 + li = j0 p + j1, advanced by 16 per
         // tile without a division
         int jn0 = li / p, jn1 = li - (li / p) * p;
+        double bv[M][KM], bn[M][KM];
+        if constexpr (PF) load_b(jn0 < p ? jn0 : 0, jn0 < p ? jn1 : 0, bv);
         for (int n0 = 0; n0 < pp; n0 += 16) {
             const bool nok = jn0 < p;
             const int j0 = nok ? jn0 : 0, j1 = nok ? jn1 : 0;
-            const int64_t row = rb + (int64_t)j0 * g12 + (int64_t)j1 * g.G[2];
-            dbl4 d[M];
-#pragma unroll
-            for (int q = 0; q < M; ++q) d[q] = (dbl4){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int q = 0; q < M; ++q) {
-                // all loads of this component first (addresses clamped into the
-                // box, so none is conditional), then the products: the loads
-                // are in flight together instead of one per product
-                const double *Uq = U + q * tot + row;
-                double bv[KM];
-#pragma unroll
-                for (int kk = 0; kk < KM; ++kk) bv[kk] = Uq[min(lk * nkk + kk, p - 1)];
-                // no select on B: A is zero for j2 >= p, and the columns past
-                // p^2 (finite values of the box) get the weight 0 below
-#pragma unroll
-                for (int kk = 0; kk < KM; ++kk)
-                    if (kk < nkk) d[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[kk], bv[kk], d[q], 0, 0, 0);
+            // the next tile's column
+            int kn0 = jn0, kn1 = jn1 + 16;
+            while (kn1 >= p) {
+                kn1 -= p;
+                ++kn0;
             }
-            // weights of the four D rows this lane holds (points 4 r + lk)
+            // one component: the next tile's fragments are loaded now (past
+            // the last tile: the clamped column 0, loaded and not used);
+            // several: this tile's, all before its products
+            if constexpr (PF)
+                load_b(kn0 < p ? kn0 : 0, kn0 < p ? kn1 : 0, bn);
+            else
+                load_b(j0, j1, bv);
+            // no select on B: A is zero for j2 >= p, and the columns past p^2
+            // (finite values of the box) get the weight 0 below
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 4 * r + lk;
-                const double w = nok ? W0[j0 * 16 + i] * W1[j1 * 16 + i] : 0.0;
+            for (int b = 0; b < NB; ++b) {
+                dbl4 d[M];
 #pragma unroll
-                for (int q = 0; q < M; ++q) part[q][r] = fma(w, d[q][r], part[q][r]);
+                for (int q = 0; q < M; ++q) {
+                    d[q] = (dbl4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int kk = 0; kk < KM; ++kk)
+                        if (kk < nkk) d[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[b][kk], bv[q][kk], d[q], 0, 0, 0);
+                }
+                // weights of the four D rows this lane holds (points 4 r + lk of block b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 4 * r + lk;
+                    const double w = nok ? W0[(b * p + j0) * 16 + i] * W1[(b * p + j1) * 16 + i] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < M; ++q) part[b][q][r] = fma(w, d[q][r], part[b][q][r]);
+                }
             }
-            jn1 += 16;
-            while (jn1 >= p) {
-                jn1 -= p;
-                ++jn0;
-            }
+            if constexpr (PF)
+#pragma unroll
+                for (int q = 0; q < M; ++q)
+#pragma unroll
+                    for (int kk = 0; kk < KM; ++kk) bv[q][kk] = bn[q][kk];
+            jn0 = kn0;
+            jn1 = kn1;
         }
         // sum over the 16 lanes of a row group, in a fixed order
 #pragma unroll
-        for (int q = 0; q < M; ++q)
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                for (int off = 8; off > 0; off >>= 1) part[q][r] += __shfl_xor(part[q][r], off);
+            for (int q = 0; q < M; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    for (int off = 8; off > 0; off >>= 1) part[b][q][r] += __shfl_xor(part[b][q][r], off);
         if (li == 0) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 4 * r + lk;
-                if (i < nv) {
-                    const int64_t pi = perm[s0 + i];
+            for (int b = 0; b < NB; ++b)
 #pragma unroll
-                    for (int q = 0; q < M; ++q) {
-                        if constexpr (ACC)
-                            u[pi * M + q] += part[q][r];
-                        else
-                            u[pi * M + q] = part[q][r];
+                for (int r = 0; r < 4; ++r) {
+                    const int i = b * 16 + 4 * r + lk;
+                    if (i < nv) {
+                        const int64_t pi = perm[s0 + i];
+#pragma unroll
+                        for (int q = 0; q < M; ++q) {
+                            if constexpr (ACC)
+                                u[pi * M + q] += part[b][q][r];
+                            else
+                                u[pi * M + q] = part[b][q][r];
+                        }
                     }
                 }
-            }
         }
     }
 }
@@ -554,22 +584,28 @@ extern "C" int dmk_cheb_anterp(const dmk_grid *grid, const dmk_bins *bins, int p
 
 namespace dmk {
 namespace {
-template <int KM>
-void launch_eval_mfma(int m, bool acc, dim3 grd, size_t lds, hipStream_t st, const ChebGeom &g, const int32_t *bsp,
+// one launch of k_cheb_eval_mfma; the LDS holds each wavefront's l0 and l1
+// rows of a group of NB blocks (32 NB p doubles)
+template <int M, int KM, int NB>
+void launch_em(bool acc, dim3 grd, hipStream_t st, const ChebGeom &g, const int32_t *bsp, const int32_t *pm,
+               const double *lag, const double *U, double *u)
+{
+    const size_t lds = sizeof(double) * (size_t)(CB_T / WAVE) * 32 * NB * g.p;
+    if (acc)
+        hipLaunchKernelGGL((k_cheb_eval_mfma<M, true, KM, NB>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u);
+    else
+        hipLaunchKernelGGL((k_cheb_eval_mfma<M, false, KM, NB>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u);
+}
+// NB1: blocks per group for one component (several components keep one
+// block per group: their B fragments and sums already fill the registers)
+template <int KM, int NB1>
+void launch_eval_mfma(int m, bool acc, dim3 grd, hipStream_t st, const ChebGeom &g, const int32_t *bsp,
                       const int32_t *pm, const double *lag, const double *U, double *u)
 {
-    if (acc) {
-        switch (m) {
-        case 1: hipLaunchKernelGGL((k_cheb_eval_mfma<1, true, KM>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u); break;
-        case 3: hipLaunchKernelGGL((k_cheb_eval_mfma<3, true, KM>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u); break;
-        default: hipLaunchKernelGGL((k_cheb_eval_mfma<9, true, KM>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u); break;
-        }
-    } else {
-        switch (m) {
-        case 1: hipLaunchKernelGGL((k_cheb_eval_mfma<1, false, KM>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u); break;
-        case 3: hipLaunchKernelGGL((k_cheb_eval_mfma<3, false, KM>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u); break;
-        default: hipLaunchKernelGGL((k_cheb_eval_mfma<9, false, KM>), grd, dim3(CB_T), lds, st, g, bsp, pm, lag, U, u); break;
-        }
+    switch (m) {
+    case 1: launch_em<1, KM, NB1>(acc, grd, st, g, bsp, pm, lag, U, u); break;
+    case 3: launch_em<3, KM, 1>(acc, grd, st, g, bsp, pm, lag, U, u); break;
+    default: launch_em<9, KM, 1>(acc, grd, st, g, bsp, pm, lag, U, u); break;
     }
 }
 }  // namespace
@@ -591,15 +627,19 @@ extern "C" int dmk_cheb_eval(const dmk_grid *grid, const dmk_bins *bins, int p, 
     const int64_t nbox = (g.G[0] / p) * (g.G[1] / p) * (g.G[2] / p);
     if (g.N >= 16 * nbox) {
         // boxes of 16 or more points on average: matrix-core contraction per box
-        const size_t elds = sizeof(double) * (size_t)(CB_T / WAVE) * 32 * p;
+        // groups of 2 blocks for one component while p <= 32 (LDS <= 64 KiB)
+        const bool acc = accumulate != 0;
         for (g.wg0 = 0; g.wg0 < nbox; g.wg0 += MAX_WG) {
-        const dim3 grd((unsigned)std::min(MAX_WG, nbox - g.wg0));
-        if ((p + 3) / 4 <= 4)
-            launch_eval_mfma<4>(m, accumulate != 0, grd, elds, stream, g, bsp, pm, lag, u_grid, u);
-        else if ((p + 3) / 4 <= 8)
-            launch_eval_mfma<8>(m, accumulate != 0, grd, elds, stream, g, bsp, pm, lag, u_grid, u);
-        else
-            launch_eval_mfma<KMAX>(m, accumulate != 0, grd, elds, stream, g, bsp, pm, lag, u_grid, u);
+            const dim3 grd((unsigned)std::min(MAX_WG, nbox - g.wg0));
+            const int nkk = (p + 3) / 4;
+            if (nkk <= 4)
+                launch_eval_mfma<4, 2>(m, acc, grd, stream, g, bsp, pm, lag, u_grid, u);
+            else if (nkk <= 5)
+                launch_eval_mfma<5, 2>(m, acc, grd, stream, g, bsp, pm, lag, u_grid, u);
+            else if (nkk <= 8)
+                launch_eval_mfma<8, 2>(m, acc, grd, stream, g, bsp, pm, lag, u_grid, u);
+            else
+                launch_eval_mfma<KMAX, 1>(m, acc, grd, stream, g, bsp, pm, lag, u_grid, u);
         }
         DMK_HIP_CHECK(hipGetLastError());
         return DMK_OK;

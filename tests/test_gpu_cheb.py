@@ -35,6 +35,7 @@ CASES = [
     ((2.0, 1.0, 1.5), 1, (4, 2, 3), 5, 400),
     ((1.0, 1.0, 1.0), 3, (1, 1, 1), 12, 200),
     ((1.0, 1.0, 1.0), 0, (3, 3, 3), 4, 5),     # most boxes empty
+    ((1.0, 1.0, 1.0), 3, (2, 1, 1), 20, 1229),  # ~600 points a box: several block groups per wavefront, ragged tail
 ]
 
 
