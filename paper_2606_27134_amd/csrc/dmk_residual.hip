@@ -803,10 +803,11 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
     };
 
     // Pair step over queue entries [base, base + cnt), cnt <= 64, one per lane.
-    //  * multi-box tiles: a batch holds the pairs of several targets; every
-    //    lane adds its pair term to its target's FP64 sum with an LDS atomic
-    //    add (the target's sums are only touched by this wavefront, one
-    //    instruction after another, so the order is fixed);
+    //  * multi-box tiles: a batch holds the pairs of several targets, each
+    //    target's entries one run of consecutive lanes; a segmented sum over
+    //    the lanes leaves each run's total in its last lane, which adds it to
+    //    the target's FP64 sum (only this wavefront touches that sum, one
+    //    batch after another, so the order is fixed);
     //  * dense tiles: a batch holds one target's pairs; each lane keeps a
     //    running FP32 sum part[] of at most TILE_CAP / 64 terms, reduced when
     //    the target's range in the chunk is done and added to its FP64 sum.
@@ -832,18 +833,13 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
         }
     };
 
-    // evaluate every full batch of the queue, keep the rest (< 64 entries)
+    // evaluate full batches from the top of the queue (its last 64 entries,
+    // in target order like the whole queue) until fewer than 64 are left;
+    // the entries below stay where they are
     auto drain = [&]() {
         wave_sync();
-        const int nfull = qn / WAVE;
-        for (int k = 0; k < nfull; ++k) batch(k * WAVE, WAVE);
-        const int left = qn - nfull * WAVE;
-        uint32_t e = 0;
-        if (lane < left) e = queue[nfull * WAVE + lane];
+        for (; qn >= WAVE; qn -= WAVE) batch(qn - WAVE, WAVE);
         wave_sync();
-        if (lane < left) queue[lane] = e;
-        wave_sync();
-        qn = left;
     };
 
     const int qtot = dense ? S.qtot : S.soff[nslab];
