@@ -7,8 +7,10 @@
 // 4.1.3).  This file builds, all with integer or contraction-free IEEE FP64
 // arithmetic so that the output is bit-exact:
 //   1. the wrapped coordinate y and the box id of every point;
-//   2. a stable LSD radix sort (8-bit digits) of the box ids -> perm, skey;
-//   3. box_start by binary search in the sorted ids;
+//   2. a stable LSD radix sort (digits of up to 9 bits) of the box ids ->
+//      perm, skey;
+//   3. box_start from the key changes of the sorted ids (or by binary search
+//      when there are fewer points than boxes);
 //   4. the sorted wrapped coordinates ys (SoA);
 //   5. the per-axis neighbour / image tables;
 //   6. the target tiles walked by the residual kernels.
@@ -52,42 +54,46 @@ __device__ inline int box_coord(double y, int ax, const BinGeom &g)
     return b;
 }
 
-__global__ void k_bin_keys(const double *__restrict__ x, int64_t N, BinGeom g, int32_t *__restrict__ key,
-                           int32_t *__restrict__ err)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    int b[3];
-    bool ok = true;
-    for (int ax = 0; ax < 3; ++ax) {
-        double y = 0.0;
-        ok = wrap_coord(x[3 * i + ax], ax, g, y) && ok;
-        b[ax] = ok ? box_coord(y, ax, g) : 0;
-    }
-    if (!ok) atomicOr(err, 1);
-    key[i] = ok ? (b[0] * g.n[1] + b[1]) * g.n[2] + b[2] : 0;
-}
 
 // ---------------------------------------------------------------------------
-// 2. stable LSD radix sort of (key, original index), 8-bit digits.
+// 2. stable LSD radix sort of (key, original index), digits of up to 9 bits
+//    (RS_BINS buckets): as few passes as the key width allows.
 constexpr int RS_THREADS = 256;
 constexpr int RS_ITEMS = 8;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+constexpr int RS_MAXBITS = 9;
+constexpr int RS_BINS = 1 << RS_MAXBITS;
+constexpr int RS_BPT = RS_BINS / RS_THREADS;  // buckets per thread
 
-__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const int32_t *__restrict__ keys, int64_t N, int shift,
+// element count: n, or *nptr when given (counts that only the device knows)
+__device__ inline int64_t count_of(int64_t n, const int32_t *nptr, int64_t cap)
+{
+    if (!nptr) return n;
+    const int64_t v = *nptr;
+    return v < 0 ? 0 : (v > cap ? cap : v);
+}
+
+// per-block bucket counts, hist[d * nblk + block] for every bucket d < 2^nbits
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const int32_t *__restrict__ keys, int64_t n,
+                                                        const int32_t *__restrict__ nptr, int shift, int nbits,
                                                         int32_t *__restrict__ hist, int nblk)
 {
-    __shared__ int h[256];
+    __shared__ int h[RS_BINS];
     const int tid = threadIdx.x;
-    h[tid] = 0;
+    const int nb = 1 << nbits, mask = nb - 1;
+    const int64_t N = count_of(n, nptr, n);
+    for (int q = 0; q < RS_BPT; ++q) h[q * RS_THREADS + tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
     for (int r = 0; r < RS_ITEMS; ++r) {
         int64_t i = base + r * RS_THREADS + tid;
-        if (i < N) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+        if (i < N) atomicAdd(&h[(keys[i] >> shift) & mask], 1);
     }
     __syncthreads();
-    hist[(int64_t)tid * nblk + blockIdx.x] = h[tid];
+    for (int q = 0; q < RS_BPT; ++q) {
+        const int d = q * RS_THREADS + tid;
+        if (d < nb) hist[(int64_t)d * nblk + blockIdx.x] = h[d];
+    }
 }
 
 // Exclusive scan of a[0..n) in place.  A chunk of NT x 16 values goes
@@ -217,31 +223,41 @@ void scan_excl(int32_t *a, int64_t n, int32_t *part, hipStream_t s)
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BT), 0, s, a, n, (const int32_t *)part);
 }
 
+// Stable scatter of one pass: each block ranks its elements within their
+// bucket (wavefront match over the digit bits, then the wavefronts in order,
+// then the rounds in order) and writes them at the scanned block offsets.
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__restrict__ kin,
-                                                           const int32_t *__restrict__ vin, int64_t N, int shift,
+                                                           const int32_t *__restrict__ vin, int64_t n,
+                                                           const int32_t *__restrict__ nptr, int shift, int nbits,
                                                            const int32_t *__restrict__ hist, int nblk,
                                                            int32_t *__restrict__ kout, int32_t *__restrict__ vout)
 {
-    __shared__ int base[256];
-    __shared__ int run[256];
-    __shared__ int wcnt[RS_THREADS / WAVE][256];
+    __shared__ int base[RS_BINS];
+    __shared__ int run[RS_BINS];
+    __shared__ int wcnt[RS_THREADS / WAVE][RS_BINS];
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int w = tid / WAVE;
-    base[tid] = hist[(int64_t)tid * nblk + blockIdx.x];
-    run[tid] = 0;
+    const int nb = 1 << nbits, mask = nb - 1;
+    const int64_t N = count_of(n, nptr, n);
+    for (int q = 0; q < RS_BPT; ++q) {
+        const int d = q * RS_THREADS + tid;
+        base[d] = d < nb ? hist[(int64_t)d * nblk + blockIdx.x] : 0;
+        run[d] = 0;
+    }
     const int64_t b0 = (int64_t)blockIdx.x * RS_TILE;
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     for (int r = 0; r < RS_ITEMS; ++r) {
-        for (int q = 0; q < RS_THREADS / WAVE; ++q) wcnt[q][tid] = 0;
+        for (int q = 0; q < RS_THREADS / WAVE; ++q)
+            for (int e = 0; e < RS_BPT; ++e) wcnt[q][e * RS_THREADS + tid] = 0;
         __syncthreads();
         const int64_t i = b0 + r * RS_THREADS + tid;
         const bool valid = i < N;
         const int k = valid ? kin[i] : 0;
         const int v = valid ? (vin ? vin[i] : (int)i) : 0;
-        const int d = (k >> shift) & 255;
+        const int d = (k >> shift) & mask;
         uint64_t m = __ballot(valid);
-        for (int bit = 0; bit < 8; ++bit) {
+        for (int bit = 0; bit < nbits; ++bit) {
             const bool on = (d >> bit) & 1;
             const uint64_t bb = __ballot(valid && on);
             m &= on ? bb : ~bb;
@@ -254,19 +270,64 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__rest
         if (valid) {
             int off = base[d] + run[d];
             for (int q = 0; q < w; ++q) off += wcnt[q][d];
-            kout[off + rank] = k;
-            vout[off + rank] = v;
+            const int64_t o = (int64_t)off + rank;
+            kout[o] = k;
+            vout[o] = v;
         }
         __syncthreads();
-        int add = 0;
-        for (int q = 0; q < RS_THREADS / WAVE; ++q) add += wcnt[q][tid];
-        run[tid] += add;
+        for (int e = 0; e < RS_BPT; ++e) {
+            const int dd = e * RS_THREADS + tid;
+            int add = 0;
+            for (int q = 0; q < RS_THREADS / WAVE; ++q) add += wcnt[q][dd];
+            run[dd] += add;
+        }
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// 3.-5. box_start, sorted coordinates, axis tables
+// 3.-5. sorted coordinates, box_start, axis tables
+
+// ys[ax][j] = wrapped x[perm[j]][ax]: each thread takes GY consecutive sorted
+// points and issues all of its loads before its stores
+constexpr int GY = 4;
+__global__ void k_gather_ys(const double *__restrict__ x, const int32_t *__restrict__ perm, int64_t N, BinGeom g,
+                            double *__restrict__ ys)
+{
+    const int64_t j0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * GY;
+    if (j0 >= N) return;
+    int64_t i[GY];
+    double v[GY][3];
+#pragma unroll
+    for (int u = 0; u < GY; ++u) i[u] = j0 + u < N ? perm[j0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < GY; ++u)
+        for (int ax = 0; ax < 3; ++ax) v[u][ax] = x[3 * i[u] + ax];
+#pragma unroll
+    for (int u = 0; u < GY; ++u)
+        if (j0 + u < N)
+            for (int ax = 0; ax < 3; ++ax) {
+                double y = 0.0;
+                wrap_coord(v[u][ax], ax, g, y);
+                ys[(int64_t)ax * N + j0 + u] = y;
+            }
+}
+
+// box_start from the key changes of the sorted keys: sorted position j is
+// the start of every box b with skey[j-1] < b <= skey[j] (skey[-1] = -1,
+// skey[N] = nbox), so each b in [0, nbox] is written exactly once.  Used when
+// there are at least as many points as boxes (short gaps); otherwise the
+// binary search below.
+__global__ void k_box_start_fill(const int32_t *__restrict__ skey, int64_t N, int64_t nbox,
+                                 int32_t *__restrict__ bs)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > N) return;
+    const int64_t kp = j > 0 ? skey[j - 1] : -1;
+    const int64_t kc = j < N ? skey[j] : nbox;
+    for (int64_t b = kp + 1; b <= kc; ++b) bs[b] = (int32_t)j;
+}
+
 __global__ void k_box_start(const int32_t *__restrict__ skey, int64_t N, int64_t nbox, int32_t *__restrict__ bs)
 {
     int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -283,26 +344,11 @@ __global__ void k_box_start(const int32_t *__restrict__ skey, int64_t N, int64_t
     bs[b] = (int32_t)lo;
 }
 
-__global__ void k_gather_ys(const double *__restrict__ x, const int32_t *__restrict__ perm, int64_t N, BinGeom g,
-                            double *__restrict__ ys)
-{
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    const int64_t i = perm[j];
-    for (int ax = 0; ax < 3; ++ax) {
-        double y = 0.0;
-        wrap_coord(x[3 * i + ax], ax, g, y);
-        ys[(int64_t)ax * N + j] = y;
-    }
-}
-
 // row r of the table (axes stacked: rows [0,n0) axis 0, [n0,n0+n1) axis 1, rest axis 2),
 // column c = offset + 1 for offsets -1, 0, +1.
-__global__ void k_axis_tables(BinGeom g, int32_t *__restrict__ nbr, int8_t *__restrict__ img)
+__device__ inline void axis_table_entry(const BinGeom &g, int e, int32_t *__restrict__ nbr,
+                                        int8_t *__restrict__ img)
 {
-    const int total = g.n[0] + g.n[1] + g.n[2];
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 3 * total) return;
     const int row = e / 3, c = e % 3;
     int ax = 0, b = row;
     if (b >= g.n[0]) {
@@ -331,13 +377,48 @@ __global__ void k_axis_tables(BinGeom g, int32_t *__restrict__ nbr, int8_t *__re
     img[e] = (int8_t)s;
 }
 
+// wrap + box id of point i (i < N), and entry e = i of the axis tables (e <
+// 3 * (n0 + n1 + n2))
+__global__ void k_bin_keys(const double *__restrict__ x, int64_t N, BinGeom g, int32_t *__restrict__ key,
+                           int32_t *__restrict__ err, int32_t *__restrict__ nbr, int8_t *__restrict__ img)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 3 * (int64_t)(g.n[0] + g.n[1] + g.n[2])) axis_table_entry(g, (int)i, nbr, img);
+    if (i >= N) return;
+    int b[3];
+    bool ok = true;
+    for (int ax = 0; ax < 3; ++ax) {
+        double y = 0.0;
+        ok = wrap_coord(x[3 * i + ax], ax, g, y) && ok;
+        b[ax] = ok ? box_coord(y, ax, g) : 0;
+    }
+    if (!ok) atomicOr(err, 1);
+    key[i] = ok ? (b[0] * g.n[1] + b[1]) * g.n[2] + b[2] : 0;
+}
+
 // ---------------------------------------------------------------------------
 // 6. target tiles, one leaf column (b0, b1) at a time.
 struct TileGeom {
     int n[3];
+    int D;
     const int32_t *bs;
-    const int32_t *nbr;
 };
+
+// neighbour index along axis ax of coordinate b at offset off in {-1, 0, 1}:
+// wrapped on a periodic axis, -1 past the end of a free one (the same
+// definition as the axis tables)
+__device__ inline int nb_of(const TileGeom &g, int ax, int b, int off)
+{
+    const int n = g.n[ax];
+    int nb = b + off;
+    if (ax < g.D) {
+        if (nb < 0) nb += n;
+        if (nb >= n) nb -= n;
+    } else if (nb < 0 || nb >= n) {
+        nb = -1;
+    }
+    return nb;
+}
 
 __device__ inline int box_count(const TileGeom &g, int col, int zp)
 {
@@ -350,9 +431,8 @@ __device__ inline int box_count(const TileGeom &g, int col, int zp)
 __device__ inline int phys_z(const TileGeom &g, int zv)
 {
     if (zv >= 0 && zv < g.n[2]) return zv;
-    const int r0 = g.n[0] + g.n[1];
-    if (zv == -1) return g.nbr[3 * r0 + 0];
-    return g.nbr[3 * (r0 + g.n[2] - 1) + 2];
+    if (zv == -1) return nb_of(g, 2, 0, -1);
+    return nb_of(g, 2, g.n[2] - 1, 1);
 }
 
 __device__ inline int slab_count(const TileGeom &g, const int ccol[9], int zv)
@@ -374,10 +454,12 @@ __device__ inline int cost_key(int64_t cost)
 }
 
 // One wavefront per leaf column (b0, b1).  The lanes first stage, for the
-// column's z range, the target count of each box and the slab count (sources
-// in the 9 stencil columns at that z) in LDS; the column is then walked in z,
-// each tile growing while its targets, its staged sources and its z extent
-// fit.  Columns taller than TW_ZST boxes read the rest from the box starts.
+// column's z range, the first target and the target count of each box and
+// the slab count (sources in the 9 stencil columns at that z) in LDS
+// (dynamic: three ints per box, for the first TW_ZST boxes); the column is
+// then walked in z, each tile growing while its targets, its staged sources
+// and its z extent fit.  Columns taller than TW_ZST boxes read the rest from
+// the box starts.
 constexpr int TW_ZST = 2048;
 
 struct ColView {
@@ -385,8 +467,10 @@ struct ColView {
     const int *ccol;
     const int *snt;
     const int *ssl;
+    const int *sbs;
     int col;
     __device__ int nt(int z) const { return z < TW_ZST ? snt[z] : box_count(*g, col, z); }
+    __device__ int first(int z) const { return z < TW_ZST ? sbs[z] : g->bs[(int64_t)col * g->n[2] + z]; }
     // slab count at virtual z in [-1, n2]
     __device__ int sl(int zv) const
     {
@@ -396,25 +480,32 @@ struct ColView {
     }
 };
 
+// Writes (WRITE) or counts the tiles of each column.  The counting pass
+// leaves the last column's count in st[2]; the writing pass, given the
+// scanned counts, the total number of tiles in st[1].
 template <bool WRITE>
 __global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *__restrict__ counts,
-                                                int4 *__restrict__ tiles, int32_t *__restrict__ tkey)
+                                                int4 *__restrict__ tiles, int32_t *__restrict__ tkey,
+                                                int32_t *__restrict__ st)
 {
-    __shared__ int snt[TW_ZST];
-    __shared__ int ssl[TW_ZST];
+    extern __shared__ int tw_lds[];
+    const int n2 = g.n[2];
+    const int zst = n2 < TW_ZST ? n2 : TW_ZST;
+    int *snt = tw_lds, *ssl = tw_lds + zst, *sbs = tw_lds + 2 * zst;
     const int col = col0 + (int)blockIdx.x;
     const int lane = threadIdx.x;
     const int b0 = col / g.n[1], b1 = col % g.n[1];
     int ccol[9];
     for (int k = 0; k < 9; ++k) {
-        const int nb0 = g.nbr[3 * b0 + (k / 3)];
-        const int nb1 = g.nbr[3 * (g.n[0] + b1) + (k % 3)];
+        const int nb0 = nb_of(g, 0, b0, k / 3 - 1);
+        const int nb1 = nb_of(g, 1, b1, k % 3 - 1);
         ccol[k] = (nb0 < 0 || nb1 < 0) ? -1 : nb0 * g.n[1] + nb1;
     }
-    const int n2 = g.n[2];
-    const int zst = n2 < TW_ZST ? n2 : TW_ZST;
     for (int z = lane; z < zst; z += WAVE) {
-        snt[z] = box_count(g, col, z);
+        const int64_t b = (int64_t)col * n2 + z;
+        const int s0 = g.bs[b];
+        snt[z] = g.bs[b + 1] - s0;
+        sbs[z] = s0;
         int sc = 0;
         for (int k = 0; k < 9; ++k) sc += box_count(g, ccol[k], z);
         ssl[z] = sc;
@@ -424,7 +515,7 @@ __global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *_
     // tile starting at z may end at z + l for the l whose extent, targets and
     // staged sources all fit; each of these only grows with l, so the lanes
     // that fit form a prefix and one ballot gives the end.
-    const ColView cv{&g, ccol, snt, ssl, col};
+    const ColView cv{&g, ccol, snt, ssl, sbs, col};
     int cnt = 0;
     const int out = WRITE ? counts[col] : 0;
     int z = 0;
@@ -440,7 +531,7 @@ __global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *_
         }
         const int nt = cv.nt(z);
         const int q1 = cv.sl(z - 1) + cv.sl(z) + cv.sl(z + 1);
-        const int first = g.bs[(int64_t)col * n2 + z];
+        const int first = cv.first(z);
         if (nt > TILE_T || q1 > TILE_CAP) {
             const int nd = (nt + TILE_T - 1) / TILE_T;
             if (WRITE)
@@ -481,7 +572,13 @@ __global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *_
         ++cnt;
         z = z1 + 1;
     }
-    if (!WRITE && lane == 0) counts[col] = cnt;
+    if (lane == 0 && !WRITE) counts[col] = cnt;
+    if (lane == 0 && col == g.n[0] * g.n[1] - 1) {
+        if (WRITE)
+            st[1] = out + cnt;
+        else
+            st[2] = cnt;
+    }
 }
 
 // Final tile order.  Tiles are sorted heavy-first by cost bucket (skey,
@@ -505,9 +602,11 @@ __device__ inline int64_t bound_of(const int32_t *__restrict__ a, int64_t n, int
 }
 
 __global__ void k_gather_tiles(const int4 *__restrict__ tin, const int32_t *__restrict__ order,
-                               const int32_t *__restrict__ skey, int64_t n, int4 *__restrict__ tout)
+                               const int32_t *__restrict__ skey, const int32_t *__restrict__ nptr, int64_t cap,
+                               int4 *__restrict__ tout)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = count_of(0, nptr, cap);
     if (i >= n) return;
     const int32_t key = skey[i];
     const int64_t o = bound_of(skey, n, key, false), B = bound_of(skey, n, key, true) - o;
@@ -518,12 +617,6 @@ __global__ void k_gather_tiles(const int4 *__restrict__ tin, const int32_t *__re
     tout[i] = tin[order[o + start + k / XCDS]];
 }
 
-__global__ void k_tile_total(const int32_t *__restrict__ counts, int ncol, const int32_t *__restrict__ last_raw,
-                             int32_t *__restrict__ status)
-{
-    // counts holds the exclusive scan; last_raw the raw count of the last column
-    status[1] = (ncol > 0) ? counts[ncol - 1] + *last_raw : 0;
-}
 
 }  // namespace dmk
 
@@ -562,7 +655,7 @@ Layout layout_for(const dmk_grid *g, int64_t N)
     const int64_t nblk = (N + RS_TILE - 1) / RS_TILE;
     l.max_tiles = max_tiles_for(N, nbox);
     const int64_t tblk = (l.max_tiles + RS_TILE - 1) / RS_TILE;
-    const int64_t nh = 256 * (nblk > 0 ? nblk : 1), nth = 256 * (tblk > 0 ? tblk : 1);
+    const int64_t nh = (int64_t)RS_BINS * (nblk > 0 ? nblk : 1), nth = (int64_t)RS_BINS * (tblk > 0 ? tblk : 1);
     const int64_t phase1 = 2 * N + nh + scan_part_ints(nh) + 64;
     const int64_t phase2 = (ncol + 64) + 7 * l.max_tiles + nth + scan_part_ints(nth > ncol ? nth : ncol) + 64;
     l.tmp_ints = phase1 > phase2 ? phase1 : phase2;
@@ -662,40 +755,45 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     int32_t *hist = bins->tmp + 2 * N;
 
     DMK_HIP_CHECK(hipMemsetAsync(bins->status, 0, sizeof(int32_t) * 4, stream));
+    // box ids, and the axis tables
+    const int rows = grid->n[0] + grid->n[1] + grid->n[2];
+    hipLaunchKernelGGL(k_bin_keys, dim3(nblocks(std::max(N, (int64_t)3 * rows), 256)), dim3(256), 0, stream, x, N, g,
+                       bins->key, bins->status, bins->axis_nbr, bins->axis_img);
     if (N > 0) {
-        hipLaunchKernelGGL(k_bin_keys, dim3(nblocks(N, 256)), dim3(256), 0, stream, x, N, g, bins->key,
-                           bins->status);
-        // radix passes over ceil(log2(nbox)) bits
+        // radix passes over ceil(log2(nbox)) bits, digits of at most 9 bits
         int bits = 0;
         while (bits < 31 && ((int64_t)1 << bits) < nbox) ++bits;
-        int passes = (bits + 7) / 8;
-        if (passes < 1) passes = 1;
+        const int passes = bits > 0 ? (bits + RS_MAXBITS - 1) / RS_MAXBITS : 1;
+        const int width = bits > 0 ? (bits + passes - 1) / passes : 1;
         const int32_t *kin = bins->key;
         const int32_t *vin = nullptr;
         for (int p = 0; p < passes; ++p) {
             const bool to_final = ((passes - 1 - p) % 2) == 0;
             int32_t *kout = to_final ? bins->skey : altk;
             int32_t *vout = to_final ? bins->perm : altv;
-            hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_THREADS), 0, stream, kin, N, 8 * p, hist,
-                               (int)nblk);
-            scan_excl(hist, (int64_t)256 * nblk, hist + 256 * nblk, stream);
-            hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(RS_THREADS), 0, stream, kin, vin, N, 8 * p,
-                               hist, (int)nblk, kout, vout);
+            const int64_t nh = ((int64_t)1 << width) * nblk;
+            hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_THREADS), 0, stream, kin, N,
+                               (const int32_t *)nullptr, width * p, width, hist, (int)nblk);
+            scan_excl(hist, nh, hist + nh, stream);
+            hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(RS_THREADS), 0, stream, kin, vin, N,
+                               (const int32_t *)nullptr, width * p, width, (const int32_t *)hist, (int)nblk, kout,
+                               vout);
             kin = kout;
             vin = vout;
         }
-        hipLaunchKernelGGL(k_gather_ys, dim3(nblocks(N, 256)), dim3(256), 0, stream, x, bins->perm, N, g,
-                           bins->ys);
+        hipLaunchKernelGGL(k_gather_ys, dim3(nblocks((N + GY - 1) / GY, 256)), dim3(256), 0, stream, x, bins->perm,
+                           N, g, bins->ys);
     }
-    hipLaunchKernelGGL(k_box_start, dim3(nblocks(nbox + 1, 256)), dim3(256), 0, stream, bins->skey, N, nbox,
-                       bins->box_start);
-    const int rows = grid->n[0] + grid->n[1] + grid->n[2];
-    hipLaunchKernelGGL(k_axis_tables, dim3(nblocks(3 * rows, 256)), dim3(256), 0, stream, g, bins->axis_nbr,
-                       bins->axis_img);
+    if (N >= nbox)
+        hipLaunchKernelGGL(k_box_start_fill, dim3(nblocks(N + 1, 256)), dim3(256), 0, stream, bins->skey, N, nbox,
+                           bins->box_start);
+    else
+        hipLaunchKernelGGL(k_box_start, dim3(nblocks(nbox + 1, 256)), dim3(256), 0, stream, bins->skey, N, nbox,
+                           bins->box_start);
     TileGeom tg{};
     for (int i = 0; i < 3; ++i) tg.n[i] = grid->n[i];
+    tg.D = grid->D;
     tg.bs = bins->box_start;
-    tg.nbr = bins->axis_nbr;
     // tile scratch (the point sort is done with tmp by now)
     int32_t *colcnt = bins->tmp;
     int4 *tiles_u = (int4 *)(bins->tmp + ((ncol + 64 + 3) & ~(int64_t)3));
@@ -703,38 +801,42 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     int32_t *tkey2 = tkey + bins->max_tiles;
     int32_t *torder = tkey2 + bins->max_tiles;
     int32_t *thist = torder + bins->max_tiles;
-    // one wavefront per column, in launches of fewer than 2^32 work-items
+    // one wavefront per column, in launches of fewer than 2^32 work-items;
+    // LDS: first target, target count and slab count of each staged box
     constexpr int64_t TCB = 0xffffffffu / WAVE;
+    const size_t tw_lds = sizeof(int) * 3 * (size_t)std::min(grid->n[2], TW_ZST);
     for (int64_t c0 = 0; c0 < ncol; c0 += TCB)
-        hipLaunchKernelGGL(k_tiles<false>, dim3((unsigned)std::min(TCB, ncol - c0)), dim3(WAVE), 0, stream, tg,
-                           (int)c0, colcnt, tiles_u, tkey);
-    // keep the raw count of the last column, scan, then total
-    DMK_HIP_CHECK(hipMemcpyAsync(bins->status + 2, colcnt + ncol - 1, sizeof(int32_t), hipMemcpyDeviceToDevice,
-                                 stream));
-    scan_excl(colcnt, ncol, thist + 256 * ((bins->max_tiles + RS_TILE - 1) / RS_TILE), stream);
+        hipLaunchKernelGGL(k_tiles<false>, dim3((unsigned)std::min(TCB, ncol - c0)), dim3(WAVE), tw_lds, stream, tg,
+                           (int)c0, colcnt, tiles_u, tkey, bins->status);
+    // scan of the per-column counts (the last column's raw count is kept in
+    // status[2]), then the tiles and their total (status[1])
+    scan_excl(colcnt, ncol, thist + RS_BINS * ((bins->max_tiles + RS_TILE - 1) / RS_TILE), stream);
     for (int64_t c0 = 0; c0 < ncol; c0 += TCB)
-        hipLaunchKernelGGL(k_tiles<true>, dim3((unsigned)std::min(TCB, ncol - c0)), dim3(WAVE), 0, stream, tg,
-                           (int)c0, colcnt, tiles_u, tkey);
-    hipLaunchKernelGGL(k_tile_total, dim3(1), dim3(1), 0, stream, colcnt, (int)ncol, bins->status + 2,
-                       bins->status);
+        hipLaunchKernelGGL(k_tiles<true>, dim3((unsigned)std::min(TCB, ncol - c0)), dim3(WAVE), tw_lds, stream, tg,
+                           (int)c0, colcnt, tiles_u, tkey, bins->status);
+    // order the tiles heavy-first (stable within a cost bucket): one pass over
+    // the 6-bit cost key, sized for the most tiles there can be and reading
+    // the actual count from status[1], so that the host waits only once
+    {
+        const int64_t cap = bins->max_tiles;
+        const int64_t tb = (cap + RS_TILE - 1) / RS_TILE;
+        constexpr int TKB = 6;
+        const int64_t nh = ((int64_t)1 << TKB) * tb;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tb), dim3(RS_THREADS), 0, stream, tkey, cap,
+                           (const int32_t *)(bins->status + 1), 0, TKB, thist, (int)tb);
+        scan_excl(thist, nh, thist + nh, stream);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tb), dim3(RS_THREADS), 0, stream, tkey,
+                           (const int32_t *)nullptr, cap, (const int32_t *)(bins->status + 1), 0, TKB,
+                           (const int32_t *)thist, (int)tb, tkey2, torder);
+        hipLaunchKernelGGL(k_gather_tiles, dim3(nblocks(cap, 256)), dim3(256), 0, stream, tiles_u, torder,
+                           (const int32_t *)tkey2, (const int32_t *)(bins->status + 1), cap, (int4 *)bins->tiles);
+    }
     DMK_HIP_CHECK(hipGetLastError());
     int32_t st[4] = {0, 0, 0, 0};
     DMK_HIP_CHECK(hipMemcpyAsync(st, bins->status, sizeof(st), hipMemcpyDeviceToHost, stream));
     DMK_HIP_CHECK(hipStreamSynchronize(stream));
     if (st[0] != 0) return DMK_EDOMAIN;
     if (st[1] < 0 || st[1] > bins->max_tiles) return DMK_ESIZE;
-    // order the tiles heavy-first (stable within a cost bucket)
-    const int64_t nt = st[1];
-    if (nt > 0) {
-        const int64_t tb = (nt + RS_TILE - 1) / RS_TILE;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tb), dim3(RS_THREADS), 0, stream, tkey, nt, 0, thist, (int)tb);
-        scan_excl(thist, (int64_t)256 * tb, thist + 256 * tb, stream);
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tb), dim3(RS_THREADS), 0, stream, tkey,
-                           (const int32_t *)nullptr, nt, 0, thist, (int)tb, tkey2, torder);
-        hipLaunchKernelGGL(k_gather_tiles, dim3(nblocks(nt, 256)), dim3(256), 0, stream, tiles_u, torder,
-                           (const int32_t *)tkey2, nt, (int4 *)bins->tiles);
-        DMK_HIP_CHECK(hipGetLastError());
-    }
     bins->ntiles = st[1];
     return DMK_OK;
 }
