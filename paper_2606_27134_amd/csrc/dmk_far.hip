@@ -17,8 +17,9 @@
 //
 //   Y[a][o][c] = s * sum_i coef(i, o) X[a][i][c]
 //
-// with coef a view of one of the E_i tables.  On a cover of the cell by cut
-// cubes every contraction is such a direct sum.  On an exact tiling, an axis
+// with coef a view of one of the E_i tables (grids with no axis factored
+// over the cube index run all of this in three fused launches, k_far_c1..3).
+// On a cover of the cell by cut cubes every contraction is such a direct sum.  On an exact tiling, an axis
 // of 8 or more cubes factors through a DFT over the cube index (Sec. 4, large
 // aspect ratios): a dense product on the matrix cores up to 64 cubes, an FFT
 // (mixed-radix Stockham stages, or Bluestein's chirp convolution for lengths
@@ -702,6 +703,54 @@ __global__ __launch_bounds__(PREP_T) void k_far_prep(FarGeom g, FarWin w, double
     far_phihat_mode(g, w, PH, m, threadIdx.x & (WAVE - 1));
 }
 
+// sum_q Khat_jq(k) x[q] for the kernel's mollified Fourier symbol at wave
+// vector k (k2 = |k|^2, q = |k| sigma, ph / dph = phihat and phihat' at q)
+template <int KERN>
+__device__ inline void mode_weight(const double k[3], double k2, double q, double ph, double dph, const double2 *x,
+                                   double2 *out)
+{
+    const double Hh = ph / k2;
+    const double Bh = (ph - 0.5 * q * dph) / (k2 * k2);
+    if constexpr (KERN == 0) {
+        out[0] = make_double2(Hh * x[0].x, Hh * x[0].y);
+    } else if constexpr (KERN == 1) {
+        for (int j = 0; j < 3; ++j) {
+            double re = 0.0, im = 0.0;
+            for (int l = 0; l < 3; ++l) {
+                const double K = ((j == l ? k2 : 0.0) - k[j] * k[l]) * Bh;
+                re += K * x[l].x;
+                im += K * x[l].y;
+            }
+            out[j] = make_double2(re, im);
+        }
+    } else if constexpr (KERN == 2) {
+        // i * T: multiplying by i maps (re, im) to (-im, re)
+        for (int j = 0; j < 3; ++j) {
+            double re = 0.0, im = 0.0;
+            for (int l = 0; l < 3; ++l)
+                for (int mm = 0; mm < 3; ++mm) {
+                    const double T = ((j == l ? k[mm] : 0.0) + (l == mm ? k[j] : 0.0) + (mm == j ? k[l] : 0.0)) * k2 -
+                                     2.0 * k[j] * k[l] * k[mm];
+                    const double K = T * Bh;
+                    re += K * x[3 * l + mm].x;
+                    im += K * x[3 * l + mm].y;
+                }
+            out[j] = make_double2(-im, re);
+        }
+    } else {
+        // sum_l -(i/2) eps_jlm k_m Hhat chi_l = (i/2) Hhat (k x chi)_j
+        const double h = 0.5 * Hh;
+        const double cr[3] = {k[1] * x[2].x - k[2] * x[1].x, k[2] * x[0].x - k[0] * x[2].x,
+                              k[0] * x[1].x - k[1] * x[0].x};
+        const double ci[3] = {k[1] * x[2].y - k[2] * x[1].y, k[2] * x[0].y - k[0] * x[2].y,
+                              k[0] * x[1].y - k[1] * x[0].y};
+        // i h (cr + i ci) = (-h ci, h cr)
+        for (int j = 0; j < 3; ++j) out[j] = make_double2(-h * ci[j], h * cr[j]);
+    }
+    (void)Bh;
+    (void)Hh;
+}
+
 // W[j][m] = sum_q Khat_jq(k_m) chi[q][m] for every mode m (0 at k = 0), one
 // thread per mode, with phihat and phihat' from the octant table
 constexpr int FW_T = 256;
@@ -729,8 +778,6 @@ __global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, double sigma, c
             ((int64_t)abs(n0) * (g.K[1] + 1) + abs(n1)) * (int64_t)(g.K[2] + 1) + abs(n2);
         const double2 pd = PH[o];
         const double ph = pd.x, dph = pd.y;
-        const double Hh = ph / k2;
-        const double Bh = (ph - 0.5 * q * dph) / (k2 * k2);
         double2 x[MI];
         if (nsplit > 1) {
             // chi from the split partial results of its contraction, added in
@@ -747,44 +794,229 @@ __global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, double sigma, c
         } else {
             for (int c = 0; c < MI; ++c) x[c] = chi[c * nm + m];
         }
-        if constexpr (KERN == 0) {
-            out[0] = make_double2(Hh * x[0].x, Hh * x[0].y);
-        } else if constexpr (KERN == 1) {
-            for (int j = 0; j < 3; ++j) {
-                double re = 0.0, im = 0.0;
-                for (int l = 0; l < 3; ++l) {
-                    const double K = ((j == l ? k2 : 0.0) - k[j] * k[l]) * Bh;
-                    re += K * x[l].x;
-                    im += K * x[l].y;
-                }
-                out[j] = make_double2(re, im);
-            }
-        } else if constexpr (KERN == 2) {
-            // i * T: multiplying by i maps (re, im) to (-im, re)
-            for (int j = 0; j < 3; ++j) {
-                double re = 0.0, im = 0.0;
-                for (int l = 0; l < 3; ++l)
-                    for (int mm = 0; mm < 3; ++mm) {
-                        const double T = ((j == l ? k[mm] : 0.0) + (l == mm ? k[j] : 0.0) + (mm == j ? k[l] : 0.0)) * k2 -
-                                         2.0 * k[j] * k[l] * k[mm];
-                        const double K = T * Bh;
-                        re += K * x[3 * l + mm].x;
-                        im += K * x[3 * l + mm].y;
-                    }
-                out[j] = make_double2(-im, re);
-            }
-        } else {
-            // sum_l -(i/2) eps_jlm k_m Hhat chi_l = (i/2) Hhat (k x chi)_j
-            const double h = 0.5 * Hh;
-            const double cr[3] = {k[1] * x[2].x - k[2] * x[1].x, k[2] * x[0].x - k[0] * x[2].x,
-                                  k[0] * x[1].x - k[1] * x[0].x};
-            const double ci[3] = {k[1] * x[2].y - k[2] * x[1].y, k[2] * x[0].y - k[0] * x[2].y,
-                                  k[0] * x[1].y - k[1] * x[0].y};
-            // i h (cr + i ci) = (-h ci, h cr)
-            for (int j = 0; j < 3; ++j) out[j] = make_double2(-h * ci[j], h * cr[j]);
-        }
+        mode_weight<KERN>(k, k2, q, ph, dph, x, out);
     }
     for (int j = 0; j < MO; ++j) Wt[j * nm + m] = out[j];
+}
+
+// ---------------------------------------------------------------------------
+// Small grids (no axis factored over the cube index): the whole far field in
+// three launches.  Each workgroup keeps its share in LDS and computes the
+// phase factors it needs itself (as the table entries above):
+//   k_far_c1, one (component, g0) slab:  T2[q][g0][n1][n2] = sum_g1 conj(E1)
+//             sum_g2 conj(E2) rho[q][g0][g1][g2];
+//   k_far_c2, one (n1, n2) pencil: chi over g0 (scaled by 1/|Omega|), the
+//             window's transform of its octant modes, the mode weights, and
+//             back over n0: V1[j][g0][n1][n2];
+//   k_far_c3, one (component, g0) slab: u[j][g0][g1][g2] = Re sum_n2 E2
+//             sum_n1 E1 V1[j][g0][n1][n2].
+// Every sum takes the fused multiply-adds of k_mode, split over the lanes in a
+// fixed order (wg_sums).
+constexpr int FC_T = 256;
+constexpr size_t FC_LDS = 64 * 1024;
+
+// Sums of a workgroup: out o (o < nout) = sum over i < nin of the terms that
+// acc(o, i, re, im) adds.  Each output takes L lanes of one wavefront (L a
+// power of two, as many as the FC_T threads allow, at most 64); lane r of the
+// group adds the terms i = r, r + L, ... in order, and the L partial sums are
+// combined by xor shuffles, so the order of every sum is fixed.  st(o, re,
+// im) stores the result (called by the group's first lane).
+template <class Acc, class Store>
+__device__ inline void wg_sums(int nout, int nin, int tid, Acc acc, Store st)
+{
+    int L = 1;
+    while (L < WAVE && 2 * L * nout <= FC_T && 2 * L <= nin) L *= 2;
+    const int per = FC_T / L;  // outputs per round
+    for (int o0 = 0; o0 < nout; o0 += per) {
+        const int o = o0 + tid / L, r = tid & (L - 1);
+        double re = 0.0, im = 0.0;
+        if (o < nout) {
+#pragma unroll 4
+            for (int i = r; i < nin; i += L) acc(o, i, re, im);
+        }
+        for (int off = L / 2; off > 0; off >>= 1) {
+            re += __shfl_xor(re, off);
+            im += __shfl_xor(im, off);
+        }
+        if (o < nout && r == 0) st(o, re, im);
+    }
+}
+
+// E_i[gi][n], n >= 0 (the table entry far_table_entry writes)
+__device__ inline double2 far_phase(const FarGeom &g, int ax, int gi, int n)
+{
+    const int b = gi / g.p, j = gi % g.p;
+    const double v = (double)b + 0.5 + 0.5 * cospi((double)(2 * j + 1) / (double)(2 * g.p));
+    const double xr = g.cover ? v * g.hr[ax] : v / (double)g.M[ax];
+    double sn, cs;
+    sincospi(2.0 * (double)n * xr, &sn, &cs);
+    return make_double2(cs, sn);
+}
+
+// the imaginary part of E_i[.][n] (n of either sign) from the row of n >= 0
+__device__ inline double phase_im(const double2 e, int n) { return n < 0 ? -e.y : e.y; }
+
+__device__ inline void fill_phases(const FarGeom &g, int ax, double2 *e, int tid)
+{
+    const int kk = g.K[ax] + 1;
+    for (int t = tid; t < g.G[ax] * kk; t += FC_T) e[t] = far_phase(g, ax, t / kk, t % kk);
+}
+
+__global__ __launch_bounds__(FC_T) void k_far_c1(FarGeom g, const double *__restrict__ rho, double2 *__restrict__ T2)
+{
+    extern __shared__ double2 fc_lds[];
+    const int G1 = g.G[1], G2 = g.G[2], W1 = g.W[1], W2 = g.W[2], K1 = g.K[1], K2 = g.K[2];
+    double2 *e2 = fc_lds;
+    double2 *e1 = e2 + G2 * (K2 + 1);
+    double2 *t1 = e1 + G1 * (K1 + 1);
+    double *x = (double *)(t1 + G1 * W2);
+    const int64_t a = blockIdx.x;  // q * G0 + g0
+    const int tid = threadIdx.x;
+    fill_phases(g, 2, e2, tid);
+    fill_phases(g, 1, e1, tid);
+    const double *xs = rho + a * G1 * G2;
+    for (int t = tid; t < G1 * G2; t += FC_T) x[t] = xs[t];
+    __syncthreads();
+    wg_sums(
+        G1 * W2, G2, tid,
+        [&](int t, int i, double &re, double &im) {
+            const int g1 = t / W2, n = t % W2 - K2;
+            const double2 e = e2[i * (K2 + 1) + (n < 0 ? -n : n)];
+            const double ei = -phase_im(e, n);
+            const double xv = x[g1 * G2 + i];
+            re = fma(e.x, xv, re);
+            im = fma(ei, xv, im);
+        },
+        [&](int t, double re, double im) { t1[t] = make_double2(re, im); });
+    __syncthreads();
+    double2 *out = T2 + a * W1 * W2;
+    wg_sums(
+        W1 * W2, G1, tid,
+        [&](int t, int i, double &re, double &im) {
+            const int n = t / W2 - K1, c = t % W2;
+            const double2 e = e1[i * (K1 + 1) + (n < 0 ? -n : n)];
+            const double ei = -phase_im(e, n);
+            const double2 xv = t1[i * W2 + c];
+            re = fma(e.x, xv.x, fma(-ei, xv.y, re));
+            im = fma(e.x, xv.y, fma(ei, xv.x, im));
+        },
+        [&](int t, double re, double im) { out[t] = make_double2(re, im); });
+}
+
+template <int KERN>
+__global__ __launch_bounds__(FC_T) void k_far_c2(FarGeom g, FarWin w, double sigma, double invV,
+                                                 const double2 *__restrict__ T2, double2 *__restrict__ V1)
+{
+    constexpr int MI = KERN == 0 ? 1 : (KERN == 2 ? 9 : 3);
+    constexpr int MO = KERN == 0 ? 1 : 3;
+    extern __shared__ double2 fc_lds[];
+    const int G0 = g.G[0], W0 = g.W[0], W1 = g.W[1], W2 = g.W[2], K0 = g.K[0];
+    double2 *e0 = fc_lds;
+    double2 *xp = e0 + G0 * (K0 + 1);  // [MI][G0]
+    double2 *ch = xp + MI * G0;        // [MI][W0]
+    double2 *ph = ch + MI * W0;        // [K0 + 1]
+    double2 *wo = ph + (K0 + 1);       // [MO][W0]
+    const int n1i = (int)blockIdx.x / W2, n2i = (int)blockIdx.x % W2;
+    const int n1 = n1i - g.K[1], n2 = n2i - g.K[2];
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    fill_phases(g, 0, e0, tid);
+    for (int t = tid; t < MI * G0; t += FC_T) xp[t] = T2[((int64_t)t * W1 + n1i) * W2 + n2i];
+    // phihat and phihat' of the octant modes (|n0|, |n1|, |n2|), one wavefront each
+    for (int a0 = wv; a0 <= K0; a0 += FC_T / WAVE) {
+        const int a1 = n1 < 0 ? -n1 : n1, a2 = n2 < 0 ? -n2 : n2;
+        double p0 = 0.0, p1 = 0.0;
+        if (a0 != 0 || a1 != 0 || a2 != 0) {
+            const double k[3] = {2.0 * M_PI * a0 / g.L[0], 2.0 * M_PI * a1 / g.L[1], 2.0 * M_PI * a2 / g.L[2]};
+            const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+            win_hat(w, sqrt(k2) * w.sigma, lane, p0, p1);
+        }
+        if (lane == 0) ph[a0] = make_double2(p0, p1);
+    }
+    __syncthreads();
+    wg_sums(
+        MI * W0, G0, tid,
+        [&](int t, int i, double &re, double &im) {
+            const int q = t / W0, n = t % W0 - K0;
+            const double2 e = e0[i * (K0 + 1) + (n < 0 ? -n : n)];
+            const double ei = -phase_im(e, n);
+            const double2 xv = xp[q * G0 + i];
+            re = fma(e.x, xv.x, fma(-ei, xv.y, re));
+            im = fma(e.x, xv.y, fma(ei, xv.x, im));
+        },
+        [&](int t, double re, double im) { ch[t] = make_double2(invV * re, invV * im); });
+    __syncthreads();
+    // mode weights (as k_far_weights)
+    for (int i = tid; i < W0; i += FC_T) {
+        const int n0 = i - K0;
+        double2 out[MO];
+        for (int j = 0; j < MO; ++j) out[j] = make_double2(0.0, 0.0);
+        if (n0 != 0 || n1 != 0 || n2 != 0) {
+            const double k[3] = {2.0 * M_PI * n0 / g.L[0], 2.0 * M_PI * n1 / g.L[1], 2.0 * M_PI * n2 / g.L[2]};
+            const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+            const double q = sqrt(k2) * sigma;
+            const double2 pd = ph[n0 < 0 ? -n0 : n0];
+            double2 x[MI];
+            for (int c = 0; c < MI; ++c) x[c] = ch[c * W0 + i];
+            mode_weight<KERN>(k, k2, q, pd.x, pd.y, x, out);
+        }
+        for (int j = 0; j < MO; ++j) wo[j * W0 + i] = out[j];
+    }
+    __syncthreads();
+    wg_sums(
+        MO * G0, W0, tid,
+        [&](int t, int i, double &re, double &im) {
+            const int j = t / G0, g0 = t % G0, n = i - K0;
+            const double2 e = e0[g0 * (K0 + 1) + (n < 0 ? -n : n)];
+            const double ei = phase_im(e, n);
+            const double2 xv = wo[j * W0 + i];
+            re = fma(e.x, xv.x, fma(-ei, xv.y, re));
+            im = fma(e.x, xv.y, fma(ei, xv.x, im));
+        },
+        [&](int t, double re, double im) { V1[((int64_t)t * W1 + n1i) * W2 + n2i] = make_double2(re, im); });
+}
+
+__global__ __launch_bounds__(FC_T) void k_far_c3(FarGeom g, const double2 *__restrict__ V1, double *__restrict__ u)
+{
+    extern __shared__ double2 fc_lds[];
+    const int G1 = g.G[1], G2 = g.G[2], W1 = g.W[1], W2 = g.W[2], K1 = g.K[1], K2 = g.K[2];
+    double2 *e1 = fc_lds;
+    double2 *e2 = e1 + G1 * (K1 + 1);
+    double2 *v1 = e2 + G2 * (K2 + 1);  // [W1][W2]
+    double2 *v2 = v1 + W1 * W2;        // [G1][W2]
+    const int64_t a = blockIdx.x;      // j * G0 + g0
+    const int tid = threadIdx.x;
+    fill_phases(g, 1, e1, tid);
+    fill_phases(g, 2, e2, tid);
+    const double2 *vs = V1 + a * W1 * W2;
+    for (int t = tid; t < W1 * W2; t += FC_T) v1[t] = vs[t];
+    __syncthreads();
+    wg_sums(
+        G1 * W2, W1, tid,
+        [&](int t, int i, double &re, double &im) {
+            const int g1 = t / W2, c = t % W2, n = i - K1;
+            const double2 e = e1[g1 * (K1 + 1) + (n < 0 ? -n : n)];
+            const double ei = phase_im(e, n);
+            const double2 xv = v1[i * W2 + c];
+            re = fma(e.x, xv.x, fma(-ei, xv.y, re));
+            im = fma(e.x, xv.y, fma(ei, xv.x, im));
+        },
+        [&](int t, double re, double im) { v2[t] = make_double2(re, im); });
+    __syncthreads();
+    double *out = u + a * G1 * G2;
+    wg_sums(
+        G1 * G2, W2, tid,
+        [&](int t, int i, double &re, double &im) {
+            const int g1 = t / G2, g2 = t % G2, n = i - K2;
+            const double2 e = e2[g2 * (K2 + 1) + (n < 0 ? -n : n)];
+            const double ei = phase_im(e, n);
+            const double2 xv = v2[g1 * W2 + i];
+            re = fma(e.x, xv.x, fma(-ei, xv.y, re));
+            (void)im;
+        },
+        [&](int t, double re, double im) {
+            (void)im;
+            out[t] = re;
+        });
 }
 
 int m_in_k(int k) { return k == 0 ? 1 : (k == 2 ? 9 : 3); }
@@ -1214,6 +1446,32 @@ void contract_eval(const FarGeom &g, int ax, int64_t comps, const double2 *X, co
         mode<false, ROUT, false>(Z, E + g.doff[ax], ac.A, M, M, g.p * ac.C, M, 1, 1.0, Y, part, st);
 }
 
+// LDS bytes of the three compact kernels, or 0 where the compact form does
+// not apply (an axis factored over the cube index)
+struct FarCompact {
+    size_t l1, l2, l3;
+};
+
+inline FarCompact far_compact(const FarGeom &g, int64_t Q, int64_t J)
+{
+    FarCompact c{0, 0, 0};
+    for (int ax = 0; ax < 3; ++ax)
+        if (g.fac[ax]) return c;
+    const size_t z = sizeof(double2);
+    const size_t G0 = g.G[0], G1 = g.G[1], G2 = g.G[2], W0 = g.W[0], W1 = g.W[1], W2 = g.W[2];
+    const size_t k0 = g.K[0] + 1, k1 = g.K[1] + 1, k2 = g.K[2] + 1;
+    const size_t l1 = z * (G2 * k2 + G1 * k1 + G1 * W2) + sizeof(double) * G1 * G2;
+    const size_t l2 = z * (G0 * k0 + Q * G0 + Q * W0 + k0 + J * W0);
+    const size_t l3 = z * (G1 * k1 + G2 * k2 + W1 * W2 + G1 * W2);
+    if (l1 > FC_LDS || l2 > FC_LDS || l3 > FC_LDS) return c;
+    if (!grid_fits(Q * (int64_t)G0, FC_T) || !grid_fits((int64_t)W1 * W2, FC_T) || !grid_fits(J * (int64_t)G0, FC_T))
+        return c;
+    c.l1 = l1;
+    c.l2 = l2;
+    c.l3 = l3;
+    return c;
+}
+
 struct FarLayout {
     int64_t E, T1, T2, CHI, WT, V1, V2, PH, PART, Z, FA, FB, total;  // byte offsets
 };
@@ -1338,6 +1596,21 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     const int W0 = g.W[0], W1 = g.W[1], W2 = g.W[2];
     const double invV = 1.0 / (g.L[0] * g.L[1] * g.L[2]);
 
+    // small grids: three launches, each workgroup holding its share in LDS
+    const FarCompact fc = far_compact(g, Q, J);
+    if (fc.l1) {
+        hipLaunchKernelGGL(k_far_c1, dim3((unsigned)(Q * g.G[0])), dim3(FC_T), fc.l1, stream, g, rho_grid, T2);
+        const dim3 gp((unsigned)((int64_t)W1 * W2));
+        switch (kernel) {
+        case 0: hipLaunchKernelGGL(k_far_c2<0>, gp, dim3(FC_T), fc.l2, stream, g, w, sigma0, invV, T2, V1); break;
+        case 1: hipLaunchKernelGGL(k_far_c2<1>, gp, dim3(FC_T), fc.l2, stream, g, w, sigma0, invV, T2, V1); break;
+        case 2: hipLaunchKernelGGL(k_far_c2<2>, gp, dim3(FC_T), fc.l2, stream, g, w, sigma0, invV, T2, V1); break;
+        default: hipLaunchKernelGGL(k_far_c2<3>, gp, dim3(FC_T), fc.l2, stream, g, w, sigma0, invV, T2, V1); break;
+        }
+        hipLaunchKernelGGL(k_far_c3, dim3((unsigned)(J * g.G[0])), dim3(FC_T), fc.l3, stream, g, V1, u_grid);
+        DMK_HIP_CHECK(hipGetLastError());
+        return DMK_OK;
+    }
     const int64_t ne = g.nE + g.nD;
     const int64_t no = (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1);
     const unsigned nbt = (unsigned)nblk(ne, PREP_T);
