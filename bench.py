@@ -263,6 +263,8 @@ def roofline(kernel, prec, P_in, r, khash=None, workload=None):
         roof["valu_issue_frac"] = None if vi is None else vi.get(dom)
         ex = read_traffic(workload, prec, khash, field="valu_tflops")
         roof["valu_executed_tflops"] = None if ex is None else ex.get(dom)
+        lu = read_traffic(workload, prec, khash, field="lane_utilisation")
+        roof["valu_lane_utilisation"] = None if lu is None else lu.get(dom)
     return roof
 
 
