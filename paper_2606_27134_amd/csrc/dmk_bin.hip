@@ -65,23 +65,22 @@ constexpr int RS_MAXBITS = 9;
 constexpr int RS_BINS = 1 << RS_MAXBITS;
 constexpr int RS_BPT = RS_BINS / RS_THREADS;  // buckets per thread
 
-// element count: n, or *nptr when given (counts that only the device knows)
-__device__ inline int64_t count_of(int64_t n, const int32_t *nptr, int64_t cap)
-{
-    if (!nptr) return n;
-    const int64_t v = *nptr;
-    return v < 0 ? 0 : (v > cap ? cap : v);
-}
+// Workgroup barrier that orders LDS only: waits for this wavefront's LDS
+// operations, not for its global stores (__syncthreads also waits for those,
+// which costs a memory round trip where no thread reads them back).
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Order of LDS accesses within one wavefront (which the LDS unit serves in
+// order): a compiler fence only.
+__device__ inline void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 // per-block bucket counts, hist[d * nblk + block] for every bucket d < 2^nbits
-__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const int32_t *__restrict__ keys, int64_t n,
-                                                        const int32_t *__restrict__ nptr, int shift, int nbits,
-                                                        int32_t *__restrict__ hist, int nblk)
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const int32_t *__restrict__ keys, int64_t N, int shift,
+                                                        int nbits, int32_t *__restrict__ hist, int nblk)
 {
     __shared__ int h[RS_BINS];
     const int tid = threadIdx.x;
     const int nb = 1 << nbits, mask = nb - 1;
-    const int64_t N = count_of(n, nptr, n);
     for (int q = 0; q < RS_BPT; ++q) h[q * RS_THREADS + tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
@@ -123,7 +122,7 @@ __device__ int scan_chunk(int32_t *__restrict__ a, int64_t base, int m, int carr
         const int i = r * NT + tid;
         buf[scan_pad(i)] = i < m ? a[base + i] : 0;
     }
-    __syncthreads();
+    lds_barrier();
     int v[SCAN_I];
     int tsum = 0;
 #pragma unroll
@@ -138,7 +137,7 @@ __device__ int scan_chunk(int32_t *__restrict__ a, int64_t base, int m, int carr
         if (lane >= off) x += y;
     }
     if (lane == WAVE - 1) wsum[w] = x;
-    __syncthreads();
+    lds_barrier();
     int wpre = 0, tot = 0;
 #pragma unroll
     for (int q = 0; q < NT / WAVE; ++q) {
@@ -152,12 +151,12 @@ __device__ int scan_chunk(int32_t *__restrict__ a, int64_t base, int m, int carr
         buf[scan_pad(tid * SCAN_I + i)] = run;
         run += v[i];
     }
-    __syncthreads();
+    lds_barrier();
     for (int r = 0; r < SCAN_I; ++r) {
         const int i = r * NT + tid;
         if (i < m) a[base + i] = buf[scan_pad(i)];
     }
-    __syncthreads();  // buf and wsum are rewritten by the next chunk
+    lds_barrier();  // buf and wsum are rewritten by the next chunk
     return tot;
 }
 
@@ -226,36 +225,44 @@ void scan_excl(int32_t *a, int64_t n, int32_t *part, hipStream_t s)
 // Stable scatter of one pass: each block ranks its elements within their
 // bucket (wavefront match over the digit bits, then the wavefronts in order,
 // then the rounds in order) and writes them at the scanned block offsets.
+// Every thread loads its RS_ITEMS keys and values before the first round.
+// wcnt[w][d] holds wavefront w's count of digit d in the current round and is
+// zero otherwise: the lane that writes an entry clears it once the round's
+// offsets are read.  base[d] is the block's next output of digit d; the
+// last wavefront holding d in a round advances it by the round's count, and
+// the next round reads it after its first barrier.
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__restrict__ kin,
-                                                           const int32_t *__restrict__ vin, int64_t n,
-                                                           const int32_t *__restrict__ nptr, int shift, int nbits,
+                                                           const int32_t *__restrict__ vin, int64_t N,
+                                                           int shift, int nbits,
                                                            const int32_t *__restrict__ hist, int nblk,
                                                            int32_t *__restrict__ kout, int32_t *__restrict__ vout)
 {
+    constexpr int NWV = RS_THREADS / WAVE;
     __shared__ int base[RS_BINS];
-    __shared__ int run[RS_BINS];
-    __shared__ int wcnt[RS_THREADS / WAVE][RS_BINS];
+    __shared__ int wcnt[NWV][RS_BINS];
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int w = tid / WAVE;
     const int nb = 1 << nbits, mask = nb - 1;
-    const int64_t N = count_of(n, nptr, n);
+    const int64_t b0 = (int64_t)blockIdx.x * RS_TILE;
+    int kk[RS_ITEMS], vv[RS_ITEMS];
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int64_t i = b0 + r * RS_THREADS + tid;
+        kk[r] = i < N ? kin[i] : 0;
+        vv[r] = i < N ? (vin ? vin[i] : (int)i) : 0;
+    }
     for (int q = 0; q < RS_BPT; ++q) {
         const int d = q * RS_THREADS + tid;
         base[d] = d < nb ? hist[(int64_t)d * nblk + blockIdx.x] : 0;
-        run[d] = 0;
+        for (int u = 0; u < NWV; ++u) wcnt[u][d] = 0;
     }
-    const int64_t b0 = (int64_t)blockIdx.x * RS_TILE;
+    __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+#pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
-        for (int q = 0; q < RS_THREADS / WAVE; ++q)
-            for (int e = 0; e < RS_BPT; ++e) wcnt[q][e * RS_THREADS + tid] = 0;
-        __syncthreads();
-        const int64_t i = b0 + r * RS_THREADS + tid;
-        const bool valid = i < N;
-        const int k = valid ? kin[i] : 0;
-        const int v = valid ? (vin ? vin[i] : (int)i) : 0;
-        const int d = (k >> shift) & mask;
+        const bool valid = b0 + r * RS_THREADS + tid < N;
+        const int d = (kk[r] >> shift) & mask;
         uint64_t m = __ballot(valid);
         for (int bit = 0; bit < nbits; ++bit) {
             const bool on = (d >> bit) & 1;
@@ -265,23 +272,27 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__rest
         if (!valid) m = 0;
         const int rank = __popcll(m & below);
         const bool last = valid && ((m >> lane) == 1ull);
-        if (last) wcnt[w][d] = __popcll(m);
-        __syncthreads();
+        const int cnt = __popcll(m);
+        if (last) wcnt[w][d] = cnt;
+        lds_barrier();
+        int nbase = -1;  // new base of d, set by the last wavefront holding d
         if (valid) {
-            int off = base[d] + run[d];
+            int off = base[d];
             for (int q = 0; q < w; ++q) off += wcnt[q][d];
             const int64_t o = (int64_t)off + rank;
-            kout[o] = k;
-            vout[o] = v;
+            kout[o] = kk[r];
+            vout[o] = vv[r];
+            if (last) {
+                bool final = true;
+                for (int q = w + 1; q < NWV; ++q) final = final && wcnt[q][d] == 0;
+                if (final) nbase = off + cnt;
+            }
         }
-        __syncthreads();
-        for (int e = 0; e < RS_BPT; ++e) {
-            const int dd = e * RS_THREADS + tid;
-            int add = 0;
-            for (int q = 0; q < RS_THREADS / WAVE; ++q) add += wcnt[q][dd];
-            run[dd] += add;
+        lds_barrier();
+        if (last) {
+            if (nbase >= 0) base[d] = nbase;
+            wcnt[w][d] = 0;
         }
-        __syncthreads();
     }
 }
 
@@ -445,12 +456,34 @@ __device__ inline int slab_count(const TileGeom &g, const int ccol[9], int zv)
 }
 
 // Cost of a tile = sum over its targets of the size of their stencil ranges.
-// The key orders tiles heavy-first by power-of-two cost bucket, so a stable
-// sort by key keeps spatially adjacent tiles of similar cost together.
-__device__ inline int cost_key(int64_t cost)
+// Tiles are ordered heavy-first by power-of-two cost class: class 0 holds the
+// costs of bit length TK_CLASSES and more, class TK_CLASSES - 1 those of bit
+// length 1.  A tile's cost is below 2^37 (at most 64 targets times a
+// three-slab neighbourhood of fewer than 2^30 points), so no two bit lengths
+// share a class.
+constexpr int TK_CLASSES = 40;
+__device__ inline int tile_class(int64_t cost)
 {
-    const int bucket = 64 - __clzll((unsigned long long)(cost + 1));
-    return 64 - bucket;
+    const int len = 64 - __clzll((unsigned long long)(cost + 1));
+    return TK_CLASSES - (len < TK_CLASSES ? len : TK_CLASSES);
+}
+
+// Final position of the tile of stable rank r in a class of B tiles at
+// offset o.  Workgroup i of the pair kernels runs on XCD i mod 8; within the
+// class the positions o + k with k mod 8 = q (one XCD) take the q-th
+// contiguous run of the class's tiles, so every XCD works on a spatially
+// compact share of every class (tiles that stage the same neighbour columns
+// meet in one L2) and the heavy classes stay spread over all XCDs.
+__device__ inline int64_t xcd_position(int64_t o, int64_t B, int64_t r)
+{
+    int64_t start = 0;
+    int q = 0;
+    for (; q < XCDS - 1; ++q) {
+        const int64_t len = q < B ? (B - q + XCDS - 1) / XCDS : 0;  // run of XCD q
+        if (r < start + len) break;
+        start += len;
+    }
+    return o + XCDS * (r - start) + q;
 }
 
 // One wavefront per leaf column (b0, b1).  The lanes first stage, for the
@@ -480,18 +513,25 @@ struct ColView {
     }
 };
 
-// Writes (WRITE) or counts the tiles of each column.  The counting pass
-// leaves the last column's count in st[2]; the writing pass, given the
-// scanned counts, the total number of tiles in st[1].
+// Counting pass (WRITE false): the column's tiles per cost class, into
+// table[c * ncol + col] (class-major, so that the exclusive scan of the table
+// gives every (class, column) its first rank in the stable heavy-first
+// order); the last column also zeroes the sentinel table[TK_CLASSES * ncol],
+// which the scan turns into the number of tiles.  Writing pass: each tile at
+// its final position (xcd_position), and the number of tiles in st[1].
 template <bool WRITE>
-__global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *__restrict__ counts,
-                                                int4 *__restrict__ tiles, int32_t *__restrict__ tkey,
-                                                int32_t *__restrict__ st)
+__global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *__restrict__ table,
+                                                int4 *__restrict__ tiles, int64_t cap, int32_t *__restrict__ st)
 {
     extern __shared__ int tw_lds[];
     const int n2 = g.n[2];
     const int zst = n2 < TW_ZST ? n2 : TW_ZST;
     int *snt = tw_lds, *ssl = tw_lds + zst, *sbs = tw_lds + 2 * zst;
+    int *run = tw_lds + 3 * zst;        // tiles of each class so far in this column
+    int *cbase = run + TK_CLASSES;      // rank of this column's first tile within each class
+    int *cofs = cbase + TK_CLASSES;     // first position of each class
+    int *clen = cofs + TK_CLASSES;      // tiles in each class
+    const int64_t ncol = (int64_t)g.n[0] * g.n[1];
     const int col = col0 + (int)blockIdx.x;
     const int lane = threadIdx.x;
     const int b0 = col / g.n[1], b1 = col % g.n[1];
@@ -510,14 +550,27 @@ __global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *_
         for (int k = 0; k < 9; ++k) sc += box_count(g, ccol[k], z);
         ssl[z] = sc;
     }
+    if (lane < TK_CLASSES) {
+        run[lane] = 0;
+        if (WRITE) {
+            const int64_t o = table[(int64_t)lane * ncol];
+            cbase[lane] = (int)(table[(int64_t)lane * ncol + col] - o);
+            cofs[lane] = (int)o;
+            clen[lane] = (int)(table[(int64_t)(lane + 1) * ncol] - o);
+        }
+    }
     __syncthreads();
+    // One wavefront per workgroup: from here on, the LDS counters are read by
+    // all lanes and updated by lane 0 in program order (wave_fence).
+    // final position of the next tile of class c (uniform c)
+    auto place = [&](int c, int ahead) -> int64_t {
+        return xcd_position(cofs[c], clen[c], (int64_t)cbase[c] + run[c] + ahead);
+    };
     // The walk, with the whole wavefront on every step (z stays uniform).  A
     // tile starting at z may end at z + l for the l whose extent, targets and
     // staged sources all fit; each of these only grows with l, so the lanes
     // that fit form a prefix and one ballot gives the end.
     const ColView cv{&g, ccol, snt, ssl, sbs, col};
-    int cnt = 0;
-    const int out = WRITE ? counts[col] : 0;
     int z = 0;
     while (z < n2) {
         {  // next box with targets
@@ -533,14 +586,26 @@ __global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *_
         const int q1 = cv.sl(z - 1) + cv.sl(z) + cv.sl(z + 1);
         const int first = cv.first(z);
         if (nt > TILE_T || q1 > TILE_CAP) {
+            // dense: nd tiles of TILE_T targets, the last one of the rest;
+            // all but possibly the last share one class
             const int nd = (nt + TILE_T - 1) / TILE_T;
-            if (WRITE)
+            const int cf = tile_class((int64_t)TILE_T * q1);
+            const int cl = tile_class((int64_t)(nt - (nd - 1) * TILE_T) * q1);
+            const int nf = cl == cf ? nd : nd - 1;  // tiles of class cf
+            if (WRITE) {
                 for (int c = lane; c < nd; c += WAVE) {
-                    const int m = nt - c * TILE_T < TILE_T ? nt - c * TILE_T : TILE_T;
-                    tiles[out + cnt + c] = make_int4(col, z, -(z + 1), first + c * TILE_T);
-                    tkey[out + cnt + c] = cost_key((int64_t)m * q1);
+                    const bool lastc = c == nd - 1 && cl != cf;
+                    const int64_t pos = lastc ? place(cl, 0) : place(cf, c);
+                    if (pos < cap)
+                        tiles[pos] = make_int4(col, z, -(z + 1), first + c * TILE_T);
                 }
-            cnt += nd;
+            }
+            wave_fence();
+            if (lane == 0) {
+                run[cf] += nf;
+                if (cl != cf) run[cl] += 1;
+            }
+            wave_fence();
             ++z;
             continue;
         }
@@ -560,63 +625,26 @@ __global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *_
         Q += cv.sl(z - 1) + cv.sl(z);
         const int len = __popcll(__ballot(inr && T <= TILE_T && Q <= TILE_CAP));
         const int z1 = z + len - 1;
-        if (WRITE) {
-            // cost: sum over the tile's boxes of targets x the three slabs
-            long long c = lane < len ? (long long)ntl * (cv.sl(ze - 1) + cv.sl(ze) + cv.sl(ze + 1)) : 0;
-            for (int off = WAVE / 2; off > 0; off >>= 1) c += __shfl_xor(c, off);
-            if (lane == 0) {
-                tiles[out + cnt] = make_int4(col, z, z1, first);
-                tkey[out + cnt] = cost_key((int64_t)c);
-            }
+        // cost: sum over the tile's boxes of targets x the three slabs
+        long long cost = lane < len ? (long long)ntl * (cv.sl(ze - 1) + cv.sl(ze) + cv.sl(ze + 1)) : 0;
+        for (int off = WAVE / 2; off > 0; off >>= 1) cost += __shfl_xor(cost, off);
+        const int c = tile_class((int64_t)cost);
+        if (WRITE && lane == 0) {
+            const int64_t pos = place(c, 0);
+            if (pos < cap) tiles[pos] = make_int4(col, z, z1, first);
         }
-        ++cnt;
+        wave_fence();
+        if (lane == 0) run[c] += 1;
+        wave_fence();
         z = z1 + 1;
     }
-    if (lane == 0 && !WRITE) counts[col] = cnt;
-    if (lane == 0 && col == g.n[0] * g.n[1] - 1) {
-        if (WRITE)
-            st[1] = out + cnt;
-        else
-            st[2] = cnt;
+    if (!WRITE) {
+        if (lane < TK_CLASSES) table[(int64_t)lane * ncol + col] = run[lane];
+        if (lane == 0 && col == ncol - 1) table[(int64_t)TK_CLASSES * ncol] = 0;
+    } else if (lane == 0 && col == ncol - 1) {
+        st[1] = table[(int64_t)TK_CLASSES * ncol];
     }
 }
-
-// Final tile order.  Tiles are sorted heavy-first by cost bucket (skey,
-// stable, so within a bucket they keep the column-by-column walk order), and
-// workgroup i of the pair kernels runs on XCD i mod 8.  Within each bucket
-// [o, o + B) the positions k with k mod 8 = q (one XCD) take the q-th
-// contiguous run of the bucket's tiles: every XCD works on a spatially
-// compact share of every bucket, so tiles that stage the same neighbour
-// columns meet in one L2, and the heavy buckets stay spread over all XCDs.
-__device__ inline int64_t bound_of(const int32_t *__restrict__ a, int64_t n, int32_t v, bool upper)
-{
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (upper ? a[mid] <= v : a[mid] < v)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-__global__ void k_gather_tiles(const int4 *__restrict__ tin, const int32_t *__restrict__ order,
-                               const int32_t *__restrict__ skey, const int32_t *__restrict__ nptr, int64_t cap,
-                               int4 *__restrict__ tout)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = count_of(0, nptr, cap);
-    if (i >= n) return;
-    const int32_t key = skey[i];
-    const int64_t o = bound_of(skey, n, key, false), B = bound_of(skey, n, key, true) - o;
-    const int64_t k = i - o;
-    const int q = (int)(k & (XCDS - 1));
-    int64_t start = 0;  // tiles of the groups before q
-    for (int qq = 0; qq < q; ++qq) start += qq < B ? (B - qq + XCDS - 1) / XCDS : 0;
-    tout[i] = tin[order[o + start + k / XCDS]];
-}
-
 
 }  // namespace dmk
 
@@ -654,10 +682,10 @@ Layout layout_for(const dmk_grid *g, int64_t N)
     const int64_t ncol = (int64_t)g->n[0] * g->n[1];
     const int64_t nblk = (N + RS_TILE - 1) / RS_TILE;
     l.max_tiles = max_tiles_for(N, nbox);
-    const int64_t tblk = (l.max_tiles + RS_TILE - 1) / RS_TILE;
-    const int64_t nh = (int64_t)RS_BINS * (nblk > 0 ? nblk : 1), nth = (int64_t)RS_BINS * (tblk > 0 ? tblk : 1);
+    const int64_t nh = (int64_t)RS_BINS * (nblk > 0 ? nblk : 1);
     const int64_t phase1 = 2 * N + nh + scan_part_ints(nh) + 64;
-    const int64_t phase2 = (ncol + 64) + 7 * l.max_tiles + nth + scan_part_ints(nth > ncol ? nth : ncol) + 64;
+    const int64_t ntab = (int64_t)TK_CLASSES * ncol;  // tile count table, then its scan's partials
+    const int64_t phase2 = ((ntab + 1 + 63) & ~(int64_t)63) + scan_part_ints(ntab + 1) + 64;
     l.tmp_ints = phase1 > phase2 ? phase1 : phase2;
     size_t off = 0;
     l.key = off;
@@ -772,12 +800,11 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
             int32_t *kout = to_final ? bins->skey : altk;
             int32_t *vout = to_final ? bins->perm : altv;
             const int64_t nh = ((int64_t)1 << width) * nblk;
-            hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_THREADS), 0, stream, kin, N,
-                               (const int32_t *)nullptr, width * p, width, hist, (int)nblk);
+            hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_THREADS), 0, stream, kin, N, width * p,
+                               width, hist, (int)nblk);
             scan_excl(hist, nh, hist + nh, stream);
             hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(RS_THREADS), 0, stream, kin, vin, N,
-                               (const int32_t *)nullptr, width * p, width, (const int32_t *)hist, (int)nblk, kout,
-                               vout);
+                               width * p, width, (const int32_t *)hist, (int)nblk, kout, vout);
             kin = kout;
             vin = vout;
         }
@@ -794,43 +821,25 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     for (int i = 0; i < 3; ++i) tg.n[i] = grid->n[i];
     tg.D = grid->D;
     tg.bs = bins->box_start;
-    // tile scratch (the point sort is done with tmp by now)
-    int32_t *colcnt = bins->tmp;
-    int4 *tiles_u = (int4 *)(bins->tmp + ((ncol + 64 + 3) & ~(int64_t)3));
-    int32_t *tkey = (int32_t *)(tiles_u + bins->max_tiles);
-    int32_t *tkey2 = tkey + bins->max_tiles;
-    int32_t *torder = tkey2 + bins->max_tiles;
-    int32_t *thist = torder + bins->max_tiles;
+    // tile scratch (the point sort is done with tmp by now): the class x
+    // column count table with its sentinel, then the scan's partial sums
+    const int64_t ntab = (int64_t)TK_CLASSES * ncol;
+    int32_t *table = bins->tmp;
+    int32_t *tpart = bins->tmp + ((ntab + 1 + 63) & ~(int64_t)63);
     // one wavefront per column, in launches of fewer than 2^32 work-items;
-    // LDS: first target, target count and slab count of each staged box
+    // LDS: first target, target count and slab count of each staged box, and
+    // four ints per cost class
     constexpr int64_t TCB = 0xffffffffu / WAVE;
-    const size_t tw_lds = sizeof(int) * 3 * (size_t)std::min(grid->n[2], TW_ZST);
+    const size_t tw_lds = sizeof(int) * (3 * (size_t)std::min(grid->n[2], TW_ZST) + 4 * TK_CLASSES);
     for (int64_t c0 = 0; c0 < ncol; c0 += TCB)
         hipLaunchKernelGGL(k_tiles<false>, dim3((unsigned)std::min(TCB, ncol - c0)), dim3(WAVE), tw_lds, stream, tg,
-                           (int)c0, colcnt, tiles_u, tkey, bins->status);
-    // scan of the per-column counts (the last column's raw count is kept in
-    // status[2]), then the tiles and their total (status[1])
-    scan_excl(colcnt, ncol, thist + RS_BINS * ((bins->max_tiles + RS_TILE - 1) / RS_TILE), stream);
+                           (int)c0, table, (int4 *)bins->tiles, bins->max_tiles, bins->status);
+    // first rank of every (class, column) in the heavy-first order, and the
+    // number of tiles in the sentinel; then every tile at its place
+    scan_excl(table, ntab + 1, tpart, stream);
     for (int64_t c0 = 0; c0 < ncol; c0 += TCB)
         hipLaunchKernelGGL(k_tiles<true>, dim3((unsigned)std::min(TCB, ncol - c0)), dim3(WAVE), tw_lds, stream, tg,
-                           (int)c0, colcnt, tiles_u, tkey, bins->status);
-    // order the tiles heavy-first (stable within a cost bucket): one pass over
-    // the 6-bit cost key, sized for the most tiles there can be and reading
-    // the actual count from status[1], so that the host waits only once
-    {
-        const int64_t cap = bins->max_tiles;
-        const int64_t tb = (cap + RS_TILE - 1) / RS_TILE;
-        constexpr int TKB = 6;
-        const int64_t nh = ((int64_t)1 << TKB) * tb;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tb), dim3(RS_THREADS), 0, stream, tkey, cap,
-                           (const int32_t *)(bins->status + 1), 0, TKB, thist, (int)tb);
-        scan_excl(thist, nh, thist + nh, stream);
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tb), dim3(RS_THREADS), 0, stream, tkey,
-                           (const int32_t *)nullptr, cap, (const int32_t *)(bins->status + 1), 0, TKB,
-                           (const int32_t *)thist, (int)tb, tkey2, torder);
-        hipLaunchKernelGGL(k_gather_tiles, dim3(nblocks(cap, 256)), dim3(256), 0, stream, tiles_u, torder,
-                           (const int32_t *)tkey2, (const int32_t *)(bins->status + 1), cap, (int4 *)bins->tiles);
-    }
+                           (int)c0, table, (int4 *)bins->tiles, bins->max_tiles, bins->status);
     DMK_HIP_CHECK(hipGetLastError());
     int32_t st[4] = {0, 0, 0, 0};
     DMK_HIP_CHECK(hipMemcpyAsync(st, bins->status, sizeof(st), hipMemcpyDeviceToHost, stream));
