@@ -804,10 +804,11 @@ __global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, double sigma, c
 // three launches.  Each workgroup keeps its share in LDS and computes the
 // phase factors it needs itself (as the table entries above):
 //   k_far_c1, one (component, g0) slab:  T2[q][g0][n1][n2] = sum_g1 conj(E1)
-//             sum_g2 conj(E2) rho[q][g0][g1][g2];
+//             sum_g2 conj(E2) rho[q][g0][g1][g2]; further workgroups beside
+//             the slabs write the window's transform per octant mode (PH);
 //   k_far_c2, one (n1, n2) pencil: chi over g0 (scaled by 1/|Omega|), the
-//             window's transform of its octant modes, the mode weights, and
-//             back over n0: V1[j][g0][n1][n2];
+//             mode weights (the window's transform from PH), and back over
+//             n0: V1[j][g0][n1][n2];
 //   k_far_c3, one (component, g0) slab: u[j][g0][g1][g2] = Re sum_n2 E2
 //             sum_n1 E1 V1[j][g0][n1][n2].
 // Every sum takes the fused multiply-adds of k_mode, split over the lanes in a
@@ -862,8 +863,14 @@ __device__ inline void fill_phases(const FarGeom &g, int ax, double2 *e, int tid
     for (int t = tid; t < g.G[ax] * kk; t += FC_T) e[t] = far_phase(g, ax, t / kk, t % kk);
 }
 
-__global__ __launch_bounds__(FC_T) void k_far_c1(FarGeom g, const double *__restrict__ rho, double2 *__restrict__ T2)
+__global__ __launch_bounds__(FC_T) void k_far_c1(FarGeom g, const double *__restrict__ rho, double2 *__restrict__ T2,
+                                                 FarWin w, double2 *__restrict__ PH, unsigned nslab)
 {
+    if (blockIdx.x >= nslab) {  // the window's transform per octant mode, one per wavefront
+        const int64_t m = (int64_t)(blockIdx.x - nslab) * (FC_T / WAVE) + threadIdx.x / WAVE;
+        far_phihat_mode(g, w, PH, m, threadIdx.x & (WAVE - 1));
+        return;
+    }
     extern __shared__ double2 fc_lds[];
     const int G1 = g.G[1], G2 = g.G[2], W1 = g.W[1], W2 = g.W[2], K1 = g.K[1], K2 = g.K[2];
     double2 *e2 = fc_lds;
@@ -904,7 +911,7 @@ __global__ __launch_bounds__(FC_T) void k_far_c1(FarGeom g, const double *__rest
 }
 
 template <int KERN>
-__global__ __launch_bounds__(FC_T) void k_far_c2(FarGeom g, FarWin w, double sigma, double invV,
+__global__ __launch_bounds__(FC_T) void k_far_c2(FarGeom g, double sigma, double invV, const double2 *__restrict__ PH,
                                                  const double2 *__restrict__ T2, double2 *__restrict__ V1)
 {
     constexpr int MI = KERN == 0 ? 1 : (KERN == 2 ? 9 : 3);
@@ -918,19 +925,13 @@ __global__ __launch_bounds__(FC_T) void k_far_c2(FarGeom g, FarWin w, double sig
     double2 *wo = ph + (K0 + 1);       // [MO][W0]
     const int n1i = (int)blockIdx.x / W2, n2i = (int)blockIdx.x % W2;
     const int n1 = n1i - g.K[1], n2 = n2i - g.K[2];
-    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    const int tid = threadIdx.x;
     fill_phases(g, 0, e0, tid);
     for (int t = tid; t < MI * G0; t += FC_T) xp[t] = T2[((int64_t)t * W1 + n1i) * W2 + n2i];
-    // phihat and phihat' of the octant modes (|n0|, |n1|, |n2|), one wavefront each
-    for (int a0 = wv; a0 <= K0; a0 += FC_T / WAVE) {
+    // phihat and phihat' of the octant modes (|n0|, |n1|, |n2|), from k_far_c1
+    {
         const int a1 = n1 < 0 ? -n1 : n1, a2 = n2 < 0 ? -n2 : n2;
-        double p0 = 0.0, p1 = 0.0;
-        if (a0 != 0 || a1 != 0 || a2 != 0) {
-            const double k[3] = {2.0 * M_PI * a0 / g.L[0], 2.0 * M_PI * a1 / g.L[1], 2.0 * M_PI * a2 / g.L[2]};
-            const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-            win_hat(w, sqrt(k2) * w.sigma, lane, p0, p1);
-        }
-        if (lane == 0) ph[a0] = make_double2(p0, p1);
+        for (int a0 = tid; a0 <= K0; a0 += FC_T) ph[a0] = PH[((int64_t)a0 * (g.K[1] + 1) + a1) * (g.K[2] + 1) + a2];
     }
     __syncthreads();
     wg_sums(
@@ -1464,7 +1465,9 @@ inline FarCompact far_compact(const FarGeom &g, int64_t Q, int64_t J)
     const size_t l2 = z * (G0 * k0 + Q * G0 + Q * W0 + k0 + J * W0);
     const size_t l3 = z * (G1 * k1 + G2 * k2 + W1 * W2 + G1 * W2);
     if (l1 > FC_LDS || l2 > FC_LDS || l3 > FC_LDS) return c;
-    if (!grid_fits(Q * (int64_t)G0, FC_T) || !grid_fits((int64_t)W1 * W2, FC_T) || !grid_fits(J * (int64_t)G0, FC_T))
+    const int64_t nom = (int64_t)k0 * k1 * k2;  // octant modes, one wavefront each beside the slabs
+    if (!grid_fits(Q * (int64_t)G0 + nblk(nom, FC_T / WAVE), FC_T) || !grid_fits((int64_t)W1 * W2, FC_T) ||
+        !grid_fits(J * (int64_t)G0, FC_T))
         return c;
     c.l1 = l1;
     c.l2 = l2;
@@ -1599,13 +1602,17 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
     // small grids: three launches, each workgroup holding its share in LDS
     const FarCompact fc = far_compact(g, Q, J);
     if (fc.l1) {
-        hipLaunchKernelGGL(k_far_c1, dim3((unsigned)(Q * g.G[0])), dim3(FC_T), fc.l1, stream, g, rho_grid, T2);
+        // the slabs, and beside them the octant table of the window's transform
+        const unsigned nslab = (unsigned)(Q * g.G[0]);
+        const int64_t nom = (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1);
+        hipLaunchKernelGGL(k_far_c1, dim3(nslab + (unsigned)nblk(nom, FC_T / WAVE)), dim3(FC_T), fc.l1, stream, g,
+                           rho_grid, T2, w, PH, nslab);
         const dim3 gp((unsigned)((int64_t)W1 * W2));
         switch (kernel) {
-        case 0: hipLaunchKernelGGL(k_far_c2<0>, gp, dim3(FC_T), fc.l2, stream, g, w, sigma0, invV, T2, V1); break;
-        case 1: hipLaunchKernelGGL(k_far_c2<1>, gp, dim3(FC_T), fc.l2, stream, g, w, sigma0, invV, T2, V1); break;
-        case 2: hipLaunchKernelGGL(k_far_c2<2>, gp, dim3(FC_T), fc.l2, stream, g, w, sigma0, invV, T2, V1); break;
-        default: hipLaunchKernelGGL(k_far_c2<3>, gp, dim3(FC_T), fc.l2, stream, g, w, sigma0, invV, T2, V1); break;
+        case 0: hipLaunchKernelGGL(k_far_c2<0>, gp, dim3(FC_T), fc.l2, stream, g, sigma0, invV, PH, T2, V1); break;
+        case 1: hipLaunchKernelGGL(k_far_c2<1>, gp, dim3(FC_T), fc.l2, stream, g, sigma0, invV, PH, T2, V1); break;
+        case 2: hipLaunchKernelGGL(k_far_c2<2>, gp, dim3(FC_T), fc.l2, stream, g, sigma0, invV, PH, T2, V1); break;
+        default: hipLaunchKernelGGL(k_far_c2<3>, gp, dim3(FC_T), fc.l2, stream, g, sigma0, invV, PH, T2, V1); break;
         }
         hipLaunchKernelGGL(k_far_c3, dim3((unsigned)(J * g.G[0])), dim3(FC_T), fc.l3, stream, g, V1, u_grid);
         DMK_HIP_CHECK(hipGetLastError());
