@@ -802,7 +802,9 @@ __global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, double sigma, c
 // ---------------------------------------------------------------------------
 // Small grids (no axis factored over the cube index): the whole far field in
 // three launches.  Each workgroup keeps its share in LDS and computes the
-// phase factors it needs itself (as the table entries above):
+// phase factors it needs itself (as the table entries above); the slab
+// kernels run 1024-thread workgroups (few workgroups, so each thread's serial
+// share of a sum is what costs), the pencil kernel 256:
 //   k_far_c1, one (component, g0) slab:  T2[q][g0][n1][n2] = sum_g1 conj(E1)
 //             sum_g2 conj(E2) rho[q][g0][g1][g2]; further workgroups beside
 //             the slabs write the window's transform per octant mode (PH);
@@ -813,21 +815,24 @@ __global__ __launch_bounds__(FW_T) void k_far_weights(FarGeom g, double sigma, c
 //             sum_n1 E1 V1[j][g0][n1][n2].
 // Every sum takes the fused multiply-adds of k_mode, split over the lanes in a
 // fixed order (wg_sums).
-constexpr int FC_T = 256;
+constexpr int FC_TS = 1024;  // threads of the slab kernels (k_far_c1, k_far_c3)
+constexpr int FC_TP = 256;   // threads of the pencil kernel (k_far_c2)
 constexpr size_t FC_LDS = 64 * 1024;
+constexpr int FC_PRE = 8;   // slab values per thread loaded ahead (doubles)
+constexpr int FC_PRE2 = 4;  // pencil / slab values per thread loaded ahead (complex)
 
 // Sums of a workgroup: out o (o < nout) = sum over i < nin of the terms that
 // acc(o, i, re, im) adds.  Each output takes L lanes of one wavefront (L a
-// power of two, as many as the FC_T threads allow, at most 64); lane r of the
+// power of two, as many as the NT threads allow, at most 64); lane r of the
 // group adds the terms i = r, r + L, ... in order, and the L partial sums are
 // combined by xor shuffles, so the order of every sum is fixed.  st(o, re,
 // im) stores the result (called by the group's first lane).
-template <class Acc, class Store>
+template <int NT, class Acc, class Store>
 __device__ inline void wg_sums(int nout, int nin, int tid, Acc acc, Store st)
 {
     int L = 1;
-    while (L < WAVE && 2 * L * nout <= FC_T && 2 * L <= nin) L *= 2;
-    const int per = FC_T / L;  // outputs per round
+    while (L < WAVE && 2 * L * nout <= NT && 2 * L <= nin) L *= 2;
+    const int per = NT / L;  // outputs per round
     for (int o0 = 0; o0 < nout; o0 += per) {
         const int o = o0 + tid / L, r = tid & (L - 1);
         double re = 0.0, im = 0.0;
@@ -857,17 +862,18 @@ __device__ inline double2 far_phase(const FarGeom &g, int ax, int gi, int n)
 // the imaginary part of E_i[.][n] (n of either sign) from the row of n >= 0
 __device__ inline double phase_im(const double2 e, int n) { return n < 0 ? -e.y : e.y; }
 
+template <int NT>
 __device__ inline void fill_phases(const FarGeom &g, int ax, double2 *e, int tid)
 {
     const int kk = g.K[ax] + 1;
-    for (int t = tid; t < g.G[ax] * kk; t += FC_T) e[t] = far_phase(g, ax, t / kk, t % kk);
+    for (int t = tid; t < g.G[ax] * kk; t += NT) e[t] = far_phase(g, ax, t / kk, t % kk);
 }
 
-__global__ __launch_bounds__(FC_T) void k_far_c1(FarGeom g, const double *__restrict__ rho, double2 *__restrict__ T2,
+__global__ __launch_bounds__(FC_TS) void k_far_c1(FarGeom g, const double *__restrict__ rho, double2 *__restrict__ T2,
                                                  FarWin w, double2 *__restrict__ PH, unsigned nslab)
 {
     if (blockIdx.x >= nslab) {  // the window's transform per octant mode, one per wavefront
-        const int64_t m = (int64_t)(blockIdx.x - nslab) * (FC_T / WAVE) + threadIdx.x / WAVE;
+        const int64_t m = (int64_t)(blockIdx.x - nslab) * (FC_TS / WAVE) + threadIdx.x / WAVE;
         far_phihat_mode(g, w, PH, m, threadIdx.x & (WAVE - 1));
         return;
     }
@@ -879,12 +885,25 @@ __global__ __launch_bounds__(FC_T) void k_far_c1(FarGeom g, const double *__rest
     double *x = (double *)(t1 + G1 * W2);
     const int64_t a = blockIdx.x;  // q * G0 + g0
     const int tid = threadIdx.x;
-    fill_phases(g, 2, e2, tid);
-    fill_phases(g, 1, e1, tid);
+    // the slab's first FC_PRE values per thread are loaded before the phase
+    // factors are computed, so that the two overlap
     const double *xs = rho + a * G1 * G2;
-    for (int t = tid; t < G1 * G2; t += FC_T) x[t] = xs[t];
+    double xr[FC_PRE];
+#pragma unroll
+    for (int u = 0; u < FC_PRE; ++u) {
+        const int t = tid + u * FC_TS;
+        xr[u] = t < G1 * G2 ? xs[t] : 0.0;
+    }
+    fill_phases<FC_TS>(g, 2, e2, tid);
+    fill_phases<FC_TS>(g, 1, e1, tid);
+#pragma unroll
+    for (int u = 0; u < FC_PRE; ++u) {
+        const int t = tid + u * FC_TS;
+        if (t < G1 * G2) x[t] = xr[u];
+    }
+    for (int t = tid + FC_PRE * FC_TS; t < G1 * G2; t += FC_TS) x[t] = xs[t];
     __syncthreads();
-    wg_sums(
+    wg_sums<FC_TS>(
         G1 * W2, G2, tid,
         [&](int t, int i, double &re, double &im) {
             const int g1 = t / W2, n = t % W2 - K2;
@@ -897,7 +916,7 @@ __global__ __launch_bounds__(FC_T) void k_far_c1(FarGeom g, const double *__rest
         [&](int t, double re, double im) { t1[t] = make_double2(re, im); });
     __syncthreads();
     double2 *out = T2 + a * W1 * W2;
-    wg_sums(
+    wg_sums<FC_TS>(
         W1 * W2, G1, tid,
         [&](int t, int i, double &re, double &im) {
             const int n = t / W2 - K1, c = t % W2;
@@ -911,7 +930,7 @@ __global__ __launch_bounds__(FC_T) void k_far_c1(FarGeom g, const double *__rest
 }
 
 template <int KERN>
-__global__ __launch_bounds__(FC_T) void k_far_c2(FarGeom g, double sigma, double invV, const double2 *__restrict__ PH,
+__global__ __launch_bounds__(FC_TP) void k_far_c2(FarGeom g, double sigma, double invV, const double2 *__restrict__ PH,
                                                  const double2 *__restrict__ T2, double2 *__restrict__ V1)
 {
     constexpr int MI = KERN == 0 ? 1 : (KERN == 2 ? 9 : 3);
@@ -926,15 +945,26 @@ __global__ __launch_bounds__(FC_T) void k_far_c2(FarGeom g, double sigma, double
     const int n1i = (int)blockIdx.x / W2, n2i = (int)blockIdx.x % W2;
     const int n1 = n1i - g.K[1], n2 = n2i - g.K[2];
     const int tid = threadIdx.x;
-    fill_phases(g, 0, e0, tid);
-    for (int t = tid; t < MI * G0; t += FC_T) xp[t] = T2[((int64_t)t * W1 + n1i) * W2 + n2i];
+    double2 xr[FC_PRE2];  // the pencil's first values, loaded before the phase factors
+#pragma unroll
+    for (int u = 0; u < FC_PRE2; ++u) {
+        const int t = tid + u * FC_TP;
+        xr[u] = t < MI * G0 ? T2[((int64_t)t * W1 + n1i) * W2 + n2i] : make_double2(0.0, 0.0);
+    }
+    fill_phases<FC_TP>(g, 0, e0, tid);
+#pragma unroll
+    for (int u = 0; u < FC_PRE2; ++u) {
+        const int t = tid + u * FC_TP;
+        if (t < MI * G0) xp[t] = xr[u];
+    }
+    for (int t = tid + FC_PRE2 * FC_TP; t < MI * G0; t += FC_TP) xp[t] = T2[((int64_t)t * W1 + n1i) * W2 + n2i];
     // phihat and phihat' of the octant modes (|n0|, |n1|, |n2|), from k_far_c1
     {
         const int a1 = n1 < 0 ? -n1 : n1, a2 = n2 < 0 ? -n2 : n2;
-        for (int a0 = tid; a0 <= K0; a0 += FC_T) ph[a0] = PH[((int64_t)a0 * (g.K[1] + 1) + a1) * (g.K[2] + 1) + a2];
+        for (int a0 = tid; a0 <= K0; a0 += FC_TP) ph[a0] = PH[((int64_t)a0 * (g.K[1] + 1) + a1) * (g.K[2] + 1) + a2];
     }
     __syncthreads();
-    wg_sums(
+    wg_sums<FC_TP>(
         MI * W0, G0, tid,
         [&](int t, int i, double &re, double &im) {
             const int q = t / W0, n = t % W0 - K0;
@@ -947,7 +977,7 @@ __global__ __launch_bounds__(FC_T) void k_far_c2(FarGeom g, double sigma, double
         [&](int t, double re, double im) { ch[t] = make_double2(invV * re, invV * im); });
     __syncthreads();
     // mode weights (as k_far_weights)
-    for (int i = tid; i < W0; i += FC_T) {
+    for (int i = tid; i < W0; i += FC_TP) {
         const int n0 = i - K0;
         double2 out[MO];
         for (int j = 0; j < MO; ++j) out[j] = make_double2(0.0, 0.0);
@@ -963,7 +993,7 @@ __global__ __launch_bounds__(FC_T) void k_far_c2(FarGeom g, double sigma, double
         for (int j = 0; j < MO; ++j) wo[j * W0 + i] = out[j];
     }
     __syncthreads();
-    wg_sums(
+    wg_sums<FC_TP>(
         MO * G0, W0, tid,
         [&](int t, int i, double &re, double &im) {
             const int j = t / G0, g0 = t % G0, n = i - K0;
@@ -976,7 +1006,7 @@ __global__ __launch_bounds__(FC_T) void k_far_c2(FarGeom g, double sigma, double
         [&](int t, double re, double im) { V1[((int64_t)t * W1 + n1i) * W2 + n2i] = make_double2(re, im); });
 }
 
-__global__ __launch_bounds__(FC_T) void k_far_c3(FarGeom g, const double2 *__restrict__ V1, double *__restrict__ u)
+__global__ __launch_bounds__(FC_TS) void k_far_c3(FarGeom g, const double2 *__restrict__ V1, double *__restrict__ u)
 {
     extern __shared__ double2 fc_lds[];
     const int G1 = g.G[1], G2 = g.G[2], W1 = g.W[1], W2 = g.W[2], K1 = g.K[1], K2 = g.K[2];
@@ -986,12 +1016,23 @@ __global__ __launch_bounds__(FC_T) void k_far_c3(FarGeom g, const double2 *__res
     double2 *v2 = v1 + W1 * W2;        // [G1][W2]
     const int64_t a = blockIdx.x;      // j * G0 + g0
     const int tid = threadIdx.x;
-    fill_phases(g, 1, e1, tid);
-    fill_phases(g, 2, e2, tid);
     const double2 *vs = V1 + a * W1 * W2;
-    for (int t = tid; t < W1 * W2; t += FC_T) v1[t] = vs[t];
+    double2 xr[FC_PRE2];  // the slab's first values, loaded before the phase factors
+#pragma unroll
+    for (int u = 0; u < FC_PRE2; ++u) {
+        const int t = tid + u * FC_TS;
+        xr[u] = t < W1 * W2 ? vs[t] : make_double2(0.0, 0.0);
+    }
+    fill_phases<FC_TS>(g, 1, e1, tid);
+    fill_phases<FC_TS>(g, 2, e2, tid);
+#pragma unroll
+    for (int u = 0; u < FC_PRE2; ++u) {
+        const int t = tid + u * FC_TS;
+        if (t < W1 * W2) v1[t] = xr[u];
+    }
+    for (int t = tid + FC_PRE2 * FC_TS; t < W1 * W2; t += FC_TS) v1[t] = vs[t];
     __syncthreads();
-    wg_sums(
+    wg_sums<FC_TS>(
         G1 * W2, W1, tid,
         [&](int t, int i, double &re, double &im) {
             const int g1 = t / W2, c = t % W2, n = i - K1;
@@ -1004,7 +1045,7 @@ __global__ __launch_bounds__(FC_T) void k_far_c3(FarGeom g, const double2 *__res
         [&](int t, double re, double im) { v2[t] = make_double2(re, im); });
     __syncthreads();
     double *out = u + a * G1 * G2;
-    wg_sums(
+    wg_sums<FC_TS>(
         G1 * G2, W2, tid,
         [&](int t, int i, double &re, double &im) {
             const int g1 = t / G2, g2 = t % G2, n = i - K2;
@@ -1466,8 +1507,8 @@ inline FarCompact far_compact(const FarGeom &g, int64_t Q, int64_t J)
     const size_t l3 = z * (G1 * k1 + G2 * k2 + W1 * W2 + G1 * W2);
     if (l1 > FC_LDS || l2 > FC_LDS || l3 > FC_LDS) return c;
     const int64_t nom = (int64_t)k0 * k1 * k2;  // octant modes, one wavefront each beside the slabs
-    if (!grid_fits(Q * (int64_t)G0 + nblk(nom, FC_T / WAVE), FC_T) || !grid_fits((int64_t)W1 * W2, FC_T) ||
-        !grid_fits(J * (int64_t)G0, FC_T))
+    if (!grid_fits(Q * (int64_t)G0 + nblk(nom, FC_TS / WAVE), FC_TS) || !grid_fits((int64_t)W1 * W2, FC_TP) ||
+        !grid_fits(J * (int64_t)G0, FC_TS))
         return c;
     c.l1 = l1;
     c.l2 = l2;
@@ -1605,16 +1646,16 @@ extern "C" int dmk_far3p_eval(const dmk_far_grid *fg, int kernel, double sigma0,
         // the slabs, and beside them the octant table of the window's transform
         const unsigned nslab = (unsigned)(Q * g.G[0]);
         const int64_t nom = (int64_t)(g.K[0] + 1) * (g.K[1] + 1) * (g.K[2] + 1);
-        hipLaunchKernelGGL(k_far_c1, dim3(nslab + (unsigned)nblk(nom, FC_T / WAVE)), dim3(FC_T), fc.l1, stream, g,
+        hipLaunchKernelGGL(k_far_c1, dim3(nslab + (unsigned)nblk(nom, FC_TS / WAVE)), dim3(FC_TS), fc.l1, stream, g,
                            rho_grid, T2, w, PH, nslab);
         const dim3 gp((unsigned)((int64_t)W1 * W2));
         switch (kernel) {
-        case 0: hipLaunchKernelGGL(k_far_c2<0>, gp, dim3(FC_T), fc.l2, stream, g, sigma0, invV, PH, T2, V1); break;
-        case 1: hipLaunchKernelGGL(k_far_c2<1>, gp, dim3(FC_T), fc.l2, stream, g, sigma0, invV, PH, T2, V1); break;
-        case 2: hipLaunchKernelGGL(k_far_c2<2>, gp, dim3(FC_T), fc.l2, stream, g, sigma0, invV, PH, T2, V1); break;
-        default: hipLaunchKernelGGL(k_far_c2<3>, gp, dim3(FC_T), fc.l2, stream, g, sigma0, invV, PH, T2, V1); break;
+        case 0: hipLaunchKernelGGL(k_far_c2<0>, gp, dim3(FC_TP), fc.l2, stream, g, sigma0, invV, PH, T2, V1); break;
+        case 1: hipLaunchKernelGGL(k_far_c2<1>, gp, dim3(FC_TP), fc.l2, stream, g, sigma0, invV, PH, T2, V1); break;
+        case 2: hipLaunchKernelGGL(k_far_c2<2>, gp, dim3(FC_TP), fc.l2, stream, g, sigma0, invV, PH, T2, V1); break;
+        default: hipLaunchKernelGGL(k_far_c2<3>, gp, dim3(FC_TP), fc.l2, stream, g, sigma0, invV, PH, T2, V1); break;
         }
-        hipLaunchKernelGGL(k_far_c3, dim3((unsigned)(J * g.G[0])), dim3(FC_T), fc.l3, stream, g, V1, u_grid);
+        hipLaunchKernelGGL(k_far_c3, dim3((unsigned)(J * g.G[0])), dim3(FC_TS), fc.l3, stream, g, V1, u_grid);
         DMK_HIP_CHECK(hipGetLastError());
         return DMK_OK;
     }
