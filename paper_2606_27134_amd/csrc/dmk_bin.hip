@@ -222,15 +222,18 @@ void scan_excl(int32_t *a, int64_t n, int32_t *part, hipStream_t s)
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BT), 0, s, a, n, (const int32_t *)part);
 }
 
-// Stable scatter of one pass: each block ranks its elements within their
+// Stable scatter of one pass.  Each block ranks its elements within their
 // bucket (wavefront match over the digit bits, then the wavefronts in order,
-// then the rounds in order) and writes them at the scanned block offsets.
-// Every thread loads its RS_ITEMS keys and values before the first round.
-// wcnt[w][d] holds wavefront w's count of digit d in the current round and is
-// zero otherwise: the lane that writes an entry clears it once the round's
-// offsets are read.  base[d] is the block's next output of digit d; the
-// last wavefront holding d in a round advances it by the round's count, and
-// the next round reads it after its first barrier.
+// then the rounds in order), places them in bucket order in LDS, and writes
+// them out by consecutive threads, so that the elements of one bucket (about
+// RS_TILE / RS_BINS of them) leave as one contiguous run instead of one
+// store per element.  Every thread loads its RS_ITEMS keys and values before
+// the first round.  wcnt[w][d] holds wavefront w's count of digit d in the
+// current round and is zero otherwise: the lane that writes an entry clears
+// it once the round's ranks are read.  run[d] counts the block's elements of
+// digit d so far (the last wavefront holding d in a round advances it); its
+// exclusive scan over the digits then gives each digit's first place in LDS.
+static_assert(RS_BINS == 2 * RS_THREADS, "two digits per thread in the local scan");
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__restrict__ kin,
                                                            const int32_t *__restrict__ vin, int64_t N,
                                                            int shift, int nbits,
@@ -238,27 +241,33 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__rest
                                                            int32_t *__restrict__ kout, int32_t *__restrict__ vout)
 {
     constexpr int NWV = RS_THREADS / WAVE;
-    __shared__ int base[RS_BINS];
+    __shared__ int base[RS_BINS];  // the block's first output of each digit
+    __shared__ int run[RS_BINS];
     __shared__ int wcnt[NWV][RS_BINS];
+    __shared__ int wtot[NWV];
+    __shared__ int sk[RS_TILE], sv[RS_TILE];
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int w = tid / WAVE;
     const int nb = 1 << nbits, mask = nb - 1;
     const int64_t b0 = (int64_t)blockIdx.x * RS_TILE;
-    int kk[RS_ITEMS], vv[RS_ITEMS];
+    int kk[RS_ITEMS], vv[RS_ITEMS], lr[RS_ITEMS];
 #pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
         const int64_t i = b0 + r * RS_THREADS + tid;
         kk[r] = i < N ? kin[i] : 0;
         vv[r] = i < N ? (vin ? vin[i] : (int)i) : 0;
+        lr[r] = 0;
     }
     for (int q = 0; q < RS_BPT; ++q) {
         const int d = q * RS_THREADS + tid;
         base[d] = d < nb ? hist[(int64_t)d * nblk + blockIdx.x] : 0;
+        run[d] = 0;
         for (int u = 0; u < NWV; ++u) wcnt[u][d] = 0;
     }
-    __syncthreads();
+    lds_barrier();
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    // ranks within the block
 #pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
         const bool valid = b0 + r * RS_THREADS + tid < N;
@@ -275,24 +284,57 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__rest
         const int cnt = __popcll(m);
         if (last) wcnt[w][d] = cnt;
         lds_barrier();
-        int nbase = -1;  // new base of d, set by the last wavefront holding d
+        int nrun = -1;  // new count of d, set by the last wavefront holding d
         if (valid) {
-            int off = base[d];
+            int off = run[d];
             for (int q = 0; q < w; ++q) off += wcnt[q][d];
-            const int64_t o = (int64_t)off + rank;
-            kout[o] = kk[r];
-            vout[o] = vv[r];
+            lr[r] = off + rank;
             if (last) {
                 bool final = true;
                 for (int q = w + 1; q < NWV; ++q) final = final && wcnt[q][d] == 0;
-                if (final) nbase = off + cnt;
+                if (final) nrun = off + cnt;
             }
         }
         lds_barrier();
         if (last) {
-            if (nbase >= 0) base[d] = nbase;
+            if (nrun >= 0) run[d] = nrun;
             wcnt[w][d] = 0;
         }
+    }
+    lds_barrier();
+    // run[d] becomes the first LDS place of digit d (thread t owns 2t, 2t+1)
+    {
+        const int c0 = run[2 * tid], c1 = run[2 * tid + 1];
+        int x = c0 + c1;
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const int y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == WAVE - 1) wtot[w] = x;
+        lds_barrier();
+        int pre = 0;
+        for (int q = 0; q < w; ++q) pre += wtot[q];
+        const int ex = pre + x - (c0 + c1);
+        run[2 * tid] = ex;
+        run[2 * tid + 1] = ex + c0;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        if (b0 + r * RS_THREADS + tid < N) {
+            const int lp = run[(kk[r] >> shift) & mask] + lr[r];
+            sk[lp] = kk[r];
+            sv[lp] = vv[r];
+        }
+    }
+    lds_barrier();
+    const int nvalid = N - b0 < RS_TILE ? (int)(N - b0) : RS_TILE;
+    for (int q = tid; q < nvalid; q += RS_THREADS) {
+        const int k = sk[q];
+        const int d = (k >> shift) & mask;
+        const int64_t o = (int64_t)base[d] + (q - run[d]);
+        kout[o] = k;
+        vout[o] = sv[q];
     }
 }
 
