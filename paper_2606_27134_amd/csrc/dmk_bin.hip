@@ -19,6 +19,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "dmk_internal.h"
 
@@ -555,6 +556,49 @@ struct ColView {
     }
 };
 
+// Cross-lane sums of the tile walk with DPP moves (row shifts by 1, 2, 4, 8,
+// then the row totals carried by row broadcasts from lanes 15 and 31), which
+// stay in the VALU instead of going through the LDS crossbar as shuffles do.
+// With bound_ctrl a lane whose source lies outside its row reads 0.
+constexpr int TW_DPP_ROW_SHR = 0x110, TW_DPP_BCAST15 = 0x142, TW_DPP_BCAST31 = 0x143;
+template <int CTRL, int RM>
+__device__ inline int tw_dpp(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, RM, 0xf, true);
+}
+// inclusive sum over lanes 0..lane
+__device__ inline int tw_incl_scan(int v)
+{
+    v += tw_dpp<TW_DPP_ROW_SHR + 1, 0xf>(v);
+    v += tw_dpp<TW_DPP_ROW_SHR + 2, 0xf>(v);
+    v += tw_dpp<TW_DPP_ROW_SHR + 4, 0xf>(v);
+    v += tw_dpp<TW_DPP_ROW_SHR + 8, 0xf>(v);
+    v += tw_dpp<TW_DPP_BCAST15, 0xa>(v);
+    v += tw_dpp<TW_DPP_BCAST31, 0xc>(v);
+    return v;
+}
+// sum over the 64 lanes of a non-negative integer below 2^53 held in a double
+// (every partial sum is exact), returned in every lane
+__device__ inline double tw_total(double v)
+{
+    auto step = [](double x, auto ctrl) {
+        constexpr int C = decltype(ctrl)::value;
+        constexpr int RM = C == TW_DPP_BCAST15 ? 0xa : (C == TW_DPP_BCAST31 ? 0xc : 0xf);
+        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), C, RM, 0xf, true);
+        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), C, RM, 0xf, true);
+        return x + __hiloint2double(hi, lo);
+    };
+    v = step(v, std::integral_constant<int, TW_DPP_ROW_SHR + 1>{});
+    v = step(v, std::integral_constant<int, TW_DPP_ROW_SHR + 2>{});
+    v = step(v, std::integral_constant<int, TW_DPP_ROW_SHR + 4>{});
+    v = step(v, std::integral_constant<int, TW_DPP_ROW_SHR + 8>{});
+    v = step(v, std::integral_constant<int, TW_DPP_BCAST15>{});
+    v = step(v, std::integral_constant<int, TW_DPP_BCAST31>{});
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), WAVE - 1);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), WAVE - 1);
+    return __hiloint2double(hi, lo);
+}
+
 // Counting pass (WRITE false): the column's tiles per cost class, into
 // table[c * ncol + col] (class-major, so that the exclusive scan of the table
 // gives every (class, column) its first rank in the stable heavy-first
@@ -656,20 +700,14 @@ __global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *_
         const int ze = z + lane;
         const bool inr = ze < n2 && lane < TILE_ZMAX;
         const int ntl = inr ? cv.nt(ze) : 0;
-        int T = ntl, Q = inr ? cv.sl(ze + 1) : 0;
-        for (int off = 1; off < WAVE; off <<= 1) {
-            const int t = __shfl_up(T, off), q = __shfl_up(Q, off);
-            if (lane >= off) {
-                T += t;
-                Q += q;
-            }
-        }
-        Q += cv.sl(z - 1) + cv.sl(z);
+        const int T = tw_incl_scan(ntl);
+        const int Q = tw_incl_scan(inr ? cv.sl(ze + 1) : 0) + cv.sl(z - 1) + cv.sl(z);
         const int len = __popcll(__ballot(inr && T <= TILE_T && Q <= TILE_CAP));
         const int z1 = z + len - 1;
-        // cost: sum over the tile's boxes of targets x the three slabs
-        long long cost = lane < len ? (long long)ntl * (cv.sl(ze - 1) + cv.sl(ze) + cv.sl(ze + 1)) : 0;
-        for (int off = WAVE / 2; off > 0; off >>= 1) cost += __shfl_xor(cost, off);
+        // cost: sum over the tile's boxes of targets x the three slabs (below
+        // 2^21: at most TILE_T targets, each with at most TILE_CAP sources)
+        const double cost =
+            tw_total(lane < len ? (double)ntl * (double)(cv.sl(ze - 1) + cv.sl(ze) + cv.sl(ze + 1)) : 0.0);
         const int c = tile_class((int64_t)cost);
         if (WRITE && lane == 0) {
             const int64_t pos = place(c, 0);

@@ -139,6 +139,23 @@ def test_binning_dense_and_empty():
     _check_tiles(b, (6, 6, 6), ref, 3)
 
 
+def test_binning_dense_short_last_tile():
+    # a box of 65 targets among sparse ones: two dense tiles of 64 and 1
+    # targets, whose costs (64 and 1 times the same neighbourhood) fall in
+    # different power-of-two cost classes, so the short tile is ranked in a
+    # class of its own
+    rng = np.random.default_rng(11)
+    x = np.concatenate([0.41 + 0.02 * rng.random((65, 3)), rng.random((400, 3))])
+    print("binning dense short last tile", flush=True)
+    ref = bin_spec(x, (1, 1, 1), 3, (8, 8, 8))
+    b = R.tree_bin((1, 1, 1), 3, (8, 8, 8), dev(x))
+    np.testing.assert_array_equal(host(b.perm()), ref["perm"])
+    np.testing.assert_array_equal(host(b.box_start()), ref["box_start"])
+    dense = [t for t in host(b.tiles()) if t[2] < 0]
+    assert len(dense) == 2
+    _check_tiles(b, (8, 8, 8), ref, 3)
+
+
 def test_binning_deterministic():
     x = _points(3, 20000, (1, 1, 1), 3, "uniform")
     b1 = R.tree_bin((1, 1, 1), 3, (16, 16, 16), dev(x))
