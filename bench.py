@@ -90,6 +90,7 @@ def kernel_hash():
     traffic applies only while they are unchanged)."""
     h = hashlib.sha256()
     for f in ("paper_2606_27134_amd/csrc/dmk_residual.hip", "paper_2606_27134_amd/csrc/dmk_internal.h",
+              "paper_2606_27134_amd/csrc/dmk_dpp.h",
               "paper_2606_27134_amd/csrc/erfcx_f32.h", "paper_2606_27134_amd/csrc/erfcx_f64.h", "include/dmk.h"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())

@@ -19,8 +19,8 @@
 #include <string.h>
 
 #include <algorithm>
-#include <type_traits>
 
+#include "dmk_dpp.h"
 #include "dmk_internal.h"
 
 #pragma clang fp contract(off)
@@ -556,44 +556,11 @@ struct ColView {
     }
 };
 
-// Cross-lane sums of the tile walk with DPP moves (row shifts by 1, 2, 4, 8,
-// then the row totals carried by row broadcasts from lanes 15 and 31), which
-// stay in the VALU instead of going through the LDS crossbar as shuffles do.
-// With bound_ctrl a lane whose source lies outside its row reads 0.
-constexpr int TW_DPP_ROW_SHR = 0x110, TW_DPP_BCAST15 = 0x142, TW_DPP_BCAST31 = 0x143;
-template <int CTRL, int RM>
-__device__ inline int tw_dpp(int x)
-{
-    return __builtin_amdgcn_update_dpp(0, x, CTRL, RM, 0xf, true);
-}
-// inclusive sum over lanes 0..lane
-__device__ inline int tw_incl_scan(int v)
-{
-    v += tw_dpp<TW_DPP_ROW_SHR + 1, 0xf>(v);
-    v += tw_dpp<TW_DPP_ROW_SHR + 2, 0xf>(v);
-    v += tw_dpp<TW_DPP_ROW_SHR + 4, 0xf>(v);
-    v += tw_dpp<TW_DPP_ROW_SHR + 8, 0xf>(v);
-    v += tw_dpp<TW_DPP_BCAST15, 0xa>(v);
-    v += tw_dpp<TW_DPP_BCAST31, 0xc>(v);
-    return v;
-}
-// sum over the 64 lanes of a non-negative integer below 2^53 held in a double
-// (every partial sum is exact), returned in every lane
+// lane total of the tile walk's cost: a DPP sum over the wavefront (lane 63
+// holds it), every partial sum an integer below 2^53 and so exact
 __device__ inline double tw_total(double v)
 {
-    auto step = [](double x, auto ctrl) {
-        constexpr int C = decltype(ctrl)::value;
-        constexpr int RM = C == TW_DPP_BCAST15 ? 0xa : (C == TW_DPP_BCAST31 ? 0xc : 0xf);
-        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), C, RM, 0xf, true);
-        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), C, RM, 0xf, true);
-        return x + __hiloint2double(hi, lo);
-    };
-    v = step(v, std::integral_constant<int, TW_DPP_ROW_SHR + 1>{});
-    v = step(v, std::integral_constant<int, TW_DPP_ROW_SHR + 2>{});
-    v = step(v, std::integral_constant<int, TW_DPP_ROW_SHR + 4>{});
-    v = step(v, std::integral_constant<int, TW_DPP_ROW_SHR + 8>{});
-    v = step(v, std::integral_constant<int, TW_DPP_BCAST15>{});
-    v = step(v, std::integral_constant<int, TW_DPP_BCAST31>{});
+    wave_sum<1, double>(&v);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), WAVE - 1);
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), WAVE - 1);
     return __hiloint2double(hi, lo);
@@ -700,8 +667,8 @@ __global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *_
         const int ze = z + lane;
         const bool inr = ze < n2 && lane < TILE_ZMAX;
         const int ntl = inr ? cv.nt(ze) : 0;
-        const int T = tw_incl_scan(ntl);
-        const int Q = tw_incl_scan(inr ? cv.sl(ze + 1) : 0) + cv.sl(z - 1) + cv.sl(z);
+        const int T = wave_incl_scan(ntl);
+        const int Q = wave_incl_scan(inr ? cv.sl(ze + 1) : 0) + cv.sl(z - 1) + cv.sl(z);
         const int len = __popcll(__ballot(inr && T <= TILE_T && Q <= TILE_CAP));
         const int z1 = z + len - 1;
         // cost: sum over the tile's boxes of targets x the three slabs (below
