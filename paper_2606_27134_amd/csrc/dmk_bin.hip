@@ -345,10 +345,9 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__rest
 // ys[ax][j] = wrapped x[perm[j]][ax]: each thread takes GY consecutive sorted
 // points and issues all of its loads before its stores
 constexpr int GY = 4;
-__global__ void k_gather_ys(const double *__restrict__ x, const int32_t *__restrict__ perm, int64_t N, BinGeom g,
-                            double *__restrict__ ys)
+__device__ inline void gather_ys_at(const double *__restrict__ x, const int32_t *__restrict__ perm, int64_t N,
+                                    const BinGeom &g, double *__restrict__ ys, int64_t j0)
 {
-    const int64_t j0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * GY;
     if (j0 >= N) return;
     int64_t i[GY];
     double v[GY][3];
@@ -573,8 +572,8 @@ __device__ inline double tw_total(double v)
 // which the scan turns into the number of tiles.  Writing pass: each tile at
 // its final position (xcd_position), and the number of tiles in st[1].
 template <bool WRITE>
-__global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *__restrict__ table,
-                                                int4 *__restrict__ tiles, int64_t cap, int32_t *__restrict__ st)
+__device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ table, int4 *__restrict__ tiles,
+                          int64_t cap, int32_t *__restrict__ st)
 {
     extern __shared__ int tw_lds[];
     const int n2 = g.n[2];
@@ -585,7 +584,6 @@ __global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *_
     int *cofs = cbase + TK_CLASSES;     // first position of each class
     int *clen = cofs + TK_CLASSES;      // tiles in each class
     const int64_t ncol = (int64_t)g.n[0] * g.n[1];
-    const int col = col0 + (int)blockIdx.x;
     const int lane = threadIdx.x;
     const int b0 = col / g.n[1], b1 = col % g.n[1];
     int ccol[9];
@@ -691,6 +689,29 @@ __global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *_
     } else if (lane == 0 && col == ncol - 1) {
         st[1] = table[(int64_t)TK_CLASSES * ncol];
     }
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *__restrict__ table,
+                                                int4 *__restrict__ tiles, int64_t cap, int32_t *__restrict__ st)
+{
+    tile_walk<WRITE>(g, col0 + (int)blockIdx.x, table, tiles, cap, st);
+}
+
+// The counting walk (blocks below ncol, one column each) and the sorted
+// coordinates (the blocks after them, GY points per thread) in one launch:
+// both wait mostly on memory and do not depend on each other, so their
+// wavefronts overlap on the device.
+__global__ __launch_bounds__(WAVE) void k_ys_count(TileGeom tg, unsigned ncol, int32_t *__restrict__ table,
+                                                   int64_t cap, int32_t *__restrict__ st,
+                                                   const double *__restrict__ x, const int32_t *__restrict__ perm,
+                                                   int64_t N, BinGeom g, double *__restrict__ ys)
+{
+    if (blockIdx.x < ncol) {
+        tile_walk<false>(tg, (int)blockIdx.x, table, nullptr, cap, st);
+        return;
+    }
+    gather_ys_at(x, perm, N, g, ys, ((int64_t)(blockIdx.x - ncol) * WAVE + threadIdx.x) * GY);
 }
 
 }  // namespace dmk
@@ -855,8 +876,6 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
             kin = kout;
             vin = vout;
         }
-        hipLaunchKernelGGL(k_gather_ys, dim3(nblocks((N + GY - 1) / GY, 256)), dim3(256), 0, stream, x, bins->perm,
-                           N, g, bins->ys);
     }
     if (N >= nbox)
         hipLaunchKernelGGL(k_box_start_fill, dim3(nblocks(N + 1, 256)), dim3(256), 0, stream, bins->skey, N, nbox,
@@ -878,9 +897,20 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     // four ints per cost class
     constexpr int64_t TCB = 0xffffffffu / WAVE;
     const size_t tw_lds = sizeof(int) * (3 * (size_t)std::min(grid->n[2], TW_ZST) + 4 * TK_CLASSES);
-    for (int64_t c0 = 0; c0 < ncol; c0 += TCB)
-        hipLaunchKernelGGL(k_tiles<false>, dim3((unsigned)std::min(TCB, ncol - c0)), dim3(WAVE), tw_lds, stream, tg,
-                           (int)c0, table, (int4 *)bins->tiles, bins->max_tiles, bins->status);
+    // the counting walk and the sorted coordinates in one launch (the walk's
+    // columns first, then blocks of WAVE threads taking GY points each)
+    const int64_t nyb = N > 0 ? ((N + GY - 1) / GY + WAVE - 1) / WAVE : 0;
+    if (ncol + nyb <= TCB) {
+        hipLaunchKernelGGL(k_ys_count, dim3((unsigned)(ncol + nyb)), dim3(WAVE), tw_lds, stream, tg, (unsigned)ncol,
+                           table, bins->max_tiles, bins->status, x, (const int32_t *)bins->perm, N, g, bins->ys);
+    } else {
+        for (int64_t c0 = 0; c0 < ncol; c0 += TCB)
+            hipLaunchKernelGGL(k_tiles<false>, dim3((unsigned)std::min(TCB, ncol - c0)), dim3(WAVE), tw_lds, stream,
+                               tg, (int)c0, table, (int4 *)bins->tiles, bins->max_tiles, bins->status);
+        if (nyb > 0)
+            hipLaunchKernelGGL(k_ys_count, dim3((unsigned)nyb), dim3(WAVE), 0, stream, tg, 0u, table,
+                               bins->max_tiles, bins->status, x, (const int32_t *)bins->perm, N, g, bins->ys);
+    }
     // first rank of every (class, column) in the heavy-first order, and the
     // number of tiles in the sentinel; then every tile at its place
     scan_excl(table, ntab + 1, tpart, stream);
