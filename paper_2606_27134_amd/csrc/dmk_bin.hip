@@ -206,6 +206,30 @@ __global__ __launch_bounds__(SCAN_BT) void k_scan_apply(int32_t *__restrict__ a,
     scan_chunk<SCAN_BT>(a, base, m, part[blockIdx.x], buf, wsum);
 }
 
+// block blk scans its values from the sum of the block sums before it
+// (part[b], b < blk, as k_scan_reduce wrote them): used up to SCAN_PRE_MAX
+// blocks, where adding them in every block costs less than a launch
+constexpr int64_t SCAN_PRE_MAX = 4096;
+__global__ __launch_bounds__(SCAN_BT) void k_scan_apply_sum(int32_t *__restrict__ a, int64_t n,
+                                                            const int32_t *__restrict__ part)
+{
+    __shared__ int buf[SCAN_B + SCAN_B / 32];
+    __shared__ int wsum[SCAN_BT / WAVE];
+    const int blk = (int)blockIdx.x;
+    int t = 0;
+    for (int b = threadIdx.x; b < blk; b += SCAN_BT) t += part[b];
+    for (int off = WAVE / 2; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if ((threadIdx.x & (WAVE - 1)) == 0) wsum[threadIdx.x / WAVE] = t;
+    lds_barrier();
+    int pre = 0;
+    for (int q = 0; q < SCAN_BT / WAVE; ++q) pre += wsum[q];
+    lds_barrier();  // wsum is scan_chunk's scratch next
+    const int64_t base = (int64_t)blk * SCAN_B;
+    const int64_t rem = n - base;
+    const int m = rem < SCAN_B ? (int)rem : SCAN_B;
+    scan_chunk<SCAN_BT>(a, base, m, pre, buf, wsum);
+}
+
 // scratch ints that scan_excl needs for n values
 inline int64_t scan_part_ints(int64_t n) { return (n + SCAN_B - 1) / SCAN_B + 1; }
 
@@ -219,6 +243,10 @@ void scan_excl(int32_t *a, int64_t n, int32_t *part, hipStream_t s)
     }
     const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BT), 0, s, (const int32_t *)a, n, part);
+    if (nb <= SCAN_PRE_MAX) {
+        hipLaunchKernelGGL(k_scan_apply_sum, dim3((unsigned)nb), dim3(SCAN_BT), 0, s, a, n, (const int32_t *)part);
+        return;
+    }
     hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(SCAN_T), 0, s, part, nb);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BT), 0, s, a, n, (const int32_t *)part);
 }
