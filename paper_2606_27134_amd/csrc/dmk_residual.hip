@@ -552,7 +552,7 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(Re
     if (tile >= P.ntiles) return;
 
     const int4 TD = P.tiles[tile];
-    const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+    const int n1 = P.n[1], n2 = P.n[2];
     const int col = TD.x, z0 = TD.y;
     const bool dense = TD.z < 0;
     const int z1 = dense ? z0 : TD.z;
