@@ -90,6 +90,8 @@ typedef struct {
     int64_t N;           /* number of points                                   */
     int64_t nbox;        /* n0*n1*n2                                           */
     int64_t ntiles;      /* target tiles built by dmk_tree_bin (host value)    */
+    int64_t nheavy;      /* leading tiles of high cost, run with more           */
+                         /*          wavefronts per workgroup (host value)     */
     int64_t max_tiles;   /* capacity of `tiles`                                */
     int32_t *key;        /* [N]      box id of each point, original order       */
     int32_t *perm;       /* [N]      sorted position -> original index          */
@@ -102,7 +104,7 @@ typedef struct {
                          /*          neighbour's points sit at x + s*L_i         */
     int32_t *tiles;      /* [max_tiles][4] target tiles {leaf column, z0, z1 or  */
                          /*          -(z0+1) for one dense box, first target}  */
-    int32_t *status;     /* [4] device error word, tile count                   */
+    int32_t *status;     /* [4] device error word, tile count, heavy tiles      */
     int32_t *tmp;        /* sort / tile scratch                                  */
     int64_t tmp_ints;    /* size of tmp in int32                                 */
 } dmk_bins;
@@ -126,7 +128,8 @@ int dmk_bins_carve(const dmk_grid *grid, int64_t N, void *dev_arena, size_t aren
  *    target tiles used by the residual kernels.
  * Runs on `stream`, then synchronises it once to read the error word:
  * DMK_EDOMAIN if any coordinate is non-finite or a free-axis coordinate is
- * outside [0, L).  Sets bins->ntiles.
+ * outside [0, L).  Sets bins->ntiles and bins->nheavy (tiles are ordered by
+ * descending power-of-two cost class; the first nheavy are the costly ones).
  */
 int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bins, hipStream_t stream);
 

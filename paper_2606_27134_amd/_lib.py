@@ -26,7 +26,8 @@ class dmk_grid(ctypes.Structure):
 
 class dmk_bins(ctypes.Structure):
     _fields_ = [
-        ("N", ctypes.c_int64), ("nbox", ctypes.c_int64), ("ntiles", ctypes.c_int64), ("max_tiles", ctypes.c_int64),
+        ("N", ctypes.c_int64), ("nbox", ctypes.c_int64), ("ntiles", ctypes.c_int64), ("nheavy", ctypes.c_int64),
+        ("max_tiles", ctypes.c_int64),
         ("key", ctypes.c_void_p), ("perm", ctypes.c_void_p), ("skey", ctypes.c_void_p),
         ("box_start", ctypes.c_void_p), ("ys", ctypes.c_void_p), ("axis_nbr", ctypes.c_void_p),
         ("axis_img", ctypes.c_void_p), ("tiles", ctypes.c_void_p), ("status", ctypes.c_void_p),

@@ -532,6 +532,7 @@ __device__ inline int slab_count(const TileGeom &g, const int ccol[9], int zv)
 // three-slab neighbourhood of fewer than 2^30 points), so no two bit lengths
 // share a class.
 constexpr int TK_CLASSES = 40;
+static_assert(TILE_HEAVY_LOG >= 1 && TILE_HEAVY_LOG <= TK_CLASSES, "heavy tile threshold");
 __device__ inline int tile_class(int64_t cost)
 {
     const int len = 64 - __clzll((unsigned long long)(cost + 1));
@@ -598,7 +599,8 @@ __device__ inline double tw_total(double v)
 // gives every (class, column) its first rank in the stable heavy-first
 // order); the last column also zeroes the sentinel table[TK_CLASSES * ncol],
 // which the scan turns into the number of tiles.  Writing pass: each tile at
-// its final position (xcd_position), and the number of tiles in st[1].
+// its final position (xcd_position), the number of tiles in st[1] and the
+// number of heavy tiles (cost + 1 of bit length above TILE_HEAVY_LOG) in st[2].
 template <bool WRITE>
 __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ table, int4 *__restrict__ tiles,
                           int64_t cap, int32_t *__restrict__ st)
@@ -716,6 +718,7 @@ __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ tabl
         if (lane == 0 && col == ncol - 1) table[(int64_t)TK_CLASSES * ncol] = 0;
     } else if (lane == 0 && col == ncol - 1) {
         st[1] = table[(int64_t)TK_CLASSES * ncol];
+        st[2] = table[(int64_t)(TK_CLASSES - TILE_HEAVY_LOG) * ncol];  // tiles of the classes before
     }
 }
 
@@ -951,7 +954,9 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     DMK_HIP_CHECK(hipStreamSynchronize(stream));
     if (st[0] != 0) return DMK_EDOMAIN;
     if (st[1] < 0 || st[1] > bins->max_tiles) return DMK_ESIZE;
+    if (st[2] < 0 || st[2] > st[1]) return DMK_EHIP;
     bins->ntiles = st[1];
+    bins->nheavy = st[2];
     return DMK_OK;
 }
 

@@ -29,6 +29,18 @@ constexpr int XCDS = 8;  // accelerator complex dies: workgroup i runs on XCD i 
 constexpr int TILE_T = DMK_TILE_T;
 constexpr int TILE_CAP = DMK_TILE_CAP;
 constexpr int TILE_NW = DMK_WAVES_PER_TILE;  // wavefronts per tile workgroup
+// Tiles of cost (targets times the sources of their stencil ranges, summed
+// over the tile's boxes) 2^TILE_HEAVY_LOG - 1 or more are "heavy": they come
+// first in the tile order, and the pair kernels give them HEAVY_NW
+// wavefronts per workgroup where a workgroup of that size fits in LDS
+#ifndef DMK_TILE_HEAVY_LOG
+#define DMK_TILE_HEAVY_LOG 16
+#endif
+#ifndef DMK_WAVES_PER_HEAVY_TILE
+#define DMK_WAVES_PER_HEAVY_TILE 8
+#endif
+constexpr int TILE_HEAVY_LOG = DMK_TILE_HEAVY_LOG;
+constexpr int HEAVY_NW = DMK_WAVES_PER_HEAVY_TILE;
 #ifndef DMK_TILE_ZMAX
 #define DMK_TILE_ZMAX 46
 #endif

@@ -52,7 +52,7 @@ struct KDim {
 // a scan step reads a window of 128 staged slots
 static_assert(TILE_CAP >= 2 * WAVE && TILE_CAP < 65536, "staged slots per tile");
 
-template <int KERN, typename FP, bool BWD>
+template <int KERN, typename FP, bool BWD, bool HEAVY>
 struct Cfg {
     static constexpr int K = KERN;
     static constexpr int MIN = KDim<KERN>::MIN;
@@ -71,12 +71,16 @@ struct Cfg {
     // LDS bytes of the staged sources and of one wavefront's queue; tiles use
     // TILE_NW wavefronts, 8 when only one workgroup fits in the 160 KiB of a
     // CU (more resident waves for the same staged tile; the rest of the
-    // workgroup's LDS is below 16 KiB), and 2 if TILE_NW would not fit at all
+    // workgroup's LDS is below 16 KiB), and 2 if TILE_NW would not fit at all.
+    // The heavy-tile variant has HEAVY_NW instead of TILE_NW where that fits
+    // in LDS (whether it runs is decided at launch, heavy_pays).
     static constexpr int STAGE_B = TILE_CAP * (16 + (F32 ? 16 + 4 * (NPL - 1) : 8 * (3 + NPL))) + 64;
     static constexpr int WAVE_B = QCAP * 4;
-    static constexpr int NW = (STAGE_B + TILE_NW * WAVE_B > 150 * 1024) ? 2
-                              : (STAGE_B + TILE_NW * WAVE_B + 16 * 1024 > 80 * 1024) ? 8
-                                                                                       : TILE_NW;
+    static constexpr int NW0 = (STAGE_B + TILE_NW * WAVE_B > 150 * 1024) ? 2
+                               : (STAGE_B + TILE_NW * WAVE_B + 16 * 1024 > 80 * 1024) ? 8
+                                                                                        : TILE_NW;
+    static constexpr int NW =
+        (HEAVY && NW0 == TILE_NW && STAGE_B + HEAVY_NW * WAVE_B <= 150 * 1024) ? HEAVY_NW : NW0;
 };
 
 struct ResParams {
@@ -84,7 +88,8 @@ struct ResParams {
     int n[3], D;
     double sigma, rc;
     int64_t N;
-    int ntiles, tile0;  // tiles in all; first tile of this launch
+    int ntiles, tile0;  // end of this launch's tile range; its first tile
+    int nheavy;         // leading tiles run with the heavy-tile workgroup
     const double *ys;
     const int32_t *skey, *bs, *perm, *nbr;
     const int8_t *img;
@@ -535,10 +540,11 @@ __device__ inline bool seg_sum(int tag, T *v)
     return last;
 }
 
-template <int KERN, typename FP, bool BWD, int WIN>
-__global__ __launch_bounds__((Cfg<KERN, FP, BWD>::NW * WAVE)) void k_residual(ResParams P, WinArg<WIN, FP> WC)
+template <int KERN, typename FP, bool BWD, int WIN, bool HEAVY>
+__global__ __launch_bounds__((Cfg<KERN, FP, BWD, HEAVY>::NW * WAVE)) void k_residual(ResParams P,
+                                                                                     WinArg<WIN, FP> WC)
 {
-    using C = Cfg<KERN, FP, BWD>;
+    using C = Cfg<KERN, FP, BWD, HEAVY>;
     using T = FP;
     __shared__ Smem<C> S;
     const int tid = threadIdx.x;
@@ -948,6 +954,7 @@ int check_call(const dmk_grid *g, const dmk_bins *b, int kernel, int prec, doubl
     if (!(rc > 0.0) || !(rc <= hmin)) return DMK_ECUTOFF;
     if (b->N > 0 && (!b->perm || !b->skey || !b->box_start || !b->ys || !b->tiles || !b->axis_nbr || !b->axis_img))
         return DMK_EINVAL;
+    if (b->nheavy < 0 || b->nheavy > b->ntiles) return DMK_EINVAL;
     return DMK_OK;
 }
 
@@ -981,6 +988,47 @@ size_t ws_need(int64_t N, int kernel, int backward)
     return ws_part(N, m_in_of(kernel)) + (backward ? ws_part(N, m_out_of(kernel)) : 0) + 256;
 }
 
+// tiles [t0, t1), one workgroup per tile, in launches of fewer than 2^32
+// work-items
+template <int KERN, typename FP, bool BWD, int WIN, bool HEAVY>
+void launch_range(const ResParams &P, int t0, int t1, const WinArg<WIN, FP> &wc, hipStream_t s)
+{
+    constexpr int NT = Cfg<KERN, FP, BWD, HEAVY>::NW * WAVE;
+    constexpr int MAXB = (int)(0xffffffffu / NT);
+    for (int a = t0; a < t1; a += MAXB) {
+        ResParams Q = P;
+        Q.tile0 = a;
+        Q.ntiles = t1;
+        hipLaunchKernelGGL((k_residual<KERN, FP, BWD, WIN, HEAVY>), dim3((unsigned)min(MAXB, t1 - a)), dim3(NT), 0,
+                           s, Q, wc);
+        if (t1 - a <= MAXB) break;
+    }
+}
+
+// Whether heavy tiles run with the larger workgroup: only where it keeps
+// more wavefronts resident per CU than the smaller one, given each variant's
+// LDS and register use.  A tile's waves split its long scans between them,
+// so on a heavy tile more waves hide more of the latency of each; where the
+// registers or LDS allow no more resident waves, the larger workgroup only
+// adds waiting at its barriers (measured slower on clustered inputs).
+template <int KERN, typename FP, bool BWD, int WIN>
+bool heavy_pays()
+{
+    static const bool pays = [] {
+        constexpr int NL = Cfg<KERN, FP, BWD, false>::NW * WAVE;
+        constexpr int NH = Cfg<KERN, FP, BWD, true>::NW * WAVE;
+        if (NL == NH) return false;
+        int bl = 0, bh = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, k_residual<KERN, FP, BWD, WIN, false>, NL, 0) !=
+                hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&bh, k_residual<KERN, FP, BWD, WIN, true>, NH, 0) !=
+                hipSuccess)
+            return false;
+        return bh * NH > bl * NL;
+    }();
+    return pays;
+}
+
 template <int KERN, typename FP, bool BWD, int WIN>
 void launch_one(const ResParams &P, const dmk_pswf *w, hipStream_t s)
 {
@@ -993,16 +1041,11 @@ void launch_one(const ResParams &P, const dmk_pswf *w, hipStream_t s)
     } else {
         (void)w;
     }
-    // one workgroup per tile, in launches of fewer than 2^32 work-items
-    constexpr int NT = Cfg<KERN, FP, BWD>::NW * WAVE;
-    constexpr int MAXB = (int)(0xffffffffu / NT);
-    for (int t0 = 0; t0 < P.ntiles; t0 += MAXB) {
-        ResParams Q = P;
-        Q.tile0 = t0;
-        hipLaunchKernelGGL((k_residual<KERN, FP, BWD, WIN>), dim3((unsigned)min(MAXB, P.ntiles - t0)), dim3(NT), 0, s,
-                           Q, wc);
-        if (P.ntiles - t0 <= MAXB) break;
-    }
+    // the heavy tiles [0, nheavy) with the larger workgroup where it pays,
+    // then the others (all tiles in one range otherwise)
+    const int nh = heavy_pays<KERN, FP, BWD, WIN>() ? P.nheavy : 0;
+    if (nh > 0) launch_range<KERN, FP, BWD, WIN, true>(P, 0, nh, wc, s);
+    launch_range<KERN, FP, BWD, WIN, false>(P, nh, P.ntiles, wc, s);
 }
 
 template <bool BWD, int WIN>
@@ -1039,6 +1082,7 @@ ResParams make_params(const dmk_grid *g, const dmk_bins *b, double sigma, double
     P.rc = rc;
     P.N = b->N;
     P.ntiles = (int)b->ntiles;
+    P.nheavy = (int)b->nheavy;
     P.ys = b->ys;
     P.skey = b->skey;
     P.bs = b->box_start;

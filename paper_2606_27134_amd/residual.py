@@ -66,6 +66,11 @@ class Bins:
     def ntiles(self) -> int:
         return int(self.c.ntiles)
 
+    @property
+    def nheavy(self) -> int:
+        """Leading tiles that the pair kernels run with the larger workgroup."""
+        return int(self.c.nheavy)
+
     # views into the arena (for tests and diagnostics)
     def _view(self, ptr, count, dtype):
         esz = torch.empty((), dtype=dtype).element_size()

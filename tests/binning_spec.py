@@ -87,6 +87,28 @@ def tiles_spec(box_start, D, n, T=64, CAP=512, ZMAX=46):
     for q = 0, 1, ..., 7 in turn, the next ceil((B - q) / 8) tiles of the
     bucket in order (one contiguous run per XCD of the pair kernels).
     """
+    tiles, keys = _tile_list(box_start, D, n, T, CAP, ZMAX)
+    order = np.argsort(keys, kind="stable")
+    srt, sk = tiles[order], keys[order]
+    out = np.empty_like(srt)
+    o = 0
+    while o < len(srt):
+        B = int(np.searchsorted(sk, sk[o], side="right")) - o
+        pos = [k for q in range(8) for k in range(q, B, 8)]
+        out[o + np.asarray(pos, dtype=np.int64)] = srt[o:o + B]
+        o += B
+    return out
+
+
+def heavy_count_spec(box_start, D, n, heavy_log=16, T=64, CAP=512, ZMAX=46):
+    """Number of tiles of cost 2^heavy_log - 1 or more (bit_length(cost + 1)
+    above heavy_log): the leading tiles of the heavy-first order."""
+    _, keys = _tile_list(box_start, D, n, T, CAP, ZMAX)
+    return int((keys <= 63 - heavy_log).sum())
+
+
+def _tile_list(box_start, D, n, T, CAP, ZMAX):
+    """The tiles column by column, with their keys 64 - bit_length(cost + 1)."""
     n0, n1, n2 = (int(v) for v in n)
     nbr, _ = axis_tables_spec(D, n)
     bs = np.asarray(box_start, dtype=np.int64)
@@ -138,15 +160,4 @@ def tiles_spec(box_start, D, n, T=64, CAP=512, ZMAX=46):
                 tiles.append((col, z, z1, first))
                 keys.append(64 - (cost + 1).bit_length())
                 z = z1 + 1
-    tiles = np.asarray(tiles, dtype=np.int32).reshape(-1, 4)
-    keys = np.asarray(keys, dtype=np.int64)
-    order = np.argsort(keys, kind="stable")
-    srt, sk = tiles[order], keys[order]
-    out = np.empty_like(srt)
-    o = 0
-    while o < len(srt):
-        B = int(np.searchsorted(sk, sk[o], side="right")) - o
-        pos = [k for q in range(8) for k in range(q, B, 8)]
-        out[o + np.asarray(pos, dtype=np.int64)] = srt[o:o + B]
-        o += B
-    return out
+    return np.asarray(tiles, dtype=np.int32).reshape(-1, 4), np.asarray(keys, dtype=np.int64)

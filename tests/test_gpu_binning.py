@@ -4,7 +4,7 @@ axis tables; structural checks of the target tiles."""
 import numpy as np
 import pytest
 
-from binning_spec import axis_tables_spec, bin_spec, tiles_spec
+from binning_spec import axis_tables_spec, bin_spec, heavy_count_spec, tiles_spec
 from gpu_util import HAVE_GPU, dev, host, needs_gpu
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
@@ -13,6 +13,9 @@ if HAVE_GPU:
     import torch
     from paper_2606_27134_amd import residual as R
     from paper_2606_27134_amd import _lib as L
+
+
+HEAVY_LOG = 16  # tiles of cost 2^16 - 1 or more run with the larger workgroup
 
 
 def _points(seed, N, Lv, D, kind):
@@ -112,6 +115,7 @@ def _check_tiles(b, n, ref, D):
         covered[t0:t0 + cnt] += 1
     assert (covered == 1).all(), "every target in exactly one tile"
     np.testing.assert_array_equal(tiles.reshape(-1, 4), tiles_spec(bs, D, n))
+    assert b.nheavy == heavy_count_spec(bs, D, n, HEAVY_LOG)
 
 
 def test_binning_rejects_bad_points():
@@ -136,6 +140,8 @@ def test_binning_dense_and_empty():
     np.testing.assert_array_equal(host(b.perm()), ref["perm"])
     np.testing.assert_array_equal(host(b.box_start()), ref["box_start"])
     assert b.ntiles == (3000 + 63) // 64
+    # 46 tiles of 64 targets x 3000 sources, and one of 56 x 3000
+    assert b.nheavy == b.ntiles
     _check_tiles(b, (6, 6, 6), ref, 3)
 
 

@@ -109,6 +109,9 @@ def test_dense_boxes(kernel, prec):
     got, b = run_fwd(w, prec)
     tiles = host(b.tiles())
     assert (tiles[:, 2] < 0).sum() >= 20, "expected dense tiles"
+    # both workgroup sizes run: heavy tiles (the dense ones of the cluster
+    # box) and light ones
+    assert 20 <= b.nheavy < b.ntiles
     assert_parity(got, oracle_fwd(w), TOL[prec], "dense fwd %s %s" % (kernel, prec))
     G = W.cotangent(78, N, W.M_OUT[kernel])
     gr, gx = run_bwd(w, prec, G)
