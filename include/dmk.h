@@ -91,7 +91,9 @@ typedef struct {
     int64_t nbox;        /* n0*n1*n2                                           */
     int64_t ntiles;      /* target tiles built by dmk_tree_bin (host value)    */
     int64_t nheavy;      /* leading tiles of high cost, run with more           */
-                         /*          wavefronts per workgroup (host value)     */
+                         /*          wavefronts per workgroup (host value;     */
+                         /*          residual calls reject it outside          */
+                         /*          [0, ntiles] with DMK_EINVAL)              */
     int64_t max_tiles;   /* capacity of `tiles`                                */
     int32_t *key;        /* [N]      box id of each point, original order       */
     int32_t *perm;       /* [N]      sorted position -> original index          */
