@@ -1010,23 +1010,22 @@ void launch_range(const ResParams &P, int t0, int t1, const WinArg<WIN, FP> &wc,
 // LDS and register use.  A tile's waves split its long scans between them,
 // so on a heavy tile more waves hide more of the latency of each; where the
 // registers or LDS allow no more resident waves, the larger workgroup only
-// adds waiting at its barriers (measured slower on clustered inputs).
+// adds waiting at its barriers (measured slower on clustered inputs).  Asked
+// on every call that has heavy tiles (a host-side query of the current
+// device; nothing is cached); a failed query leaves its error for the
+// launch check.
 template <int KERN, typename FP, bool BWD, int WIN>
 bool heavy_pays()
 {
-    static const bool pays = [] {
-        constexpr int NL = Cfg<KERN, FP, BWD, false>::NW * WAVE;
-        constexpr int NH = Cfg<KERN, FP, BWD, true>::NW * WAVE;
-        if (NL == NH) return false;
-        int bl = 0, bh = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, k_residual<KERN, FP, BWD, WIN, false>, NL, 0) !=
-                hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&bh, k_residual<KERN, FP, BWD, WIN, true>, NH, 0) !=
-                hipSuccess)
-            return false;
-        return bh * NH > bl * NL;
-    }();
-    return pays;
+    constexpr int NL = Cfg<KERN, FP, BWD, false>::NW * WAVE;
+    constexpr int NH = Cfg<KERN, FP, BWD, true>::NW * WAVE;
+    if (NL == NH) return false;
+    int bl = 0, bh = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, k_residual<KERN, FP, BWD, WIN, false>, NL, 0) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&bh, k_residual<KERN, FP, BWD, WIN, true>, NH, 0) != hipSuccess)
+        return false;
+    return bh * NH > bl * NL;
 }
 
 template <int KERN, typename FP, bool BWD, int WIN>
@@ -1043,7 +1042,7 @@ void launch_one(const ResParams &P, const dmk_pswf *w, hipStream_t s)
     }
     // the heavy tiles [0, nheavy) with the larger workgroup where it pays,
     // then the others (all tiles in one range otherwise)
-    const int nh = heavy_pays<KERN, FP, BWD, WIN>() ? P.nheavy : 0;
+    const int nh = (P.nheavy > 0 && heavy_pays<KERN, FP, BWD, WIN>()) ? P.nheavy : 0;
     if (nh > 0) launch_range<KERN, FP, BWD, WIN, true>(P, 0, nh, wc, s);
     launch_range<KERN, FP, BWD, WIN, false>(P, nh, P.ntiles, wc, s);
 }
