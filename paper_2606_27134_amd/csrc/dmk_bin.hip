@@ -560,11 +560,22 @@ __device__ inline int64_t xcd_position(int64_t o, int64_t B, int64_t r)
 // One wavefront per leaf column (b0, b1).  The lanes first stage, for the
 // column's z range, the first target and the target count of each box and
 // the slab count (sources in the 9 stencil columns at that z) in LDS
-// (dynamic: three ints per box, for the first TW_ZST boxes); the column is
-// then walked in z, each tile growing while its targets, its staged sources
-// and its z extent fit.  Columns taller than TW_ZST boxes read the rest from
-// the box starts.
+// (dynamic: three ints per box, for the first TW_ZST boxes, and four per
+// cost class); the column is then walked in z, each tile growing while its
+// targets, its staged sources and its z extent fit.  Columns taller than
+// TW_ZST boxes read the rest from the box starts.  A workgroup holds up to
+// TW_WPB wavefronts, each walking a column of its own in an LDS region of its
+// own (TW_WPB where the regions total at most TW_WPB_LDS bytes, else one):
+// the walks use no workgroup barrier, and larger workgroups leave
+// workgroup slots on the CUs for the coordinate gather that shares the
+// counting walk's launch.
 constexpr int TW_ZST = 2048;
+constexpr int TW_WPB = 4;
+constexpr int TW_WPB_LDS = 32768;
+__host__ __device__ inline int tw_wave_ints(int n2)
+{
+    return 3 * (n2 < TW_ZST ? n2 : TW_ZST) + 4 * TK_CLASSES;
+}
 
 struct ColView {
     const TileGeom *g;
@@ -605,16 +616,17 @@ template <bool WRITE>
 __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ table, int4 *__restrict__ tiles,
                           int64_t cap, int32_t *__restrict__ st)
 {
-    extern __shared__ int tw_lds[];
+    extern __shared__ int tw_lds_all[];
     const int n2 = g.n[2];
     const int zst = n2 < TW_ZST ? n2 : TW_ZST;
+    int *tw_lds = tw_lds_all + (threadIdx.x / WAVE) * tw_wave_ints(n2);
     int *snt = tw_lds, *ssl = tw_lds + zst, *sbs = tw_lds + 2 * zst;
     int *run = tw_lds + 3 * zst;        // tiles of each class so far in this column
     int *cbase = run + TK_CLASSES;      // rank of this column's first tile within each class
     int *cofs = cbase + TK_CLASSES;     // first position of each class
     int *clen = cofs + TK_CLASSES;      // tiles in each class
     const int64_t ncol = (int64_t)g.n[0] * g.n[1];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (WAVE - 1);
     const int b0 = col / g.n[1], b1 = col % g.n[1];
     int ccol[9];
     for (int k = 0; k < 9; ++k) {
@@ -640,9 +652,11 @@ __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ tabl
             clen[lane] = (int)(table[(int64_t)(lane + 1) * ncol] - o);
         }
     }
-    __syncthreads();
-    // One wavefront per workgroup: from here on, the LDS counters are read by
-    // all lanes and updated by lane 0 in program order (wave_fence).
+    wave_fence();
+    // The wavefront's own LDS region: from here on, the staged boxes and the
+    // counters are read by all lanes, and the counters updated by lane 0, in
+    // program order (LDS operations of a wavefront complete in order;
+    // wave_fence keeps the compiler from moving them).
     // final position of the next tile of class c (uniform c)
     auto place = [&](int c, int ahead) -> int64_t {
         return xcd_position(cofs[c], clen[c], (int64_t)cbase[c] + run[c] + ahead);
@@ -723,26 +737,31 @@ __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ tabl
 }
 
 template <bool WRITE>
-__global__ __launch_bounds__(WAVE) void k_tiles(TileGeom g, int col0, int32_t *__restrict__ table,
-                                                int4 *__restrict__ tiles, int64_t cap, int32_t *__restrict__ st)
+__global__ __launch_bounds__(TW_WPB *WAVE) void k_tiles(TileGeom g, int64_t col0, int32_t *__restrict__ table,
+                                                         int4 *__restrict__ tiles, int64_t cap,
+                                                         int32_t *__restrict__ st)
 {
-    tile_walk<WRITE>(g, col0 + (int)blockIdx.x, table, tiles, cap, st);
+    const int64_t col = col0 + (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    if (col >= (int64_t)g.n[0] * g.n[1]) return;  // whole wavefronts
+    tile_walk<WRITE>(g, (int)col, table, tiles, cap, st);
 }
 
-// The counting walk (blocks below ncol, one column each) and the sorted
-// coordinates (the blocks after them, GY points per thread) in one launch:
+// The counting walk (blocks below nwb, one column per wavefront) and the
+// sorted coordinates (the blocks after them, GY points per thread) in one launch:
 // both wait mostly on memory and do not depend on each other, so their
 // wavefronts overlap on the device.
-__global__ __launch_bounds__(WAVE) void k_ys_count(TileGeom tg, unsigned ncol, int32_t *__restrict__ table,
-                                                   int64_t cap, int32_t *__restrict__ st,
-                                                   const double *__restrict__ x, const int32_t *__restrict__ perm,
-                                                   int64_t N, BinGeom g, double *__restrict__ ys)
+__global__ __launch_bounds__(TW_WPB *WAVE) void k_ys_count(TileGeom tg, unsigned nwb, int32_t *__restrict__ table,
+                                                            int64_t cap, int32_t *__restrict__ st,
+                                                            const double *__restrict__ x,
+                                                            const int32_t *__restrict__ perm, int64_t N, BinGeom g,
+                                                            double *__restrict__ ys)
 {
-    if (blockIdx.x < ncol) {
-        tile_walk<false>(tg, (int)blockIdx.x, table, nullptr, cap, st);
+    if (blockIdx.x < nwb) {
+        const int64_t col = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+        if (col < (int64_t)tg.n[0] * tg.n[1]) tile_walk<false>(tg, (int)col, table, nullptr, cap, st);
         return;
     }
-    gather_ys_at(x, perm, N, g, ys, ((int64_t)(blockIdx.x - ncol) * WAVE + threadIdx.x) * GY);
+    gather_ys_at(x, perm, N, g, ys, ((int64_t)(blockIdx.x - nwb) * blockDim.x + threadIdx.x) * GY);
 }
 
 }  // namespace dmk
@@ -923,31 +942,37 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     const int64_t ntab = (int64_t)TK_CLASSES * ncol;
     int32_t *table = bins->tmp;
     int32_t *tpart = bins->tmp + ((ntab + 1 + 63) & ~(int64_t)63);
-    // one wavefront per column, in launches of fewer than 2^32 work-items;
-    // LDS: first target, target count and slab count of each staged box, and
-    // four ints per cost class
-    constexpr int64_t TCB = 0xffffffffu / WAVE;
-    const size_t tw_lds = sizeof(int) * (3 * (size_t)std::min(grid->n[2], TW_ZST) + 4 * TK_CLASSES);
+    // one wavefront per column, wpb columns per workgroup, in launches of
+    // fewer than 2^32 work-items; LDS per wavefront: first target, target
+    // count and slab count of each staged box, and four ints per cost class
+    const size_t tw_wave = sizeof(int) * (size_t)tw_wave_ints(grid->n[2]);
+    const int wpb = tw_wave * TW_WPB <= (size_t)TW_WPB_LDS ? TW_WPB : 1;
+    const size_t tw_lds = tw_wave * wpb;
+    const int64_t bt = (int64_t)wpb * WAVE;          // threads per workgroup
+    const int64_t maxb = 0xffffffffu / bt;           // workgroups per launch
+    const int64_t nwb = (ncol + wpb - 1) / wpb;      // workgroups of the walks
     // the counting walk and the sorted coordinates in one launch (the walk's
-    // columns first, then blocks of WAVE threads taking GY points each)
-    const int64_t nyb = N > 0 ? ((N + GY - 1) / GY + WAVE - 1) / WAVE : 0;
-    if (ncol + nyb <= TCB) {
-        hipLaunchKernelGGL(k_ys_count, dim3((unsigned)(ncol + nyb)), dim3(WAVE), tw_lds, stream, tg, (unsigned)ncol,
-                           table, bins->max_tiles, bins->status, x, (const int32_t *)bins->perm, N, g, bins->ys);
+    // workgroups first, then workgroups of bt threads taking GY points each)
+    const int64_t nyb = N > 0 ? ((N + GY - 1) / GY + bt - 1) / bt : 0;
+    if (nwb + nyb <= maxb) {
+        hipLaunchKernelGGL(k_ys_count, dim3((unsigned)(nwb + nyb)), dim3((unsigned)bt), tw_lds, stream, tg,
+                           (unsigned)nwb, table, bins->max_tiles, bins->status, x, (const int32_t *)bins->perm, N, g,
+                           bins->ys);
     } else {
-        for (int64_t c0 = 0; c0 < ncol; c0 += TCB)
-            hipLaunchKernelGGL(k_tiles<false>, dim3((unsigned)std::min(TCB, ncol - c0)), dim3(WAVE), tw_lds, stream,
-                               tg, (int)c0, table, (int4 *)bins->tiles, bins->max_tiles, bins->status);
+        for (int64_t b0 = 0; b0 < nwb; b0 += maxb)
+            hipLaunchKernelGGL(k_tiles<false>, dim3((unsigned)std::min(maxb, nwb - b0)), dim3((unsigned)bt), tw_lds,
+                               stream, tg, b0 * wpb, table, (int4 *)bins->tiles, bins->max_tiles, bins->status);
+        // (N < 2^30 points: one launch of fewer than 2^28 threads)
         if (nyb > 0)
-            hipLaunchKernelGGL(k_ys_count, dim3((unsigned)nyb), dim3(WAVE), 0, stream, tg, 0u, table,
+            hipLaunchKernelGGL(k_ys_count, dim3((unsigned)nyb), dim3((unsigned)bt), 0, stream, tg, 0u, table,
                                bins->max_tiles, bins->status, x, (const int32_t *)bins->perm, N, g, bins->ys);
     }
     // first rank of every (class, column) in the heavy-first order, and the
     // number of tiles in the sentinel; then every tile at its place
     scan_excl(table, ntab + 1, tpart, stream);
-    for (int64_t c0 = 0; c0 < ncol; c0 += TCB)
-        hipLaunchKernelGGL(k_tiles<true>, dim3((unsigned)std::min(TCB, ncol - c0)), dim3(WAVE), tw_lds, stream, tg,
-                           (int)c0, table, (int4 *)bins->tiles, bins->max_tiles, bins->status);
+    for (int64_t b0 = 0; b0 < nwb; b0 += maxb)
+        hipLaunchKernelGGL(k_tiles<true>, dim3((unsigned)std::min(maxb, nwb - b0)), dim3((unsigned)bt), tw_lds, stream,
+                           tg, b0 * wpb, table, (int4 *)bins->tiles, bins->max_tiles, bins->status);
     DMK_HIP_CHECK(hipGetLastError());
     int32_t st[4] = {0, 0, 0, 0};
     DMK_HIP_CHECK(hipMemcpyAsync(st, bins->status, sizeof(st), hipMemcpyDeviceToHost, stream));

@@ -2,8 +2,9 @@
 
 A dispatch holds fewer than 2^32 work-items, so the library splits the pair
 kernel (one workgroup of 256 threads per tile: more than 16,777,215 tiles)
-and the tile walk of the binning (one wavefront per leaf column: more than
-67,108,863 columns) into several launches.  These cases cross those limits
+and the tile walk of the binning (one wavefront per leaf column, four
+columns per 256-thread workgroup: more than 67,108,860 columns) into several
+launches.  These cases cross those limits
 with sparse point sets and compare targets on both sides of each split with
 the oracle.
 """
@@ -21,7 +22,7 @@ if HAVE_GPU:
 TOL = {"fp64": 1e-12, "fp32c": 1e-6}
 T_C = 5.042030  # erfc(t_c) = 1e-12: Gaussian window at the cutoff
 TILE_LAUNCH = 0xFFFFFFFF // 256  # tiles per launch of the 256-thread variants
-COL_LAUNCH = 0xFFFFFFFF // 64    # columns per launch of the tile walk
+COL_LAUNCH = (0xFFFFFFFF // 256) * 4  # columns per launch of the tile walk
 
 
 def _lattice(n, seed):
