@@ -85,6 +85,36 @@ def count_pairs(w, targets=None):
     return int(q.count_neighbors(tree, w.rc)) - len(targets)
 
 
+def count_candidates(w):
+    """Candidate pairs P_cand: for every target, the points of its own leaf box
+    and its 26 neighbours (images across periodic faces), itself included --
+    the stencil the pair kernels scan.  Box counts from the points on the
+    host; a neighbour beyond a free face is empty."""
+    L = np.asarray(w.L, dtype=np.float64)
+    n = np.asarray(w.n)
+    b = np.empty((w.N, 3), dtype=np.int64)
+    for i in range(3):
+        y = np.mod(w.x[:, i], L[i]) if i < w.D else w.x[:, i]
+        b[:, i] = np.minimum(n[i] - 1, np.floor(y * (n[i] / L[i])).astype(np.int64))
+    cnt = np.bincount((b[:, 0] * n[1] + b[:, 1]) * n[2] + b[:, 2], minlength=int(np.prod(n))).reshape(n)
+    S = cnt.astype(np.int64)
+    for i in range(3):
+        T = S.copy()
+        for d in (-1, 1):
+            if i < w.D:
+                T += np.roll(S, d, axis=i)
+            else:
+                sh = np.zeros_like(S)
+                src = [slice(None)] * 3
+                dst = [slice(None)] * 3
+                src[i] = slice(max(0, -d), n[i] - max(0, d))
+                dst[i] = slice(max(0, d), n[i] - max(0, -d))
+                sh[tuple(dst)] = S[tuple(src)]
+                T += sh
+        S = T
+    return int((cnt * S).sum())
+
+
 def kernel_hash():
     """Hash of the sources that k_residual is built from (the counter-based
     traffic applies only while they are unchanged)."""
@@ -237,8 +267,11 @@ def time_residual(w, bins, prec, steps, warmup, pswf_c=None):
     t_wall = time.perf_counter() - t_wall
     ms = start.elapsed_time(stop) / steps
     el = lambda a, b: float(np.mean([ev[s][a].elapsed_time(ev[s][b]) for s in range(steps)]))  # noqa: E731
+    med = lambda a, b: float(np.median([ev[s][a].elapsed_time(ev[s][b]) for s in range(steps)]))  # noqa: E731
     res = dict(ms_per_step=ms, fwd_ms=el(0, 2), bwd_ms=el(2, 4), kernel_fwd_ms=el(1, 2), kernel_bwd_ms=el(3, 4),
-               gather_fwd_ms=el(0, 1), gather_bwd_ms=el(2, 3), wall_s=t_wall)
+               gather_fwd_ms=el(0, 1), gather_bwd_ms=el(2, 3), wall_s=t_wall,
+               median_ms={"step": med(0, 4), "fwd": med(0, 2), "bwd": med(2, 4), "kernel_fwd": med(1, 2),
+                          "kernel_bwd": med(3, 4)})
     outs = (u.cpu().numpy(), gr.cpu().numpy(), gx.cpu().numpy())
     return res, outs
 
@@ -307,10 +340,13 @@ def bench_workload(w, precs, steps, warmup):
 
 
 def config_object(label, w, P_in, bin_ms, res, errs):
+    P_cand = count_candidates(w)
     o = {"workload": "%s: %s D=%d L=%s n=%s N=%d sigma=%.6g rc=%.6g" % (
-        w.name, w.kernel, w.D, list(w.L), list(w.n), w.N, w.sigma, w.rc), "P_in": P_in, "bin_ms": bin_ms}
+        w.name, w.kernel, w.D, list(w.L), list(w.n), w.N, w.sigma, w.rc), "P_in": P_in, "P_cand": P_cand,
+        "bin_ms": bin_ms}
     for prec, r in res.items():
         o[prec] = {"value": P_in / (r["ms_per_step"] * 1e-3), "value_fwd": P_in / (r["fwd_ms"] * 1e-3),
+                   "candidate_pairs_per_s": P_cand / (r["ms_per_step"] * 1e-3), "median_ms": r["median_ms"],
                    "ms_per_step": r["ms_per_step"], "fwd_ms": r["fwd_ms"], "bwd_ms": r["bwd_ms"],
                    "kernel_fwd_ms": r["kernel_fwd_ms"], "kernel_bwd_ms": r["kernel_bwd_ms"],
                    "roofline": roofline(w.kernel, prec, P_in, r)}
@@ -478,6 +514,7 @@ def main():
                           "kernel_bwd_ms": r["kernel_bwd_ms"]}), flush=True)
         return
     P_in = count_pairs(w)
+    P_cand = count_candidates(w)
 
     # ---- PSWF split (Sec. 2.2) on the same points: support nu = rc, so the
     # same in-cutoff pairs; bandwidth c from the paper's parameter tables
@@ -503,7 +540,8 @@ def main():
         "config": {"workload": "%s: %s D=%d L=%s n=%s N=%d sigma=%.6g rc=%.6g" % (
             w.name, w.kernel, w.D, list(w.L), list(w.n), w.N, w.sigma, w.rc),
             "precision": head, "step": "residual forward + adjoint (points pre-binned)"},
-        "P_in": P_in, "bin_ms": bin_ms,
+        "P_in": P_in, "P_cand": P_cand, "candidate_pairs_per_s": P_cand / (r["ms_per_step"] * 1e-3),
+        "bin_ms": bin_ms, "median_ms": r["median_ms"],
         "fwd_ms": r["fwd_ms"], "bwd_ms": r["bwd_ms"],
         "kernel_fwd_ms": r["kernel_fwd_ms"], "kernel_bwd_ms": r["kernel_bwd_ms"],
         "gather_fwd_ms": r["gather_fwd_ms"], "gather_bwd_ms": r["gather_bwd_ms"],
