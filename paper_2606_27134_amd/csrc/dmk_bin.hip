@@ -370,28 +370,35 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__rest
 // ---------------------------------------------------------------------------
 // 3.-5. sorted coordinates, box_start, axis tables
 
-// ys[ax][j] = wrapped x[perm[j]][ax]: each thread takes GY consecutive sorted
-// points and issues all of its loads before its stores
+// ys[ax][j] = wrapped x[perm[j]][ax]: a workgroup of nt threads takes GY * nt
+// consecutive sorted points from j0, thread t the points j0 + u * nt + t
+// (u < GY), so that every load of perm and every store of ys covers
+// consecutive addresses across the lanes (whole memory lines); each thread
+// issues all of its loads before its stores
 constexpr int GY = 4;
 __device__ inline void gather_ys_at(const double *__restrict__ x, const int32_t *__restrict__ perm, int64_t N,
-                                    const BinGeom &g, double *__restrict__ ys, int64_t j0)
+                                    const BinGeom &g, double *__restrict__ ys, int64_t j0, int nt, int t)
 {
-    if (j0 >= N) return;
     int64_t i[GY];
     double v[GY][3];
 #pragma unroll
-    for (int u = 0; u < GY; ++u) i[u] = j0 + u < N ? perm[j0 + u] : 0;
+    for (int u = 0; u < GY; ++u) {
+        const int64_t j = j0 + (int64_t)u * nt + t;
+        i[u] = j < N ? perm[j] : 0;
+    }
 #pragma unroll
     for (int u = 0; u < GY; ++u)
         for (int ax = 0; ax < 3; ++ax) v[u][ax] = x[3 * i[u] + ax];
 #pragma unroll
-    for (int u = 0; u < GY; ++u)
-        if (j0 + u < N)
+    for (int u = 0; u < GY; ++u) {
+        const int64_t j = j0 + (int64_t)u * nt + t;
+        if (j < N)
             for (int ax = 0; ax < 3; ++ax) {
                 double y = 0.0;
                 wrap_coord(v[u][ax], ax, g, y);
-                ys[(int64_t)ax * N + j0 + u] = y;
+                ys[(int64_t)ax * N + j] = y;
             }
+    }
 }
 
 // box_start from the key changes of the sorted keys: sorted position j is
@@ -761,7 +768,7 @@ __global__ __launch_bounds__(TW_WPB *WAVE) void k_ys_count(TileGeom tg, unsigned
         if (col < (int64_t)tg.n[0] * tg.n[1]) tile_walk<false>(tg, (int)col, table, nullptr, cap, st);
         return;
     }
-    gather_ys_at(x, perm, N, g, ys, ((int64_t)(blockIdx.x - nwb) * blockDim.x + threadIdx.x) * GY);
+    gather_ys_at(x, perm, N, g, ys, (int64_t)(blockIdx.x - nwb) * blockDim.x * GY, (int)blockDim.x, (int)threadIdx.x);
 }
 
 }  // namespace dmk
