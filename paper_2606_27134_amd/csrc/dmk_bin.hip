@@ -263,6 +263,18 @@ void scan_excl(int32_t *a, int64_t n, int32_t *part, hipStream_t s)
 // digit d so far (the last wavefront holding d in a round advances it); its
 // exclusive scan over the digits then gives each digit's first place in LDS.
 static_assert(RS_BINS == 2 * RS_THREADS, "two digits per thread in the local scan");
+// Key tile of scatter workgroup i.  Workgroup i runs on XCD i mod 8; the
+// workgroups of one XCD take one contiguous run of tiles, so that the runs
+// that consecutive tiles write for one digit (adjacent in the output) mostly
+// meet in the L2 of one XCD, which merges their partial memory lines.
+__device__ inline int rs_tile(int i, int nblk)
+{
+    const int q = i % XCDS;
+    int s = 0;
+    for (int p = 0; p < q; ++p) s += (nblk - p + XCDS - 1) / XCDS;  // tiles of XCD p (none when p >= nblk)
+    return s + i / XCDS;
+}
+
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__restrict__ kin,
                                                            const int32_t *__restrict__ vin, int64_t N,
                                                            int shift, int nbits,
@@ -279,7 +291,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__rest
     const int lane = tid & (WAVE - 1);
     const int w = tid / WAVE;
     const int nb = 1 << nbits, mask = nb - 1;
-    const int64_t b0 = (int64_t)blockIdx.x * RS_TILE;
+    const int tile = rs_tile((int)blockIdx.x, nblk);
+    const int64_t b0 = (int64_t)tile * RS_TILE;
     int kk[RS_ITEMS], vv[RS_ITEMS], lr[RS_ITEMS];
 #pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
@@ -290,7 +303,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__rest
     }
     for (int q = 0; q < RS_BPT; ++q) {
         const int d = q * RS_THREADS + tid;
-        base[d] = d < nb ? hist[(int64_t)d * nblk + blockIdx.x] : 0;
+        base[d] = d < nb ? hist[(int64_t)d * nblk + tile] : 0;
         run[d] = 0;
         for (int u = 0; u < NWV; ++u) wcnt[u][d] = 0;
     }
