@@ -75,7 +75,20 @@ __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_b
 // order): a compiler fence only.
 __device__ inline void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
-// per-block bucket counts, hist[d * nblk + block] for every bucket d < 2^nbits
+// Key tile of radix workgroup i (histogram and scatter).  Workgroup i runs on
+// XCD i mod 8; the workgroups of one XCD take one contiguous run of tiles, so
+// that what consecutive tiles write for one digit (adjacent counts of the
+// histogram, adjacent runs of the output) mostly meets in the L2 of one XCD,
+// which merges their partial memory lines.
+__device__ inline int rs_tile(int i, int nblk)
+{
+    const int q = i % XCDS;
+    int s = 0;
+    for (int p = 0; p < q; ++p) s += (nblk - p + XCDS - 1) / XCDS;  // tiles of XCD p (none when p >= nblk)
+    return s + i / XCDS;
+}
+
+// per-tile bucket counts, hist[d * nblk + tile] for every bucket d < 2^nbits
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const int32_t *__restrict__ keys, int64_t N, int shift,
                                                         int nbits, int32_t *__restrict__ hist, int nblk)
 {
@@ -84,7 +97,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const int32_t *__restric
     const int nb = 1 << nbits, mask = nb - 1;
     for (int q = 0; q < RS_BPT; ++q) h[q * RS_THREADS + tid] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const int tile = rs_tile((int)blockIdx.x, nblk);
+    const int64_t base = (int64_t)tile * RS_TILE;
     for (int r = 0; r < RS_ITEMS; ++r) {
         int64_t i = base + r * RS_THREADS + tid;
         if (i < N) atomicAdd(&h[(keys[i] >> shift) & mask], 1);
@@ -92,7 +106,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const int32_t *__restric
     __syncthreads();
     for (int q = 0; q < RS_BPT; ++q) {
         const int d = q * RS_THREADS + tid;
-        if (d < nb) hist[(int64_t)d * nblk + blockIdx.x] = h[d];
+        if (d < nb) hist[(int64_t)d * nblk + tile] = h[d];
     }
 }
 
@@ -263,18 +277,6 @@ void scan_excl(int32_t *a, int64_t n, int32_t *part, hipStream_t s)
 // digit d so far (the last wavefront holding d in a round advances it); its
 // exclusive scan over the digits then gives each digit's first place in LDS.
 static_assert(RS_BINS == 2 * RS_THREADS, "two digits per thread in the local scan");
-// Key tile of scatter workgroup i.  Workgroup i runs on XCD i mod 8; the
-// workgroups of one XCD take one contiguous run of tiles, so that the runs
-// that consecutive tiles write for one digit (adjacent in the output) mostly
-// meet in the L2 of one XCD, which merges their partial memory lines.
-__device__ inline int rs_tile(int i, int nblk)
-{
-    const int q = i % XCDS;
-    int s = 0;
-    for (int p = 0; p < q; ++p) s += (nblk - p + XCDS - 1) / XCDS;  // tiles of XCD p (none when p >= nblk)
-    return s + i / XCDS;
-}
-
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const int32_t *__restrict__ kin,
                                                            const int32_t *__restrict__ vin, int64_t N,
                                                            int shift, int nbits,
