@@ -84,11 +84,17 @@ def test_pswf_dense_boxes(kernel, prec):
     c = C_OF[kernel]
     rc = 1.0 / 8
     b = R.tree_bin((1.0, 1.0, 1.0), 3, (8, 8, 8), dev(x))
+    assert b.nheavy > 0  # the cluster's dense tiles lead the order as heavy tiles
     got = host(R.residual_eval(b, kernel, prec, 0.0, rc, dev(rho), pswf_c=c))
     t = np.sort(rng.choice(N, size=300, replace=False))
     t = np.unique(np.concatenate([t, np.arange(N - 2500, N - 2300)]))
     ref = oracle.residual(kernel, 3, (1, 1, 1), rc, rc, x, rho, targets=t, window=_ow(c))
     assert_parity(got[t], ref, TOL[prec], "pswf dense %s %s" % (kernel, prec))
+    G = rng.normal(size=(N, W.M_OUT[kernel]))
+    gr, gx = R.residual_backward(b, kernel, prec, 0.0, rc, dev(rho), dev(G), pswf_c=c)
+    rr, rx = oracle.residual_vjp(kernel, 3, (1, 1, 1), rc, rc, x, rho, G, targets=t, window=_ow(c))
+    assert_parity(host(gr)[t], rr, TOL[prec], "pswf dense grad_rho %s %s" % (kernel, prec))
+    assert_parity(host(gx)[t], rx, TOL[prec], "pswf dense grad_x %s %s" % (kernel, prec))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
