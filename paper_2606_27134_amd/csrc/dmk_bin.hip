@@ -566,17 +566,18 @@ __device__ inline int tile_class(int64_t cost)
 // class the positions o + k with k mod 8 = q (one XCD) take the q-th
 // contiguous run of the class's tiles, so every XCD works on a spatially
 // compact share of every class (tiles that stage the same neighbour columns
-// meet in one L2) and the heavy classes stay spread over all XCDs.
-__device__ inline int64_t xcd_position(int64_t o, int64_t B, int64_t r)
+// meet in one L2) and the heavy classes stay spread over all XCDs.  o, B
+// and r come from the int32 count table, so 32-bit arithmetic holds them.
+__device__ inline int64_t xcd_position(int o, int B, int r)
 {
-    int64_t start = 0;
+    int start = 0;
     int q = 0;
     for (; q < XCDS - 1; ++q) {
-        const int64_t len = q < B ? (B - q + XCDS - 1) / XCDS : 0;  // run of XCD q
+        const int len = q < B ? (B - q + XCDS - 1) / XCDS : 0;  // run of XCD q
         if (r < start + len) break;
         start += len;
     }
-    return o + XCDS * (r - start) + q;
+    return (int64_t)o + (int64_t)XCDS * (r - start) + q;
 }
 
 // One wavefront per leaf column (b0, b1).  The lanes first stage, for the
@@ -681,7 +682,7 @@ __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ tabl
     // wave_fence keeps the compiler from moving them).
     // final position of the next tile of class c (uniform c)
     auto place = [&](int c, int ahead) -> int64_t {
-        return xcd_position(cofs[c], clen[c], (int64_t)cbase[c] + run[c] + ahead);
+        return xcd_position(cofs[c], clen[c], cbase[c] + run[c] + ahead);
     };
     // The walk, with the whole wavefront on every step (z stays uniform).  A
     // tile starting at z may end at z + l for the l whose extent, targets and
