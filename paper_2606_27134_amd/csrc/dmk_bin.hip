@@ -597,24 +597,38 @@ constexpr int TW_WPB = 4;
 constexpr int TW_WPB_LDS = 32768;
 __host__ __device__ inline int tw_wave_ints(int n2)
 {
-    return 3 * (n2 < TW_ZST ? n2 : TW_ZST) + 4 * TK_CLASSES;
+    return 3 * (n2 < TW_ZST ? n2 : TW_ZST) + 2 + 4 * TK_CLASSES;
 }
 
+// The staged column.  sslp[zv + 1] is the slab count at virtual z zv: the
+// staged boxes at 1 .. zst, and (columns of at most TW_ZST boxes) the slabs
+// across the z faces at 0 and n2 + 1, so that those reads take no branch;
+// taller columns (TALL) read what is not staged from the box starts.
+template <bool TALL>
 struct ColView {
     const TileGeom *g;
     const int *ccol;
     const int *snt;
-    const int *ssl;
+    const int *sslp;
     const int *sbs;
     int col;
-    __device__ int nt(int z) const { return z < TW_ZST ? snt[z] : box_count(*g, col, z); }
-    __device__ int first(int z) const { return z < TW_ZST ? sbs[z] : g->bs[(int64_t)col * g->n[2] + z]; }
+    __device__ int nt(int z) const
+    {
+        if (!TALL) return snt[z];
+        return z < TW_ZST ? snt[z] : box_count(*g, col, z);
+    }
+    __device__ int first(int z) const
+    {
+        if (!TALL) return sbs[z];
+        return z < TW_ZST ? sbs[z] : g->bs[(int64_t)col * g->n[2] + z];
+    }
     // slab count at virtual z in [-1, n2]
     __device__ int sl(int zv) const
     {
+        if (!TALL) return sslp[zv + 1];
         const int zp = phys_z(*g, zv);
         if (zp < 0) return 0;
-        return zp < TW_ZST ? ssl[zp] : slab_count(*g, ccol, zp);
+        return zp < TW_ZST ? sslp[zp + 1] : slab_count(*g, ccol, zp);
     }
 };
 
@@ -635,7 +649,7 @@ __device__ inline double tw_total(double v)
 // which the scan turns into the number of tiles.  Writing pass: each tile at
 // its final position (xcd_position), the number of tiles in st[1] and the
 // number of heavy tiles (cost + 1 of bit length above TILE_HEAVY_LOG) in st[2].
-template <bool WRITE>
+template <bool WRITE, bool TALL>
 __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ table, int4 *__restrict__ tiles,
                           int64_t cap, int32_t *__restrict__ st)
 {
@@ -643,8 +657,8 @@ __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ tabl
     const int n2 = g.n[2];
     const int zst = n2 < TW_ZST ? n2 : TW_ZST;
     int *tw_lds = tw_lds_all + (threadIdx.x / WAVE) * tw_wave_ints(n2);
-    int *snt = tw_lds, *ssl = tw_lds + zst, *sbs = tw_lds + 2 * zst;
-    int *run = tw_lds + 3 * zst;        // tiles of each class so far in this column
+    int *snt = tw_lds, *sslp = tw_lds + zst, *sbs = tw_lds + 2 * zst + 2;
+    int *run = tw_lds + 3 * zst + 2;    // tiles of each class so far in this column
     int *cbase = run + TK_CLASSES;      // rank of this column's first tile within each class
     int *cofs = cbase + TK_CLASSES;     // first position of each class
     int *clen = cofs + TK_CLASSES;      // tiles in each class
@@ -664,7 +678,16 @@ __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ tabl
         sbs[z] = s0;
         int sc = 0;
         for (int k = 0; k < 9; ++k) sc += box_count(g, ccol[k], z);
-        ssl[z] = sc;
+        sslp[z + 1] = sc;
+    }
+    if (!TALL) {
+        // the slabs across the z faces: wrapped (periodic z) or empty
+        wave_fence();
+        if (lane == 0) {
+            const int lo = phys_z(g, -1), hi = phys_z(g, n2);
+            sslp[0] = lo < 0 ? 0 : sslp[lo + 1];
+            sslp[n2 + 1] = hi < 0 ? 0 : sslp[hi + 1];
+        }
     }
     if (lane < TK_CLASSES) {
         run[lane] = 0;
@@ -688,7 +711,7 @@ __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ tabl
     // tile starting at z may end at z + l for the l whose extent, targets and
     // staged sources all fit; each of these only grows with l, so the lanes
     // that fit form a prefix and one ballot gives the end.
-    const ColView cv{&g, ccol, snt, ssl, sbs, col};
+    const ColView<TALL> cv{&g, ccol, snt, sslp, sbs, col};
     int z = 0;
     while (z < n2) {
         {  // next box with targets
@@ -759,20 +782,21 @@ __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ tabl
     }
 }
 
-template <bool WRITE>
+template <bool WRITE, bool TALL>
 __global__ __launch_bounds__(TW_WPB *WAVE) void k_tiles(TileGeom g, int64_t col0, int32_t *__restrict__ table,
                                                          int4 *__restrict__ tiles, int64_t cap,
                                                          int32_t *__restrict__ st)
 {
     const int64_t col = col0 + (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     if (col >= (int64_t)g.n[0] * g.n[1]) return;  // whole wavefronts
-    tile_walk<WRITE>(g, (int)col, table, tiles, cap, st);
+    tile_walk<WRITE, TALL>(g, (int)col, table, tiles, cap, st);
 }
 
 // The counting walk (blocks below nwb, one column per wavefront) and the
 // sorted coordinates (the blocks after them, GY points per thread) in one launch:
 // both wait mostly on memory and do not depend on each other, so their
 // wavefronts overlap on the device.
+template <bool TALL>
 __global__ __launch_bounds__(TW_WPB *WAVE) void k_ys_count(TileGeom tg, unsigned nwb, int32_t *__restrict__ table,
                                                             int64_t cap, int32_t *__restrict__ st,
                                                             const double *__restrict__ x,
@@ -781,7 +805,7 @@ __global__ __launch_bounds__(TW_WPB *WAVE) void k_ys_count(TileGeom tg, unsigned
 {
     if (blockIdx.x < nwb) {
         const int64_t col = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-        if (col < (int64_t)tg.n[0] * tg.n[1]) tile_walk<false>(tg, (int)col, table, nullptr, cap, st);
+        if (col < (int64_t)tg.n[0] * tg.n[1]) tile_walk<false, TALL>(tg, (int)col, table, nullptr, cap, st);
         return;
     }
     gather_ys_at(x, perm, N, g, ys, (int64_t)(blockIdx.x - nwb) * blockDim.x * GY, (int)blockDim.x, (int)threadIdx.x);
@@ -904,6 +928,36 @@ extern "C" int dmk_bins_carve(const dmk_grid *grid, int64_t N, void *arena, size
     return DMK_OK;
 }
 
+// The tile walks and the coordinate gather: the counting walk beside the
+// gather, the scan of the count table, the writing walk (columns of more than
+// TW_ZST boxes: TALL)
+template <bool TALL>
+void walks(const TileGeom &tg, int wpb, int64_t bt, int64_t maxb, int64_t nwb, int64_t nyb,
+           size_t tw_lds, int32_t *table, int32_t *tpart, int64_t ntab, dmk_bins *bins, const double *x, int64_t N,
+           const BinGeom &g, hipStream_t stream)
+{
+    if (nwb + nyb <= maxb) {
+        hipLaunchKernelGGL(k_ys_count<TALL>, dim3((unsigned)(nwb + nyb)), dim3((unsigned)bt), tw_lds, stream, tg,
+                           (unsigned)nwb, table, bins->max_tiles, bins->status, x, (const int32_t *)bins->perm, N, g,
+                           bins->ys);
+    } else {
+        for (int64_t b0 = 0; b0 < nwb; b0 += maxb)
+            hipLaunchKernelGGL((k_tiles<false, TALL>), dim3((unsigned)std::min(maxb, nwb - b0)), dim3((unsigned)bt),
+                               tw_lds, stream, tg, b0 * wpb, table, (int4 *)bins->tiles, bins->max_tiles,
+                               bins->status);
+        // (N < 2^30 points: one launch of fewer than 2^28 threads)
+        if (nyb > 0)
+            hipLaunchKernelGGL(k_ys_count<TALL>, dim3((unsigned)nyb), dim3((unsigned)bt), 0, stream, tg, 0u, table,
+                               bins->max_tiles, bins->status, x, (const int32_t *)bins->perm, N, g, bins->ys);
+    }
+    // first rank of every (class, column) in the heavy-first order, and the
+    // number of tiles in the sentinel; then every tile at its place
+    scan_excl(table, ntab + 1, tpart, stream);
+    for (int64_t b0 = 0; b0 < nwb; b0 += maxb)
+        hipLaunchKernelGGL((k_tiles<true, TALL>), dim3((unsigned)std::min(maxb, nwb - b0)), dim3((unsigned)bt),
+                           tw_lds, stream, tg, b0 * wpb, table, (int4 *)bins->tiles, bins->max_tiles, bins->status);
+}
+
 extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bins, hipStream_t stream)
 {
     int rc = check_grid(grid);
@@ -977,25 +1031,10 @@ extern "C" int dmk_tree_bin(const dmk_grid *grid, const double *x, dmk_bins *bin
     // the counting walk and the sorted coordinates in one launch (the walk's
     // workgroups first, then workgroups of bt threads taking GY points each)
     const int64_t nyb = N > 0 ? ((N + GY - 1) / GY + bt - 1) / bt : 0;
-    if (nwb + nyb <= maxb) {
-        hipLaunchKernelGGL(k_ys_count, dim3((unsigned)(nwb + nyb)), dim3((unsigned)bt), tw_lds, stream, tg,
-                           (unsigned)nwb, table, bins->max_tiles, bins->status, x, (const int32_t *)bins->perm, N, g,
-                           bins->ys);
-    } else {
-        for (int64_t b0 = 0; b0 < nwb; b0 += maxb)
-            hipLaunchKernelGGL(k_tiles<false>, dim3((unsigned)std::min(maxb, nwb - b0)), dim3((unsigned)bt), tw_lds,
-                               stream, tg, b0 * wpb, table, (int4 *)bins->tiles, bins->max_tiles, bins->status);
-        // (N < 2^30 points: one launch of fewer than 2^28 threads)
-        if (nyb > 0)
-            hipLaunchKernelGGL(k_ys_count, dim3((unsigned)nyb), dim3((unsigned)bt), 0, stream, tg, 0u, table,
-                               bins->max_tiles, bins->status, x, (const int32_t *)bins->perm, N, g, bins->ys);
-    }
-    // first rank of every (class, column) in the heavy-first order, and the
-    // number of tiles in the sentinel; then every tile at its place
-    scan_excl(table, ntab + 1, tpart, stream);
-    for (int64_t b0 = 0; b0 < nwb; b0 += maxb)
-        hipLaunchKernelGGL(k_tiles<true>, dim3((unsigned)std::min(maxb, nwb - b0)), dim3((unsigned)bt), tw_lds, stream,
-                           tg, b0 * wpb, table, (int4 *)bins->tiles, bins->max_tiles, bins->status);
+    if (grid->n[2] > TW_ZST)
+        walks<true>(tg, wpb, bt, maxb, nwb, nyb, tw_lds, table, tpart, ntab, bins, x, N, g, stream);
+    else
+        walks<false>(tg, wpb, bt, maxb, nwb, nyb, tw_lds, table, tpart, ntab, bins, x, N, g, stream);
     DMK_HIP_CHECK(hipGetLastError());
     int32_t st[4] = {0, 0, 0, 0};
     DMK_HIP_CHECK(hipMemcpyAsync(st, bins->status, sizeof(st), hipMemcpyDeviceToHost, stream));
