@@ -632,15 +632,9 @@ struct ColView {
     }
 };
 
-// lane total of the tile walk's cost: a DPP sum over the wavefront (lane 63
-// holds it), every partial sum an integer below 2^53 and so exact
-__device__ inline double tw_total(double v)
-{
-    wave_sum<1, double>(&v);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), WAVE - 1);
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), WAVE - 1);
-    return __hiloint2double(hi, lo);
-}
+// lane total of the tile walk's cost: a DPP sum over the wavefront, read
+// from lane 63
+__device__ inline int tw_total(int v) { return __builtin_amdgcn_readlane(wave_incl_scan(v), WAVE - 1); }
 
 // Counting pass (WRITE false): the column's tiles per cost class, into
 // table[c * ncol + col] (class-major, so that the exclusive scan of the table
@@ -759,10 +753,9 @@ __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ tabl
         const int Q = wave_incl_scan(inr ? cv.sl(ze + 1) : 0) + cv.sl(z - 1) + cv.sl(z);
         const int len = __popcll(__ballot(inr && T <= TILE_T && Q <= TILE_CAP));
         const int z1 = z + len - 1;
-        // cost: sum over the tile's boxes of targets x the three slabs (below
-        // 2^21: at most TILE_T targets, each with at most TILE_CAP sources)
-        const double cost =
-            tw_total(lane < len ? (double)ntl * (double)(cv.sl(ze - 1) + cv.sl(ze) + cv.sl(ze + 1)) : 0.0);
+        // cost: sum over the tile's boxes of targets x the three slabs (at
+        // most TILE_T targets, each with at most TILE_CAP sources: below 2^22)
+        const int cost = tw_total(lane < len ? ntl * (cv.sl(ze - 1) + cv.sl(ze) + cv.sl(ze + 1)) : 0);
         const int c = tile_class((int64_t)cost);
         if (WRITE && lane == 0) {
             const int64_t pos = place(c, 0);
