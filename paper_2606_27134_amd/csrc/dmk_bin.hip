@@ -396,10 +396,12 @@ __device__ inline void gather_ys_at(const double *__restrict__ x, const int32_t 
 {
     int64_t i[GY];
     double v[GY][3];
+    // (indices past the end read the last point: no branch around a load,
+    // so that all GY loads are in flight at once)
 #pragma unroll
     for (int u = 0; u < GY; ++u) {
         const int64_t j = j0 + (int64_t)u * nt + t;
-        i[u] = j < N ? perm[j] : 0;
+        i[u] = perm[j < N ? j : N - 1];
     }
 #pragma unroll
     for (int u = 0; u < GY; ++u)
@@ -665,13 +667,32 @@ __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ tabl
         const int nb1 = nb_of(g, 1, b1, k % 3 - 1);
         ccol[k] = (nb0 < 0 || nb1 < 0) ? -1 : nb0 * g.n[1] + nb1;
     }
+    // the class offsets and this column's ranks (writing pass) are loaded
+    // first, so that their latency overlaps the staging loads
+    int tb0 = 0, tb1 = 0, tb2 = 0;
+    if (WRITE && lane < TK_CLASSES) {
+        tb0 = table[(int64_t)lane * ncol];
+        tb1 = table[(int64_t)lane * ncol + col];
+        tb2 = table[(int64_t)(lane + 1) * ncol];
+    }
+    // all ten box-start pairs of a lane are loaded before any is used (a
+    // missing neighbour column, past a free face, reads column 0 and counts
+    // nothing), so that they cost one memory round trip, not ten
+    const int32_t *pcol[10];  // uniform: each column's box starts
+#pragma unroll
+    for (int k = 0; k < 10; ++k) pcol[k] = g.bs + (int64_t)(k == 9 ? col : (ccol[k] < 0 ? 0 : ccol[k])) * n2;
     for (int z = lane; z < zst; z += WAVE) {
-        const int64_t b = (int64_t)col * n2 + z;
-        const int s0 = g.bs[b];
-        snt[z] = g.bs[b + 1] - s0;
-        sbs[z] = s0;
+        int lo[10], hi[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            lo[k] = pcol[k][z];
+            hi[k] = pcol[k][z + 1];
+        }
         int sc = 0;
-        for (int k = 0; k < 9; ++k) sc += box_count(g, ccol[k], z);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) sc += ccol[k] < 0 ? 0 : hi[k] - lo[k];
+        snt[z] = hi[9] - lo[9];
+        sbs[z] = lo[9];
         sslp[z + 1] = sc;
     }
     if (!TALL) {
@@ -686,10 +707,9 @@ __device__ void tile_walk(const TileGeom &g, int col, int32_t *__restrict__ tabl
     if (lane < TK_CLASSES) {
         run[lane] = 0;
         if (WRITE) {
-            const int64_t o = table[(int64_t)lane * ncol];
-            cbase[lane] = (int)(table[(int64_t)lane * ncol + col] - o);
-            cofs[lane] = (int)o;
-            clen[lane] = (int)(table[(int64_t)(lane + 1) * ncol] - o);
+            cbase[lane] = tb1 - tb0;
+            cofs[lane] = tb0;
+            clen[lane] = tb2 - tb0;
         }
     }
     wave_fence();
