@@ -584,19 +584,30 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD, HEAVY>::NW * WAVE)) void k_resi
     const double R2 = 2.25 * (P.h[0] * P.h[0] + P.h[1] * P.h[1]) + ext_z * ext_z * P.h[2] * P.h[2];
     const float rc2s = (float)(P.rc * P.rc * (1.0 + 4e-4) + 4.2e-5 * R2);
 
-    // ---- phase A: every independent global load of the tile set-up at once
+    // ---- phase A: every global load of the tile set-up issued before any
+    // of them is used, so that the set-up waits on memory once after the
+    // tile descriptor.  A load whose piece, box or target does not exist
+    // reads index 0 (the box starts and the sorted arrays are never empty
+    // here) and its value is dropped: a load behind a branch would be waited
+    // for inside that branch.
     //  * tid < 27: source piece (neighbour column k = tid/3, z piece tid%3)
-    //  * all threads: box counts of the slab-major table (multi-box tiles)
-    //  * tid < ntgt: target coordinates and payload
+    //  * tid < 9 * nslab: box count of the slab-major table (multi-box
+    //    tiles; the entries past the workgroup size, tall tiles only, are
+    //    loaded afterwards)
+    //  * tid < TILE_T: target coordinates, payload, box and original index
+    Seg g;
+    g.glen = 0;
+    g.gstart = 0;
+    g.k = 0;
+    g.vshift = 0;
+    g.piece = 0;
+    g.pad = 0;
+    int64_t sga = 0, sgb = 0;  // box starts of the piece (when it has boxes)
+    bool sgok = false;
     if (tid < 27) {
         const int k = tid / 3, piece = tid % 3, c0 = k / 3, c1 = k % 3;
-        Seg g;
-        g.glen = 0;
-        g.gstart = 0;
         g.k = (signed char)k;
-        g.vshift = 0;
         g.piece = (signed char)piece;
-        g.pad = 0;
         int i0, i1;
         const int nb0 = axis_nb(P, 0, b0, c0 - 1, i0), nb1 = axis_nb(P, 1, b1, c1 - 1, i1);
         if (piece == 1) S.coff[k] = make_double2(i0 * P.L[0] - crx, i1 * P.L[1] - cry);
@@ -622,54 +633,85 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD, HEAVY>::NW * WAVE)) void k_resi
                 g.vshift = n2 - lo;
             }
             if (lo >= 0 && lo <= hi) {
-                g.gstart = P.bs[cb + lo];
-                g.glen = P.bs[cb + hi + 1] - g.gstart;
+                sgok = true;
+                sga = cb + lo;
+                sgb = cb + hi + 1;
             }
             (void)zimg;
             if (piece == 1) S.ccol[k] = cc;
         } else if (piece == 1) {
             S.ccol[k] = -1;
         }
+    }
+    const int M = dense ? 0 : nslab * 9;
+    int64_t dta = 0, dtc = 0;  // box start of the entry's box, and of the first box of its piece
+    bool dtok = false, dtpre = false;
+    if (tid < M) {
+        const int sl = tid / 9, k = tid - (tid / 9) * 9;
+        int i0, i1, iz;
+        const int nb0 = axis_nb(P, 0, b0, k / 3 - 1, i0), nb1 = axis_nb(P, 1, b1, k % 3 - 1, i1);
+        const int zv = za + sl;
+        const int zp = (zv < 0) ? axis_nb(P, 2, 0, -1, iz) : (zv >= n2 ? axis_nb(P, 2, n2 - 1, 1, iz) : zv);
+        if (nb0 >= 0 && nb1 >= 0 && zp >= 0) {
+            const int64_t cb = (int64_t)(nb0 * n1 + nb1) * n2;
+            dtok = true;
+            dta = cb + zp;
+            // boxes inside the domain form one piece starting at max(za, 0)
+            dtpre = zv >= 0 && zv < n2;
+            dtc = cb + (za < 0 ? 0 : za);
+        }
+    }
+    const bool tgok = tid < TILE_T && tstart + tid < P.N;  // all 64 slots; ones past ntgt are never used
+    const int64_t j = tgok ? tstart + tid : 0;
+    // the loads
+    const int sgv0 = P.bs[sga], sgv1 = P.bs[sgb];
+    const int dtv0 = P.bs[dta], dtv1 = P.bs[dta + 1], dtv2 = P.bs[dtc];
+    const double ysx = P.ys[j], ysy = P.ys[P.N + j], ysz = P.ys[2 * P.N + j];
+    double tpl[C::NTP > 0 ? C::NTP : 1];
+    for (int c = 0; c < C::NTP; ++c) tpl[c] = payload<C::MIN>(P, c, j);
+    const int skj = P.skey[j], pmj = P.perm[j];
+    // their uses
+    if (tid < 27) {
+        if (sgok) {
+            g.gstart = sgv0;
+            g.glen = sgv1 - sgv0;
+        }
         S.seg[tid] = g;
     }
-    if (!dense) {
-        const int M = nslab * 9;
-        for (int idx = tid; idx < M; idx += C::NW * WAVE) {
-            const int sl = idx / 9, k = idx - (idx / 9) * 9;
-            int i0, i1, iz;
-            const int nb0 = axis_nb(P, 0, b0, k / 3 - 1, i0), nb1 = axis_nb(P, 1, b1, k % 3 - 1, i1);
-            const int zv = za + sl;
-            const int zp = (zv < 0) ? axis_nb(P, 2, 0, -1, iz) : (zv >= n2 ? axis_nb(P, 2, n2 - 1, 1, iz) : zv);
-            int cnt = 0, pre = 0;
-            if (nb0 >= 0 && nb1 >= 0 && zp >= 0) {
-                const int64_t cb = (int64_t)(nb0 * n1 + nb1) * n2;
-                const int gs = P.bs[cb + zp];
-                cnt = P.bs[cb + zp + 1] - gs;
-                // boxes inside the domain form one piece starting at max(za, 0)
-                if (zv >= 0 && zv < n2) pre = gs - P.bs[cb + (za < 0 ? 0 : za)];
-            }
-            S.st.dtab[idx] = cnt | (pre << 16);
+    if (tid < M) S.st.dtab[tid] = dtok ? (dtv1 - dtv0) | ((dtpre ? dtv0 - dtv2 : 0) << 16) : 0;
+    for (int idx = tid + C::NW * WAVE; idx < M; idx += C::NW * WAVE) {
+        const int sl = idx / 9, k = idx - (idx / 9) * 9;
+        int i0, i1, iz;
+        const int nb0 = axis_nb(P, 0, b0, k / 3 - 1, i0), nb1 = axis_nb(P, 1, b1, k % 3 - 1, i1);
+        const int zv = za + sl;
+        const int zp = (zv < 0) ? axis_nb(P, 2, 0, -1, iz) : (zv >= n2 ? axis_nb(P, 2, n2 - 1, 1, iz) : zv);
+        int cnt = 0, pre = 0;
+        if (nb0 >= 0 && nb1 >= 0 && zp >= 0) {
+            const int64_t cb = (int64_t)(nb0 * n1 + nb1) * n2;
+            const int gs = P.bs[cb + zp];
+            cnt = P.bs[cb + zp + 1] - gs;
+            if (zv >= 0 && zv < n2) pre = gs - P.bs[cb + (za < 0 ? 0 : za)];
         }
+        S.st.dtab[idx] = cnt | (pre << 16);
     }
     for (int idx = tid; idx < C::NC * TILE_T; idx += C::NW * WAVE) (&S.tacc[0][0])[idx] = 0.0;
     int my_zt = 0, my_orig = 0;
-    if (tid < TILE_T && tstart + tid < P.N) {  // all 64 slots; ones past ntgt are never used
-        const int64_t j = tstart + tid;
-        const double X = P.ys[j] - crx, Y = P.ys[P.N + j] - cry, Z = P.ys[2 * P.N + j] - crz;
+    if (tgok) {
+        const double X = ysx - crx, Y = ysy - cry, Z = ysz - crz;
         const float hx = (float)X, hy = (float)Y, hz = (float)Z;
         S.tc[tid] = make_float4(hx, hy, hz, 0.5f * (rc2s - (hx * hx + hy * hy + hz * hz)));
         if constexpr (C::F32) {
-            const float t0 = (C::NTP > 0) ? (float)payload<C::MIN>(P, 0, j) : 0.0f;
+            const float t0 = (C::NTP > 0) ? (float)tpl[0] : 0.0f;
             S.tl[tid] = make_float4((float)(X - (double)hx), (float)(Y - (double)hy), (float)(Z - (double)hz), t0);
-            for (int c = 1; c < C::NTP; ++c) S.tp[c - 1][tid] = (float)payload<C::MIN>(P, c, j);
+            for (int c = 1; c < C::NTP; ++c) S.tp[c - 1][tid] = (float)tpl[c];
         } else {
             S.tx[tid] = X;
             S.ty[tid] = Y;
             S.tz[tid] = Z;
-            for (int c = 0; c < C::NTP; ++c) S.tpd[c][tid] = payload<C::MIN>(P, c, j);
+            for (int c = 0; c < C::NTP; ++c) S.tpd[c][tid] = tpl[c];
         }
-        if (!dense) my_zt = P.skey[j] - (int)colb;
-        my_orig = P.perm[j];
+        if (!dense) my_zt = skj - (int)colb;
+        my_orig = pmj;
     }
     __syncthreads();
 
@@ -684,7 +726,6 @@ __global__ __launch_bounds__((Cfg<KERN, FP, BWD, HEAVY>::NW * WAVE)) void k_resi
         if (lane == 26) S.qtot = incl;
     }
     if (!dense && w == 1) {
-        const int M = nslab * 9;
         int carry = 0;
         for (int base = 0; base < M; base += WAVE) {
             const int idx = base + lane;
