@@ -99,10 +99,17 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const int32_t *__restric
     __syncthreads();
     const int tile = rs_tile((int)blockIdx.x, nblk);
     const int64_t base = (int64_t)tile * RS_TILE;
+    // all keys of the thread loaded before the first count (an index past
+    // the end reads the last key, not counted)
+    int kv[RS_ITEMS];
+#pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
-        int64_t i = base + r * RS_THREADS + tid;
-        if (i < N) atomicAdd(&h[(keys[i] >> shift) & mask], 1);
+        const int64_t i = base + r * RS_THREADS + tid;
+        kv[r] = keys[i < N ? i : N - 1];
     }
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r)
+        if (base + r * RS_THREADS + tid < N) atomicAdd(&h[(kv[r] >> shift) & mask], 1);
     __syncthreads();
     for (int q = 0; q < RS_BPT; ++q) {
         const int d = q * RS_THREADS + tid;
@@ -428,8 +435,10 @@ __global__ void k_box_start_fill(const int32_t *__restrict__ skey, int64_t N, in
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j > N) return;
-    const int64_t kp = j > 0 ? skey[j - 1] : -1;
-    const int64_t kc = j < N ? skey[j] : nbox;
+    // both keys loaded together (indices clamped into [0, N); N >= 1 here)
+    const int32_t sa = skey[j > 0 ? j - 1 : 0], sc = skey[j < N ? j : N - 1];
+    const int64_t kp = j > 0 ? sa : -1;
+    const int64_t kc = j < N ? sc : nbox;
     for (int64_t b = kp + 1; b <= kc; ++b) bs[b] = (int32_t)j;
 }
 
@@ -490,11 +499,12 @@ __global__ void k_bin_keys(const double *__restrict__ x, int64_t N, BinGeom g, i
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < 3 * (int64_t)(g.n[0] + g.n[1] + g.n[2])) axis_table_entry(g, (int)i, nbr, img);
     if (i >= N) return;
+    const double xv[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};  // loaded together
     int b[3];
     bool ok = true;
     for (int ax = 0; ax < 3; ++ax) {
         double y = 0.0;
-        ok = wrap_coord(x[3 * i + ax], ax, g, y) && ok;
+        ok = wrap_coord(xv[ax], ax, g, y) && ok;
         b[ax] = ok ? box_coord(y, ax, g) : 0;
     }
     if (!ok) atomicOr(err, 1);
