@@ -168,3 +168,36 @@ def test_binning_deterministic():
     b2 = R.tree_bin((1, 1, 1), 3, (16, 16, 16), dev(x))
     assert host(b1.perm()).tobytes() == host(b2.perm()).tobytes()
     assert host(b1.tiles()).tobytes() == host(b2.tiles()).tobytes()
+
+
+def test_binning_long_runs():
+    # boxes of 32, 33, a few hundred and 9000 points among sparse boxes, the
+    # points in random order: keys, order, box starts and sorted coordinates
+    # bit-exact, and bit-identical when binned twice
+    rng = np.random.default_rng(13)
+    n = (8, 8, 8)
+    h = 1.0 / 8
+    dense = {(1, 1, 1): 32, (2, 1, 1): 33, (3, 3, 3): 300, (5, 2, 6): 700, (6, 6, 6): 9000}
+    u = rng.random((3000, 3))
+    bu = np.floor(u / h).astype(int)
+    keep = np.ones(len(u), dtype=bool)
+    for c in dense:
+        keep &= ~(bu == np.asarray(c)).all(axis=1)
+    parts = [u[keep]]
+    for c, m in dense.items():
+        parts.append((np.asarray(c) + 0.05 + 0.9 * rng.random((m, 3))) * h)
+    x = np.concatenate(parts)
+    x = x[rng.permutation(len(x))]
+    print("binning long runs", len(x), flush=True)
+    ref = bin_spec(x, (1, 1, 1), 3, n)
+    counts = np.diff(ref["box_start"])
+    assert sorted(counts[counts >= 32].tolist()) == [32, 33, 300, 700, 9000]
+    b1 = R.tree_bin((1, 1, 1), 3, n, dev(x))
+    np.testing.assert_array_equal(host(b1.perm()), ref["perm"])
+    np.testing.assert_array_equal(host(b1.skey()), ref["skey"])
+    np.testing.assert_array_equal(host(b1.box_start()), ref["box_start"])
+    assert host(b1.ys()).tobytes() == ref["ys"].tobytes()
+    _check_tiles(b1, n, ref, 3)
+    b2 = R.tree_bin((1, 1, 1), 3, n, dev(x))
+    assert host(b2.perm()).tobytes() == host(b1.perm()).tobytes()
+    assert host(b2.ys()).tobytes() == host(b1.ys()).tobytes()
