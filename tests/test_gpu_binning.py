@@ -201,3 +201,17 @@ def test_binning_long_runs():
     b2 = R.tree_bin((1, 1, 1), 3, n, dev(x))
     assert host(b2.perm()).tobytes() == host(b1.perm()).tobytes()
     assert host(b2.ys()).tobytes() == host(b1.ys()).tobytes()
+
+
+@pytest.mark.parametrize("m", list(range(1, 13)))
+def test_gather_sorted_every_width(m):
+    # dst[c][j] = src[perm[j]][c] for every record width the ABI takes, on a
+    # point count that leaves the last 256-point workgroup partly filled
+    N = 3 * 256 + 77
+    x = _points(400 + m, N, (1.0, 1.0, 1.0), 3, "uniform")
+    b = R.tree_bin((1.0, 1.0, 1.0), 3, (4, 4, 4), dev(x))
+    src = np.random.default_rng(500 + m).standard_normal((N, m))
+    print("gather_sorted m", m, flush=True)
+    got = host(R.gather_sorted(b, dev(src)))
+    perm = host(b.perm())
+    assert got.tobytes() == np.ascontiguousarray(src[perm].T).tobytes()
