@@ -263,3 +263,39 @@ def test_random_small_cases(i):
         gr, gx = run_bwd(w, prec, G)
         assert_parity(gr, rr, TOL[prec], "random %d grad_rho %s" % (i, prec))
         assert_parity(gx, rx, TOL[prec], "random %d grad_x %s" % (i, prec))
+
+
+def test_two_streams_independent():
+    """The library keeps no state between calls: binnings and evaluations
+    issued on two streams (default priority), interleaved, give results
+    bit-identical to the same calls made one after the other on the default
+    stream, and events recorded on each stream bracket that stream's work."""
+    cases = [(W.make("laplace_n2k"), "fp32c"), (W.make("laplace_n2k", kernel="stokeslet"), "fp64")]
+    ref = []
+    for w, prec in cases:
+        b = R.tree_bin(w.L, w.D, w.n, dev(w.x))
+        ref.append(host(R.residual_eval(b, w.kernel, prec, w.sigma, w.rc, dev(w.rho))))
+    inputs = [(dev(w.x), dev(w.rho)) for w, _ in cases]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    bins = []
+    for (w, _), (x, _), s in zip(cases, inputs, streams):
+        with torch.cuda.stream(s):
+            bins.append(R.tree_bin(w.L, w.D, w.n, x))
+    outs = [None, None]
+    events = [None, None]
+    print("two streams", flush=True)
+    for rep in range(3):
+        for k, ((w, prec), (_, rho), s) in enumerate(zip(cases, inputs, streams)):
+            with torch.cuda.stream(s):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                outs[k] = R.residual_eval(bins[k], w.kernel, prec, w.sigma, w.rc, rho)
+                e1.record(s)
+                events[k] = (e0, e1)
+    torch.cuda.synchronize()
+    for k in range(2):
+        assert host(outs[k]).tobytes() == ref[k].tobytes()
+        e0, e1 = events[k]
+        assert e0.elapsed_time(e1) > 0.0
